@@ -1,0 +1,319 @@
+"""FP64 CPU oracle for the SFFT image-differencing hot path.
+
+TEST INFRASTRUCTURE ONLY. Only tests/, the smoke check in __graft_entry__.py
+and the CPU-baseline leg of bench.py may import or run anything in oracle/.
+The GPU library never calls it, shares no code with it, and no stored
+expected value comes from the GPU path.
+
+What the method computes (paper Sec. 1 and Sec. 2.3.2): SFFT fits, between an
+aligned reference R and science image S, a matching kernel in a delta-function
+basis (free pixel values on an L x L grid) whose values vary over the image as
+a polynomial of degree DK, plus a differential background polynomial of degree
+DB, by least squares formulated in the Fourier domain; then it convolves the
+reference with the fitted kernel and subtracts. The paper prints none of the
+equations, so the plain definition below is written out from linear least
+squares and the convolution theorem:
+
+    theta* = argmin sum_x ( S'(x) - M_theta(x) )^2,
+    M_theta(x) = sum_i sum_delta a_(i,delta) p_i(x - delta) R'(x - delta)
+                 + sum_c b_c q_c(x),
+    D = S' - M_theta*,
+
+with R' = R - c_R, S' = S - c_S (scalar pedestals), every index taken modulo
+the image size (periodic boundary), p_i and q_c the monomials of total degree
+<= DK resp. <= DB in xt = 2x/(W-1) - 1, yt = 2y/(H-1) - 1, ordered
+for d = 0..D, for b = 0..d: (xt^(d-b) yt^b). The polynomial weight of the
+kernel is evaluated at the input (reference) pixel. Unknown (i, dy, dx) is at
+i*L*L + (dy+r)*L + (dx+r), r = (L-1)/2; background c follows all kernel terms.
+
+Two independent routes to theta*:
+  O1 (solve_bruteforce): explicit design matrix built with np.roll, lstsq.
+  O2 (build_fft64 + solve_cholesky64): the normal equations G theta = h with
+     every block filled by an FFT cross-correlation, then an equilibrated
+     Cholesky solve with iterative refinement.
+Subtraction (subtract64) is the direct tap-by-tap sum; chi2_nu is the
+residual judge used to accept a difference image.
+
+Every function is pinned by tests marked "not gpu" (brute force on tiny
+inputs, exact recovery of a planted kernel, kernel-sum invariant, textbook
+special cases, orthogonality of the residual, chi2 ~ 1 on in-model noise).
+"""
+from __future__ import annotations
+
+import re
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.fft
+import scipy.linalg
+
+# ---------------------------------------------------------------------------
+# conventions
+# ---------------------------------------------------------------------------
+
+
+def n_mono(D: int) -> int:
+    """Number of monomials of total degree <= D in two variables."""
+    return (D + 1) * (D + 2) // 2
+
+
+def monomials(D: int):
+    """Exponent pairs (a, b) of xt^a yt^b in the unknown layout's order."""
+    return [(d - b, b) for d in range(D + 1) for b in range(d + 1)]
+
+
+def n_unknowns(L: int, DK: int, DB: int) -> int:
+    return L * L * n_mono(DK) + n_mono(DB)
+
+
+def norm_coord(n: int) -> np.ndarray:
+    """2 k / (n - 1) - 1 for k = 0..n-1 (0 for n == 1)."""
+    if n == 1:
+        return np.zeros(1)
+    return 2.0 * np.arange(n, dtype=np.float64) / (n - 1) - 1.0
+
+
+def poly_images(W: int, H: int, D: int) -> np.ndarray:
+    """(n_mono(D), H, W) stack of monomial images."""
+    xt = norm_coord(W)[None, :]
+    yt = norm_coord(H)[:, None]
+    return np.stack([np.broadcast_to(xt ** a * yt ** b, (H, W)) for a, b in monomials(D)])
+
+
+def kernel_offsets(L: int):
+    """(dy, dx) of the L*L kernel taps in layout order (dy major)."""
+    r = (L - 1) // 2
+    dy, dx = np.meshgrid(np.arange(-r, r + 1), np.arange(-r, r + 1), indexing="ij")
+    return dy.ravel(), dx.ravel()
+
+
+def split_theta(theta: np.ndarray, L: int, DK: int, DB: int):
+    nK = n_mono(DK)
+    a = np.asarray(theta[: nK * L * L], dtype=np.float64).reshape(nK, L, L)
+    b = np.asarray(theta[nK * L * L:], dtype=np.float64)
+    return a, b
+
+
+def _prep(R, S, ref_pedestal, sci_pedestal):
+    Rp = np.asarray(R, dtype=np.float64) - float(ref_pedestal)
+    Sp = None if S is None else np.asarray(S, dtype=np.float64) - float(sci_pedestal)
+    return Rp, Sp
+
+
+# ---------------------------------------------------------------------------
+# O1: brute-force least squares on the explicit design matrix
+# ---------------------------------------------------------------------------
+
+
+def design_matrix(R, L, DK, DB, ref_pedestal=0.0) -> np.ndarray:
+    """A (H*W x N): column (i, delta) is the image p_i R' shifted by +delta
+    (value at x is (p_i R')(x - delta), periodic); column c is q_c."""
+    Rp, _ = _prep(R, None, ref_pedestal, 0.0)
+    H, W = Rp.shape
+    P = poly_images(W, H, DK) * Rp
+    Q = poly_images(W, H, DB)
+    cols = []
+    for i in range(P.shape[0]):
+        for dy, dx in zip(*kernel_offsets(L)):
+            cols.append(np.roll(P[i], shift=(int(dy), int(dx)), axis=(0, 1)).ravel())
+    for c in range(Q.shape[0]):
+        cols.append(Q[c].ravel())
+    return np.stack(cols, axis=1)
+
+
+def normal_bruteforce(R, S, L, DK, DB, ref_pedestal=0.0, sci_pedestal=0.0):
+    """G = A^T A, h = A^T S' from the explicit design matrix."""
+    A = design_matrix(R, L, DK, DB, ref_pedestal)
+    y = (np.asarray(S, dtype=np.float64) - sci_pedestal).ravel()
+    return A.T @ A, A.T @ y
+
+
+def solve_bruteforce(R, S, L, DK, DB, ref_pedestal=0.0, sci_pedestal=0.0) -> np.ndarray:
+    """theta* by SVD-based lstsq on the explicit design matrix."""
+    A = design_matrix(R, L, DK, DB, ref_pedestal)
+    y = (np.asarray(S, dtype=np.float64) - sci_pedestal).ravel()
+    theta, *_ = np.linalg.lstsq(A, y, rcond=None)
+    return theta
+
+
+# ---------------------------------------------------------------------------
+# O2: FP64 FFT normal equations
+# ---------------------------------------------------------------------------
+
+
+def fft_correlation(f: np.ndarray, g: np.ndarray) -> np.ndarray:
+    """C[dy, dx] = sum_u f(u) g(u + (dy, dx)), periodic, via the convolution
+    theorem: C = IDFT( conj(DFT f) * DFT g )."""
+    H, W = f.shape
+    Ff = scipy.fft.rfft2(f, workers=-1)
+    Fg = scipy.fft.rfft2(g, workers=-1)
+    return scipy.fft.irfft2(np.conj(Ff) * Fg, s=(H, W), workers=-1)
+
+
+def build_fft64(R, S, L, DK, DB, ref_pedestal=0.0, sci_pedestal=0.0):
+    """Normal equations of the periodic least-squares problem, every block
+    from a full (unpruned) FFT cross-correlation:
+      G[(i,d),(j,d')] = C_{P_i,P_j}(d - d'),  G[(i,d),c] = C_{P_i,q_c}(d),
+      G[c,c'] = sum q_c q_c',  h[(i,d)] = C_{P_i,S'}(d),  h[c] = sum q_c S',
+    with P_i = p_i R' and C_{f,g}(D) = sum_u f(u) g(u + D)."""
+    Rp, Sp = _prep(R, S, ref_pedestal, sci_pedestal)
+    H, W = Rp.shape
+    nK, nB = n_mono(DK), n_mono(DB)
+    L2 = L * L
+    N = nK * L2 + nB
+    P = poly_images(W, H, DK) * Rp
+    Q = poly_images(W, H, DB)
+    FP = [scipy.fft.rfft2(P[i], workers=-1) for i in range(nK)]
+    FQ = [scipy.fft.rfft2(Q[c], workers=-1) for c in range(nB)]
+    FS = scipy.fft.rfft2(Sp, workers=-1)
+
+    def corr(Fa, Fb):
+        return scipy.fft.irfft2(np.conj(Fa) * Fb, s=(H, W), workers=-1)
+
+    dy, dx = kernel_offsets(L)
+    ddy = (dy[:, None] - dy[None, :]) % H
+    ddx = (dx[:, None] - dx[None, :]) % W
+    G = np.zeros((N, N))
+    h = np.zeros(N)
+    kb = nK * L2
+    for i in range(nK):
+        si = slice(i * L2, (i + 1) * L2)
+        for j in range(i, nK):
+            sj = slice(j * L2, (j + 1) * L2)
+            C = corr(FP[i], FP[j])
+            blk = C[ddy, ddx]
+            G[si, sj] = blk
+            G[sj, si] = blk.T
+        for c in range(nB):
+            C = corr(FP[i], FQ[c])
+            col = C[dy % H, dx % W]
+            G[si, kb + c] = col
+            G[kb + c, si] = col
+        C = corr(FP[i], FS)
+        h[si] = C[dy % H, dx % W]
+    for c in range(nB):
+        for c2 in range(nB):
+            G[kb + c, kb + c2] = float(np.sum(Q[c] * Q[c2]))
+        h[kb + c] = float(np.sum(Q[c] * Sp))
+    return G, h
+
+
+@dataclass
+class SolveInfo:
+    status: str            # "ok" or "not_spd"
+    failed_pivot: int      # 0-based failing pivot (-1 when ok)
+    refine_iters: int
+    backward_err: float    # ||h - G theta||_inf / (||G||_inf ||theta||_inf + ||h||_inf)
+    cond_est: float        # 2-norm condition number of the equilibrated G
+
+
+def solve_cholesky64(G, h, refine: int = 2, cond: bool = False):
+    """theta = G^-1 h: equilibrate (D = diag(G)^-1/2), Cholesky factor the
+    equilibrated matrix, two triangular solves, then `refine` steps of
+    iterative refinement with the residual h - G theta in FP64.
+    Returns (theta, SolveInfo); theta is None when G is not positive definite."""
+    G = np.asarray(G, dtype=np.float64)
+    h = np.asarray(h, dtype=np.float64)
+    dg = np.diag(G).copy()
+    bad = np.where(~(dg > 0) | ~np.isfinite(dg))[0]
+    if bad.size:
+        return None, SolveInfo("not_spd", int(bad[0]), 0, np.inf, np.inf)
+    s = 1.0 / np.sqrt(dg)
+    Gt = G * s[:, None] * s[None, :]
+    try:
+        cf = scipy.linalg.cho_factor(Gt, lower=True, check_finite=True)
+    except np.linalg.LinAlgError as e:
+        m = re.search(r"(\d+)", str(e))
+        piv = int(m.group(1)) - 1 if m else -1
+        return None, SolveInfo("not_spd", piv, 0, np.inf, np.inf)
+    x = scipy.linalg.cho_solve(cf, h * s)
+    for _ in range(refine):
+        rres = h * s - Gt @ x
+        x = x + scipy.linalg.cho_solve(cf, rres)
+    theta = x * s
+    res = h - G @ theta
+    berr = float(np.max(np.abs(res)) /
+                 (np.max(np.sum(np.abs(G), axis=1)) * np.max(np.abs(theta)) + np.max(np.abs(h))))
+    kappa = float(np.linalg.cond(Gt)) if cond else float("nan")
+    return theta, SolveInfo("ok", -1, refine, berr, kappa)
+
+
+# ---------------------------------------------------------------------------
+# convolve-and-subtract, chi2 judge
+# ---------------------------------------------------------------------------
+
+
+def model_image(R, theta, L, DK, DB, ref_pedestal=0.0) -> np.ndarray:
+    """M_theta(x) by direct summation over the L*L taps and the monomials."""
+    Rp, _ = _prep(R, None, ref_pedestal, 0.0)
+    H, W = Rp.shape
+    a, b = split_theta(theta, L, DK, DB)
+    P = poly_images(W, H, DK) * Rp
+    M = np.zeros((H, W))
+    r = (L - 1) // 2
+    for i in range(P.shape[0]):
+        for dy in range(-r, r + 1):
+            for dx in range(-r, r + 1):
+                c = a[i, dy + r, dx + r]
+                if c != 0.0:
+                    M += c * np.roll(P[i], shift=(dy, dx), axis=(0, 1))
+    Q = poly_images(W, H, DB)
+    for c in range(Q.shape[0]):
+        M += b[c] * Q[c]
+    return M
+
+
+def subtract64(R, S, theta, L, DK, DB, ref_pedestal=0.0, sci_pedestal=0.0) -> np.ndarray:
+    """Difference image D = S' - M_theta."""
+    Sp = np.asarray(S, dtype=np.float64) - sci_pedestal
+    return Sp - model_image(R, theta, L, DK, DB, ref_pedestal)
+
+
+def kernel_sums(theta, L, DK, DB=0) -> np.ndarray:
+    """kappa_i = sum_delta a_(i,delta): the flux-ratio polynomial."""
+    a, _ = split_theta(theta, L, DK, DB)
+    return a.reshape(a.shape[0], -1).sum(axis=1)
+
+
+def variance_image(R, S, theta, L, DK, DB) -> np.ndarray:
+    """V(x) = max(S(x), 1) + kappa2(x) max(R(x), 1) with kappa2(x) =
+    sum_delta (sum_i a_(i,delta) p_i(x))^2: Poisson variance (gain 1) of S
+    plus that of the convolved reference, on raw (pedestal-free) images."""
+    R = np.asarray(R, dtype=np.float64)
+    S = np.asarray(S, dtype=np.float64)
+    H, W = R.shape
+    a, _ = split_theta(theta, L, DK, DB)
+    A = a.reshape(a.shape[0], -1)
+    Qm = A @ A.T
+    mono = poly_images(W, H, DK)
+    k2 = np.einsum("ij,ihw,jhw->hw", Qm, mono, mono)
+    return np.maximum(S, 1.0) + k2 * np.maximum(R, 1.0)
+
+
+def chi2_nu(R, S, D, theta, L, DK, DB) -> float:
+    """Reduced chi^2 of D over the image minus an r-pixel frame,
+    dof = |Omega| - N."""
+    H, W = np.asarray(R).shape
+    r = (L - 1) // 2
+    V = variance_image(R, S, theta, L, DK, DB)
+    Dm = np.asarray(D, dtype=np.float64)[r:H - r, r:W - r]
+    Vm = V[r:H - r, r:W - r]
+    dof = Dm.size - n_unknowns(L, DK, DB)
+    return float(np.sum(Dm * Dm / Vm) / dof)
+
+
+# ---------------------------------------------------------------------------
+# one-call path
+# ---------------------------------------------------------------------------
+
+
+def difference(R, S, L, DK, DB, ref_pedestal=0.0, sci_pedestal=0.0, refine=2):
+    """Build (O2) + solve + subtract + chi2. Returns dict."""
+    G, h = build_fft64(R, S, L, DK, DB, ref_pedestal, sci_pedestal)
+    theta, info = solve_cholesky64(G, h, refine)
+    out = dict(G=G, h=h, theta=theta, info=info)
+    if theta is not None:
+        D = subtract64(R, S, theta, L, DK, DB, ref_pedestal, sci_pedestal)
+        out["D"] = D
+        out["chi2"] = chi2_nu(R, S, D, theta, L, DK, DB)
+    return out
