@@ -1,0 +1,180 @@
+/*
+ * sfft.h -- C ABI of the MI355X (gfx950) SFFT image-differencing library.
+ *
+ * The method (paper Sec. 1 and Sec. 2.3.2, image differencing): between an
+ * aligned reference image R and science image S, fit by least squares a
+ * matching kernel in a delta-function basis (free pixel values on an L x L
+ * grid) whose values vary over the image as a polynomial of total degree DK,
+ * plus a differential-background polynomial of degree DB; the fit is
+ * assembled in the Fourier domain; then convolve R with the fitted kernel and
+ * subtract it from S. The paper gives no equations; the operation computed
+ * here is the periodic least-squares problem
+ *
+ *   theta* = argmin sum_x ( S'(x) - M(x) )^2,
+ *   M(x)   = sum_i sum_d a_(i,d) p_i(x-d) R'(x-d) + sum_c b_c q_c(x),
+ *   D(x)   = S'(x) - M(x),
+ *
+ * with R' = R - ref_pedestal, S' = S - sci_pedestal, indices modulo (W, H),
+ * p_i / q_c the monomials xt^a yt^b of total degree <= DK / <= DB in
+ * xt = 2x/(W-1) - 1, yt = 2y/(H-1) - 1, ordered for d = 0..D, for b = 0..d:
+ * (a = d - b, b). Unknowns: kernel coefficient (i, dy, dx), dy, dx in
+ * [-r, r], r = (L-1)/2, at index i*L*L + (dy+r)*L + (dx+r); background
+ * coefficient c at n(DK)*L*L + c; n(D) = (D+1)(D+2)/2.
+ *
+ * Memory: every image, matrix and vector pointer is a HIP device pointer
+ * owned by the caller; the library never frees caller memory. Workspaces are
+ * caller-provided device buffers of at least the queried size. Images are
+ * row-major, W columns by H rows, with a row pitch of `ld` elements.
+ *
+ * Execution: every compute call is asynchronous and ordered on `stream`
+ * (a hipStream_t; NULL means the null stream). The returned status covers
+ * argument validation, plan set-up and launch errors only; conditions found
+ * on the device (non-finite pixels, a matrix that is not positive definite)
+ * are written to device memory (sfft_solve_info) and must be read after the
+ * stream is synchronised. No call aborts or throws.
+ *
+ * Threading: a handle is not thread-safe; use one handle per host thread.
+ * The first call for a new image shape builds device-side plan tables with
+ * blocking copies (do it before any stream capture).
+ */
+#ifndef SFFT_MI355X_SFFT_H
+#define SFFT_MI355X_SFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SFFT_OK = 0,
+  SFFT_ERR_INVALID_ARG = 1,   /* null pointer, even or non-positive L, degree out of range, ld < W */
+  SFFT_ERR_UNSUPPORTED = 2,   /* valid problem this build does not run (see sfft_validate) */
+  SFFT_ERR_WORKSPACE = 3,     /* workspace pointer null or smaller than required */
+  SFFT_ERR_NONFINITE = 4,     /* a NaN/Inf input pixel was seen (device-side, via info) */
+  SFFT_ERR_NOT_SPD = 5,       /* normal matrix not positive definite (device-side, via info) */
+  SFFT_ERR_HIP = 6,           /* a HIP runtime call failed (no device, launch failure, ...) */
+  SFFT_ERR_INTERNAL = 7
+} sfft_status;
+
+typedef enum { SFFT_F32 = 0, SFFT_F64 = 1 } sfft_dtype;   /* element type of R, S, D */
+
+typedef enum {
+  SFFT_COMPUTE_FP64 = 0,      /* FP64 spectra, correlations and normal matrix (plain form) */
+  SFFT_COMPUTE_FP32 = 1       /* FP32 spectra and products, FP32 accumulation; FP64 solve */
+} sfft_compute;
+
+typedef struct {
+  int32_t width;              /* W: columns (x) */
+  int32_t height;             /* H: rows (y) */
+  int64_t ld;                 /* row pitch of R, S and D in elements, >= width */
+  int32_t L;                  /* kernel size, odd, 1 <= L <= min(W, H) */
+  int32_t dk;                 /* kernel polynomial degree, 0..4 */
+  int32_t db;                 /* background polynomial degree, 0..4 */
+  int32_t image_dtype;        /* sfft_dtype of R, S, D */
+  int32_t compute;            /* sfft_compute of the build */
+  int32_t reserved;           /* must be 0 */
+  double ref_pedestal;        /* c_R, subtracted from R before fitting */
+  double sci_pedestal;        /* c_S, subtracted from S before fitting */
+} sfft_desc;
+
+/* Written by sfft_solve into device memory. */
+typedef struct {
+  int32_t status;             /* SFFT_OK, SFFT_ERR_NOT_SPD or SFFT_ERR_NONFINITE */
+  int32_t failed_pivot;       /* 0-based first non-positive pivot (LAPACK potrf style), -1 if none */
+  int32_t refine_iters;       /* iterative-refinement steps applied */
+  int32_t nonfinite;          /* nonzero when the build saw a NaN/Inf pixel */
+  double backward_err;        /* ||h - G theta||_inf / (||G||_inf ||theta||_inf + ||h||_inf) */
+  double min_pivot;           /* smallest / largest diagonal of the Cholesky factor of the */
+  double max_pivot;           /* equilibrated matrix (their squared ratio bounds cond below) */
+} sfft_solve_info;
+
+typedef struct sfft_handle_s* sfft_handle;
+
+/* Handle lifetime. sfft_create binds the handle to the current HIP device;
+ * it owns only plan tables (FFT twiddles). Errors: SFFT_ERR_INVALID_ARG for
+ * a null out pointer, SFFT_ERR_HIP when no device is usable. */
+sfft_status sfft_create(sfft_handle* out);
+sfft_status sfft_destroy(sfft_handle handle);
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char* sfft_status_string(sfft_status status);
+
+/* Number of unknowns N = L*L*n(DK) + n(DB), or -1 for an invalid descriptor.
+ * Host-only; needs no device. */
+int64_t sfft_num_unknowns(const sfft_desc* desc);
+
+/* Host-only validation. SFFT_ERR_INVALID_ARG: see sfft_status.
+ * SFFT_ERR_UNSUPPORTED: W not a power of two in [16, 4096]; H < 2L or
+ * W < 2L; L > 31; DK > 2; reserved != 0. */
+sfft_status sfft_validate(const sfft_desc* desc);
+
+/* Bytes of device workspace needed by sfft_build_system, sfft_solve and
+ * sfft_subtract for this descriptor (one buffer of this size serves all
+ * three; the build leaves a non-finite flag in it that sfft_solve reports).
+ * Host-only. */
+sfft_status sfft_workspace_size(sfft_handle handle, const sfft_desc* desc, size_t* bytes);
+
+/* Normal equations G theta = h of the least-squares problem above.
+ * Kernel-kernel and kernel-science blocks come from cross-correlations
+ * computed in the Fourier domain (row FFTs along x, blocked FFT correlation
+ * along y, pruned inverse along x); kernel-background and background blocks
+ * from exact polynomial moments with periodic seam corrections.
+ *   ref, sci : device images (image_dtype, pitch ld)
+ *   G        : device, N*N doubles, row-major, both triangles written
+ *   h        : device, N doubles
+ *   ws       : device workspace of ws_bytes >= sfft_workspace_size
+ * Non-finite pixels are flagged in ws (reported by sfft_solve). */
+sfft_status sfft_build_system(sfft_handle handle, const sfft_desc* desc,
+                              const void* ref, const void* sci,
+                              double* G, double* h,
+                              void* ws, size_t ws_bytes, void* stream);
+
+/* theta = G^-1 h in FP64: equilibrate with D = diag(G)^-1/2, Cholesky-factor
+ * the equilibrated matrix, forward/back substitution, then up to max_refine
+ * (0..8) steps of iterative refinement on the residual h - G theta.
+ *   G, h : device (from sfft_build_system or any SPD system of size N)
+ *   coef : device, N doubles (written; NaN when the solve fails)
+ *   info : device sfft_solve_info (written)
+ *   ws   : the same workspace the build used (reads its non-finite flag) */
+sfft_status sfft_solve(sfft_handle handle, const sfft_desc* desc,
+                       const double* G, const double* h, double* coef,
+                       int32_t max_refine, sfft_solve_info* info,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* D = S' - M_coef(R') with periodic boundaries, accumulated in FP64.
+ * chi2 (nullable, device double): reduced chi^2 of D over the image minus an
+ * r-pixel frame, dof = |frame interior| - N, variance per pixel
+ * max(S,1) + kappa2(x) max(R,1), kappa2(x) = sum_d (sum_i a_(i,d) p_i(x))^2
+ * (Poisson noise, gain 1, on the raw images).
+ *   diff : device, image_dtype, pitch ld (may not alias ref or sci) */
+sfft_status sfft_subtract(sfft_handle handle, const sfft_desc* desc,
+                          const void* ref, const void* sci, const double* coef,
+                          void* diff, double* chi2,
+                          void* ws, size_t ws_bytes, void* stream);
+
+/* Kernel timing hook (measurement support, not part of the method).
+ * Kernels / launch groups that can be bracketed by events: */
+typedef enum {
+  SFFT_PROF_ROW_PASS = 1,     /* row DFTs + row moments (one kernel) */
+  SFFT_PROF_COL_PASS = 2,     /* blocked y-correlation (one kernel) */
+  SFFT_PROF_XINV = 3,         /* pruned x-inverse of the correlation strips (one kernel) */
+  SFFT_PROF_SUBTRACT = 4,     /* convolve-and-subtract + chi2 partials (one kernel) */
+  SFFT_PROF_SOLVE = 5,        /* every launch of sfft_solve */
+  SFFT_PROF_BUILD = 6,        /* every launch of sfft_build_system */
+  SFFT_PROF_MAX = 8
+} sfft_prof_slot;
+
+/* From now on, every call that launches `slot` records start_event
+ * (a hipEvent_t created by the caller) on the call's stream immediately
+ * before it and stop_event immediately after it. NULL events clear the slot.
+ * Events must stay valid while set. SFFT_ERR_INVALID_ARG for a bad slot. */
+sfft_status sfft_profile_events(sfft_handle handle, int32_t slot, void* start_event,
+                                void* stop_event);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFFT_MI355X_SFFT_H */

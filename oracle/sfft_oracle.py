@@ -317,3 +317,45 @@ def difference(R, S, L, DK, DB, ref_pedestal=0.0, sci_pedestal=0.0, refine=2):
         out["D"] = D
         out["chi2"] = chi2_nu(R, S, D, theta, L, DK, DB)
     return out
+
+
+def model_at(R, theta, L, DK, DB, ys, xs, ref_pedestal=0.0) -> np.ndarray:
+    """M_theta at the listed pixels only, by direct summation (for sampled
+    checks of full-size images)."""
+    R = np.asarray(R)
+    H, W = R.shape
+    a, b = split_theta(theta, L, DK, DB)
+    r = (L - 1) // 2
+    xt, yt = norm_coord(W), norm_coord(H)
+    out = np.zeros(len(ys))
+    for n, (y, x) in enumerate(zip(ys, xs)):
+        m = 0.0
+        for dy in range(-r, r + 1):
+            uy = (y - dy) % H
+            for dx in range(-r, r + 1):
+                ux = (x - dx) % W
+                rv = float(R[uy, ux]) - ref_pedestal
+                for i, (ea, eb) in enumerate(monomials(DK)):
+                    m += a[i, dy + r, dx + r] * xt[ux] ** ea * yt[uy] ** eb * rv
+        for c, (ea, eb) in enumerate(monomials(DB)):
+            m += b[c] * xt[x] ** ea * yt[y] ** eb
+        out[n] = m
+    return out
+
+
+def normal_entry(R, L, DK, row, col, ref_pedestal=0.0) -> float:
+    """One kernel-kernel normal-matrix entry by a direct periodic sum:
+    G[(i,d),(j,d')] = sum_x P_i(x - d) P_j(x - d')."""
+    Rp = np.asarray(R, dtype=np.float64) - ref_pedestal
+    H, W = Rp.shape
+    L2 = L * L
+    r = (L - 1) // 2
+    mons = monomials(DK)
+    xt, yt = norm_coord(W)[None, :], norm_coord(H)[:, None]
+    i, d = divmod(row, L2)
+    j, d2 = divmod(col, L2)
+    Pi = xt ** mons[i][0] * yt ** mons[i][1] * Rp
+    Pj = xt ** mons[j][0] * yt ** mons[j][1] * Rp
+    a = np.roll(Pi, shift=(d // L - r, d % L - r), axis=(0, 1))
+    b = np.roll(Pj, shift=(d2 // L - r, d2 % L - r), axis=(0, 1))
+    return float(np.sum(a * b))

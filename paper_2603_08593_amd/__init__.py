@@ -1,0 +1,256 @@
+"""Python binding of the MI355X SFFT image-differencing library.
+
+Thin ctypes marshalling over the C ABI in include/sfft.h: the same entry
+points (sfft_build_system, sfft_solve, sfft_subtract, ...) taking torch
+device tensors for memory and the current HIP stream. Every step of the path
+runs in the library's HIP kernels; there is no CPU fallback, and importing
+the compute entry points fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsfft_mi355x.so")
+
+SFFT_OK = 0
+SFFT_ERR_INVALID_ARG = 1
+SFFT_ERR_UNSUPPORTED = 2
+SFFT_ERR_WORKSPACE = 3
+SFFT_ERR_NONFINITE = 4
+SFFT_ERR_NOT_SPD = 5
+SFFT_ERR_HIP = 6
+SFFT_ERR_INTERNAL = 7
+
+SFFT_F32, SFFT_F64 = 0, 1
+SFFT_COMPUTE_FP64, SFFT_COMPUTE_FP32 = 0, 1
+
+
+class SfftError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("width", ctypes.c_int32),
+        ("height", ctypes.c_int32),
+        ("ld", ctypes.c_int64),
+        ("L", ctypes.c_int32),
+        ("dk", ctypes.c_int32),
+        ("db", ctypes.c_int32),
+        ("image_dtype", ctypes.c_int32),
+        ("compute", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("ref_pedestal", ctypes.c_double),
+        ("sci_pedestal", ctypes.c_double),
+    ]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("failed_pivot", ctypes.c_int32),
+        ("refine_iters", ctypes.c_int32),
+        ("nonfinite", ctypes.c_int32),
+        ("backward_err", ctypes.c_double),
+        ("min_pivot", ctypes.c_double),
+        ("max_pivot", ctypes.c_double),
+    ]
+
+
+SOLVE_INFO_BYTES = ctypes.sizeof(SolveInfo)
+
+# name -> (restype, argtypes)
+_P = ctypes.c_void_p
+_SIGS = {
+    "sfft_create": (ctypes.c_int, [ctypes.POINTER(_P)]),
+    "sfft_destroy": (ctypes.c_int, [_P]),
+    "sfft_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "sfft_num_unknowns": (ctypes.c_int64, [ctypes.POINTER(Desc)]),
+    "sfft_validate": (ctypes.c_int, [ctypes.POINTER(Desc)]),
+    "sfft_workspace_size": (ctypes.c_int, [_P, ctypes.POINTER(Desc), ctypes.POINTER(ctypes.c_size_t)]),
+    "sfft_build_system": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "sfft_solve": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, ctypes.c_int32, _P, _P,
+                                  ctypes.c_size_t, _P]),
+    "sfft_subtract": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded C library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"SFFT HIP library not built ({LIB_PATH}); run __graft_entry__.build()")
+        l = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(l, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = l
+    return _lib
+
+
+def status_string(status: int) -> str:
+    try:
+        return lib().sfft_status_string(int(status)).decode()
+    except RuntimeError:
+        return f"status {status}"
+
+
+def _check(status: int, where: str):
+    if status != SFFT_OK:
+        raise SfftError(status, where)
+
+
+def make_desc(width, height, L, dk, db, *, ld=None, image_dtype=SFFT_F32, compute=SFFT_COMPUTE_FP64,
+              ref_pedestal=0.0, sci_pedestal=0.0) -> Desc:
+    return Desc(int(width), int(height), int(width if ld is None else ld), int(L), int(dk), int(db),
+                int(image_dtype), int(compute), 0, float(ref_pedestal), float(sci_pedestal))
+
+
+def sfft_num_unknowns(desc: Desc) -> int:
+    return int(lib().sfft_num_unknowns(ctypes.byref(desc)))
+
+
+def sfft_validate(desc: Desc) -> int:
+    return int(lib().sfft_validate(ctypes.byref(desc)))
+
+
+class Handle:
+    """Owns an sfft_handle (plan tables) bound to the current device."""
+
+    def __init__(self):
+        h = _P()
+        _check(lib().sfft_create(ctypes.byref(h)), "sfft_create")
+        self._h = h
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().sfft_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _stream_ptr(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return _P(s.cuda_stream)
+
+
+def _dp(t):
+    return None if t is None else _P(t.data_ptr())
+
+
+def sfft_workspace_size(handle: Handle, desc: Desc) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().sfft_workspace_size(handle.ptr, ctypes.byref(desc), ctypes.byref(n)), "sfft_workspace_size")
+    return int(n.value)
+
+
+def sfft_build_system(handle: Handle, desc: Desc, ref, sci, G, h, ws, stream=None):
+    _check(lib().sfft_build_system(handle.ptr, ctypes.byref(desc), _dp(ref), _dp(sci), _dp(G), _dp(h),
+                                   _dp(ws), ws.numel() * ws.element_size(), _stream_ptr(stream)),
+           "sfft_build_system")
+
+
+def sfft_solve(handle: Handle, desc: Desc, G, h, coef, info, ws, max_refine=2, stream=None):
+    _check(lib().sfft_solve(handle.ptr, ctypes.byref(desc), _dp(G), _dp(h), _dp(coef), int(max_refine),
+                            _dp(info), _dp(ws), ws.numel() * ws.element_size(), _stream_ptr(stream)),
+           "sfft_solve")
+
+
+def sfft_subtract(handle: Handle, desc: Desc, ref, sci, coef, diff, chi2, ws, stream=None):
+    _check(lib().sfft_subtract(handle.ptr, ctypes.byref(desc), _dp(ref), _dp(sci), _dp(coef), _dp(diff),
+                               _dp(chi2), _dp(ws), ws.numel() * ws.element_size(), _stream_ptr(stream)),
+           "sfft_subtract")
+
+
+def read_info(info_tensor) -> SolveInfo:
+    """Copy a device sfft_solve_info (uint8 tensor) to the host."""
+    raw = bytes(info_tensor.cpu().numpy().tobytes())
+    return SolveInfo.from_buffer_copy(raw[:SOLVE_INFO_BYTES])
+
+
+@dataclass
+class Buffers:
+    G: object
+    h: object
+    coef: object
+    info: object
+    diff: object
+    chi2: object
+    ws: object
+
+
+class Differencer:
+    """Reusable device buffers + handle for one image shape and fit."""
+
+    def __init__(self, width, height, L, dk, db, *, image_dtype="float32", compute="fp64",
+                 ref_pedestal=0.0, sci_pedestal=0.0, device="cuda"):
+        import torch
+        self.torch = torch
+        self.dtype = torch.float32 if image_dtype in ("float32", torch.float32) else torch.float64
+        self.desc = make_desc(width, height, L, dk, db,
+                              image_dtype=SFFT_F32 if self.dtype == torch.float32 else SFFT_F64,
+                              compute=SFFT_COMPUTE_FP32 if compute == "fp32" else SFFT_COMPUTE_FP64,
+                              ref_pedestal=ref_pedestal, sci_pedestal=sci_pedestal)
+        st = sfft_validate(self.desc)
+        if st != SFFT_OK:
+            raise SfftError(st, "sfft_validate")
+        self.handle = Handle()
+        self.N = sfft_num_unknowns(self.desc)
+        nbytes = sfft_workspace_size(self.handle, self.desc)
+        dev = torch.device(device)
+        N = self.N
+        self.buf = Buffers(
+            G=torch.empty((N, N), dtype=torch.float64, device=dev),
+            h=torch.empty((N,), dtype=torch.float64, device=dev),
+            coef=torch.empty((N,), dtype=torch.float64, device=dev),
+            info=torch.zeros((64,), dtype=torch.uint8, device=dev),
+            diff=torch.empty((height, width), dtype=self.dtype, device=dev),
+            chi2=torch.zeros((1,), dtype=torch.float64, device=dev),
+            ws=torch.empty((nbytes + 255) // 256 * 256, dtype=torch.uint8, device=dev),
+        )
+
+    def set_pedestals(self, ref_pedestal, sci_pedestal):
+        self.desc.ref_pedestal = float(ref_pedestal)
+        self.desc.sci_pedestal = float(sci_pedestal)
+
+    def build(self, ref, sci, stream=None):
+        b = self.buf
+        sfft_build_system(self.handle, self.desc, ref, sci, b.G, b.h, b.ws, stream)
+
+    def solve(self, max_refine=2, stream=None):
+        b = self.buf
+        sfft_solve(self.handle, self.desc, b.G, b.h, b.coef, b.info, b.ws, max_refine, stream)
+
+    def subtract(self, ref, sci, coef=None, chi2=True, stream=None):
+        b = self.buf
+        sfft_subtract(self.handle, self.desc, ref, sci, b.coef if coef is None else coef, b.diff,
+                      b.chi2 if chi2 else None, b.ws, stream)
+
+    def run(self, ref, sci, max_refine=2, stream=None):
+        """build + solve + subtract (+ chi2) on the stream; asynchronous."""
+        self.build(ref, sci, stream)
+        self.solve(max_refine, stream)
+        self.subtract(ref, sci, stream=stream)
+        return self.buf
+
+    def info(self) -> SolveInfo:
+        return read_info(self.buf.info)

@@ -1,0 +1,214 @@
+// Host side of the C ABI declared in include/sfft.h: handle and plan tables,
+// argument validation, workspace sizing and kernel dispatch.
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "common.hpp"
+#include "layout.hpp"
+
+namespace sfft {
+
+hipError_t launch_build(const sfft_desc& d, const void* R, const void* S, double* G, double* hv,
+                        unsigned char* ws, const BuildPlan& p, const Prof* pf, hipStream_t st);
+hipError_t launch_solve(const sfft_desc& d, const double* G, const double* h, double* coef,
+                        int max_refine, sfft_solve_info* info, unsigned char* ws, const Prof* pf,
+                        hipStream_t st);
+hipError_t launch_subtract(const sfft_desc& d, const void* R, const void* S, const double* coef,
+                           void* D, double* chi2, unsigned char* ws, const Prof* pf,
+                           hipStream_t st);
+hipError_t prepare_kernel_attributes();
+
+struct Twiddles {
+  void* w64 = nullptr;    // cx<double>[n]
+  void* w32 = nullptr;    // cx<float>[n]
+};
+
+}  // namespace sfft
+
+struct sfft_handle_s {
+  int device = 0;
+  int num_cus = 0;
+  std::map<int, sfft::Twiddles> tw;   // keyed by transform length
+  sfft::Prof prof{};                  // timing events per sfft_prof_slot
+};
+
+namespace {
+
+using namespace sfft;
+
+// exp(-2 pi i m / n), m = 0..n-1, in FP64 on the host
+hipError_t get_twiddles(sfft_handle hd, int n, Twiddles& out) {
+  auto it = hd->tw.find(n);
+  if (it != hd->tw.end()) { out = it->second; return hipSuccess; }
+  std::vector<double> h64(2 * (size_t)n);
+  std::vector<float> h32(2 * (size_t)n);
+  for (int m = 0; m < n; ++m) {
+    const long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)n;
+    h64[2 * m] = (double)std::cos(ang);
+    h64[2 * m + 1] = (double)std::sin(ang);
+    h32[2 * m] = (float)h64[2 * m];
+    h32[2 * m + 1] = (float)h64[2 * m + 1];
+  }
+  Twiddles t;
+  hipError_t e;
+  if ((e = hipMalloc(&t.w64, sizeof(double) * 2 * n)) != hipSuccess) return e;
+  if ((e = hipMalloc(&t.w32, sizeof(float) * 2 * n)) != hipSuccess) { (void)hipFree(t.w64); return e; }
+  if ((e = hipMemcpy(t.w64, h64.data(), sizeof(double) * 2 * n, hipMemcpyHostToDevice)) != hipSuccess) return e;
+  if ((e = hipMemcpy(t.w32, h32.data(), sizeof(float) * 2 * n, hipMemcpyHostToDevice)) != hipSuccess) return e;
+  hd->tw[n] = t;
+  out = t;
+  return hipSuccess;
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+sfft_status check_device(sfft_handle hd) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return SFFT_ERR_HIP;
+  return dev == hd->device ? SFFT_OK : SFFT_ERR_INVALID_ARG;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sfft_status_string(sfft_status s) {
+  switch (s) {
+    case SFFT_OK: return "SFFT_OK";
+    case SFFT_ERR_INVALID_ARG: return "SFFT_ERR_INVALID_ARG";
+    case SFFT_ERR_UNSUPPORTED: return "SFFT_ERR_UNSUPPORTED";
+    case SFFT_ERR_WORKSPACE: return "SFFT_ERR_WORKSPACE";
+    case SFFT_ERR_NONFINITE: return "SFFT_ERR_NONFINITE";
+    case SFFT_ERR_NOT_SPD: return "SFFT_ERR_NOT_SPD";
+    case SFFT_ERR_HIP: return "SFFT_ERR_HIP";
+    case SFFT_ERR_INTERNAL: return "SFFT_ERR_INTERNAL";
+  }
+  return "SFFT_ERR_UNKNOWN";
+}
+
+int64_t sfft_num_unknowns(const sfft_desc* d) {
+  if (!d || d->L < 1 || (d->L % 2) == 0 || d->dk < 0 || d->dk > 4 || d->db < 0 || d->db > 4)
+    return -1;
+  const int64_t nk = (int64_t)(d->dk + 1) * (d->dk + 2) / 2;
+  const int64_t nb = (int64_t)(d->db + 1) * (d->db + 2) / 2;
+  return nk * d->L * d->L + nb;
+}
+
+sfft_status sfft_validate(const sfft_desc* d) {
+  if (!d) return SFFT_ERR_INVALID_ARG;
+  if (d->width < 1 || d->height < 1 || d->ld < d->width) return SFFT_ERR_INVALID_ARG;
+  if (d->L < 1 || (d->L % 2) == 0) return SFFT_ERR_INVALID_ARG;
+  if (d->L > d->width || d->L > d->height) return SFFT_ERR_INVALID_ARG;
+  if (d->dk < 0 || d->dk > 4 || d->db < 0 || d->db > 4) return SFFT_ERR_INVALID_ARG;
+  if (d->image_dtype != SFFT_F32 && d->image_dtype != SFFT_F64) return SFFT_ERR_INVALID_ARG;
+  if (d->compute != SFFT_COMPUTE_FP64 && d->compute != SFFT_COMPUTE_FP32) return SFFT_ERR_INVALID_ARG;
+  if (d->reserved != 0) return SFFT_ERR_INVALID_ARG;
+  if (!std::isfinite(d->ref_pedestal) || !std::isfinite(d->sci_pedestal)) return SFFT_ERR_INVALID_ARG;
+  if (!is_pow2(d->width) || d->width < 16 || d->width > kMaxW) return SFFT_ERR_UNSUPPORTED;
+  if (d->L > 15 || d->dk > 2) return SFFT_ERR_UNSUPPORTED;
+  if (d->width < 2 * d->L || d->height < 2 * d->L) return SFFT_ERR_UNSUPPORTED;
+  if ((int64_t)d->height * d->ld > ((int64_t)1 << 40)) return SFFT_ERR_UNSUPPORTED;
+  return SFFT_OK;
+}
+
+sfft_status sfft_create(sfft_handle* out) {
+  if (!out) return SFFT_ERR_INVALID_ARG;
+  *out = nullptr;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return SFFT_ERR_HIP;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return SFFT_ERR_HIP;
+  if (prepare_kernel_attributes() != hipSuccess) return SFFT_ERR_HIP;
+  sfft_handle h = new (std::nothrow) sfft_handle_s();
+  if (!h) return SFFT_ERR_INTERNAL;
+  h->device = dev;
+  h->num_cus = cus;
+  *out = h;
+  return SFFT_OK;
+}
+
+sfft_status sfft_destroy(sfft_handle h) {
+  if (!h) return SFFT_ERR_INVALID_ARG;
+  for (auto& kv : h->tw) {
+    if (kv.second.w64) (void)hipFree(kv.second.w64);
+    if (kv.second.w32) (void)hipFree(kv.second.w32);
+  }
+  delete h;
+  return SFFT_OK;
+}
+
+sfft_status sfft_workspace_size(sfft_handle h, const sfft_desc* d, size_t* bytes) {
+  if (!h || !bytes) return SFFT_ERR_INVALID_ARG;
+  const sfft_status s = sfft_validate(d);
+  if (s != SFFT_OK) return s;
+  *bytes = make_layout(make_geometry(*d)).total;
+  return SFFT_OK;
+}
+
+static sfft_status check_ws(const sfft_desc* d, void* ws, size_t ws_bytes) {
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0) return SFFT_ERR_WORKSPACE;
+  if (ws_bytes < make_layout(make_geometry(*d)).total) return SFFT_ERR_WORKSPACE;
+  return SFFT_OK;
+}
+
+sfft_status sfft_build_system(sfft_handle h, const sfft_desc* d, const void* ref, const void* sci,
+                              double* G, double* hv, void* ws, size_t ws_bytes, void* stream) {
+  if (!h) return SFFT_ERR_INVALID_ARG;
+  sfft_status s = sfft_validate(d);
+  if (s != SFFT_OK) return s;
+  if (!ref || !sci || !G || !hv) return SFFT_ERR_INVALID_ARG;
+  if ((s = check_ws(d, ws, ws_bytes)) != SFFT_OK) return s;
+  if ((s = check_device(h)) != SFFT_OK) return s;
+  Twiddles tw, t128;
+  if (get_twiddles(h, d->width, tw) != hipSuccess) return SFFT_ERR_HIP;
+  if (get_twiddles(h, kTP, t128) != hipSuccess) return SFFT_ERR_HIP;
+  const bool f32 = d->compute == SFFT_COMPUTE_FP32;
+  BuildPlan p{f32 ? tw.w32 : tw.w64, tw.w64, f32 ? t128.w32 : t128.w64, h->num_cus};
+  const hipError_t e = launch_build(*d, ref, sci, G, hv, static_cast<unsigned char*>(ws), p,
+                                    &h->prof, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
+}
+
+sfft_status sfft_solve(sfft_handle h, const sfft_desc* d, const double* G, const double* hv,
+                       double* coef, int32_t max_refine, sfft_solve_info* info, void* ws,
+                       size_t ws_bytes, void* stream) {
+  if (!h) return SFFT_ERR_INVALID_ARG;
+  sfft_status s = sfft_validate(d);
+  if (s != SFFT_OK) return s;
+  if (!G || !hv || !coef || !info || max_refine < 0 || max_refine > 8) return SFFT_ERR_INVALID_ARG;
+  if ((s = check_ws(d, ws, ws_bytes)) != SFFT_OK) return s;
+  if ((s = check_device(h)) != SFFT_OK) return s;
+  const hipError_t e = launch_solve(*d, G, hv, coef, max_refine, info,
+                                    static_cast<unsigned char*>(ws), &h->prof,
+                                    static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
+}
+
+sfft_status sfft_subtract(sfft_handle h, const sfft_desc* d, const void* ref, const void* sci,
+                          const double* coef, void* diff, double* chi2, void* ws, size_t ws_bytes,
+                          void* stream) {
+  if (!h) return SFFT_ERR_INVALID_ARG;
+  sfft_status s = sfft_validate(d);
+  if (s != SFFT_OK) return s;
+  if (!ref || !sci || !coef || !diff || diff == ref || diff == sci) return SFFT_ERR_INVALID_ARG;
+  if ((s = check_ws(d, ws, ws_bytes)) != SFFT_OK) return s;
+  if ((s = check_device(h)) != SFFT_OK) return s;
+  const hipError_t e = launch_subtract(*d, ref, sci, coef, diff, chi2,
+                                       static_cast<unsigned char*>(ws), &h->prof,
+                                       static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
+}
+
+sfft_status sfft_profile_events(sfft_handle h, int32_t slot, void* start_event, void* stop_event) {
+  if (!h || slot <= 0 || slot >= SFFT_PROF_MAX) return SFFT_ERR_INVALID_ARG;
+  if ((start_event == nullptr) != (stop_event == nullptr)) return SFFT_ERR_INVALID_ARG;
+  h->prof.start[slot] = start_event;
+  h->prof.stop[slot] = stop_event;
+  return SFFT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,179 @@
+// Shared device helpers of the SFFT library: complex arithmetic, in-register
+// small DFTs (radix 2/4/8/16, either sign), block reductions, launch checks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "sfft.h"
+
+namespace sfft {
+
+template <typename T>
+struct __attribute__((aligned(2 * sizeof(T)))) cx {
+  T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.re * s, a.im * s}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// conj(a) * b
+template <typename T>
+__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+// acc += conj(a) * b
+template <typename T>
+__device__ __forceinline__ void cmac_conj(cx<T>& acc, cx<T> a, cx<T> b) {
+  acc.re = fma(a.re, b.re, fma(a.im, b.im, acc.re));
+  acc.im = fma(a.re, b.im, fma(-a.im, b.re, acc.im));
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cconj(cx<T> a) { return {a.re, -a.im}; }
+// multiply by -i (forward) or +i (inverse)
+template <typename T, bool INV>
+__device__ __forceinline__ cx<T> rot90(cx<T> a) {
+  return INV ? cx<T>{-a.im, a.re} : cx<T>{a.im, -a.re};
+}
+
+// ---------------------------------------------------------------------------
+// In-register DFTs, X_k = sum_n v_n exp(-+2 pi i n k / R), unscaled.
+// INV = false: forward sign (-), INV = true: inverse sign (+).
+// ---------------------------------------------------------------------------
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft2(cx<T>& a, cx<T>& b) {
+  cx<T> t = a;
+  a = cadd(t, b);
+  b = csub(t, b);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4(cx<T>& a0, cx<T>& a1, cx<T>& a2, cx<T>& a3) {
+  cx<T> t0 = cadd(a0, a2), t1 = csub(a0, a2);
+  cx<T> t2 = cadd(a1, a3), t3 = rot90<T, INV>(csub(a1, a3));
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  a1 = cadd(t1, t3);
+  a3 = csub(t1, t3);
+}
+
+// multiply by w8^k, w8 = exp(-+2 pi i / 8)
+template <typename T, bool INV, int K>
+__device__ __forceinline__ cx<T> w8(cx<T> a) {
+  const T h = (T)0.70710678118654752440084436210485;
+  if (K == 0) return a;
+  if (K == 2) return rot90<T, INV>(a);
+  if (K == 1) return INV ? cx<T>{(a.re - a.im) * h, (a.re + a.im) * h}
+                         : cx<T>{(a.re + a.im) * h, (a.im - a.re) * h};
+  // K == 3
+  return INV ? cx<T>{-(a.re + a.im) * h, (a.re - a.im) * h}
+             : cx<T>{(a.im - a.re) * h, -(a.re + a.im) * h};
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft8(cx<T>* v) {
+  // even / odd split
+  cx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  cx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4<T, INV>(e0, e1, e2, e3);
+  dft4<T, INV>(o0, o1, o2, o3);
+  o1 = w8<T, INV, 1>(o1);
+  o2 = w8<T, INV, 2>(o2);
+  o3 = w8<T, INV, 3>(o3);
+  v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+  v[1] = cadd(e1, o1); v[5] = csub(e1, o1);
+  v[2] = cadd(e2, o2); v[6] = csub(e2, o2);
+  v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft16(cx<T>* v) {
+  cx<T> e[8], o[8];
+#pragma unroll
+  for (int n = 0; n < 8; ++n) { e[n] = v[2 * n]; o[n] = v[2 * n + 1]; }
+  dft8<T, INV>(e);
+  dft8<T, INV>(o);
+  // w16^k = cos(2 pi k / 16) -+ i sin(2 pi k / 16)
+  const T c1 = (T)0.92387953251128675612818318939679;
+  const T s1 = (T)0.38268343236508977172845998403040;
+  const T h = (T)0.70710678118654752440084436210485;
+  const T sg = INV ? (T)1 : (T)-1;
+  const cx<T> w[8] = {{(T)1, (T)0}, {c1, sg * s1}, {h, sg * h}, {s1, sg * c1},
+                      {(T)0, sg}, {-s1, sg * c1}, {-h, sg * h}, {-c1, sg * s1}};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    cx<T> t = (k == 0) ? o[k] : cmul(o[k], w[k]);
+    v[k] = cadd(e[k], t);
+    v[k + 8] = csub(e[k], t);
+  }
+}
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dft_r(cx<T>* v) {
+  if constexpr (R == 2) dft2<T, INV>(v[0], v[1]);
+  else if constexpr (R == 4) dft4<T, INV>(v[0], v[1], v[2], v[3]);
+  else if constexpr (R == 8) dft8<T, INV>(v);
+  else if constexpr (R == 16) dft16<T, INV>(v);
+}
+
+// ---------------------------------------------------------------------------
+// Reductions (fixed order: results are bit-reproducible run to run)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum of `v` over the block; every thread gets the result. `scratch` holds
+// at least blockDim.x / 64 doubles. Contains __syncthreads.
+__device__ __forceinline__ double block_sum(double v, double* scratch) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) scratch[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < nw; ++w) s += scratch[w];
+  return s;
+}
+
+__device__ __forceinline__ bool is_finite_d(double v) { return (v - v) == 0.0; }
+
+template <typename T>
+__device__ __forceinline__ double load_pix(const void* p, int64_t idx) {
+  return (double)static_cast<const T*>(p)[idx];
+}
+
+// polynomial monomial tables: exponent pairs of the layout order, up to D = 4
+struct MonoTable {
+  int n;
+  int a[15];
+  int b[15];
+};
+
+inline MonoTable make_monos(int D) {
+  MonoTable t{};
+  t.n = 0;
+  for (int d = 0; d <= D; ++d)
+    for (int b = 0; b <= d; ++b) {
+      t.a[t.n] = d - b;
+      t.b[t.n] = b;
+      ++t.n;
+    }
+  return t;
+}
+
+inline int n_mono(int D) { return (D + 1) * (D + 2) / 2; }
+
+}  // namespace sfft

@@ -1,0 +1,261 @@
+// sfft_subtract kernels: convolve the reference with the fitted spatially
+// varying kernel, subtract from the science image, and accumulate the chi2
+// judge (paper Sec. 2.3.2: difference image; Sec. 1: delta-basis kernel).
+//
+// D(x) = S'(x) - sum_d w_d(x - d) R'(x - d) - sum_c b_c q_c(x), where the
+// kernel value w_d(u) = sum_m c_m(d, u_y) xt(u_x)^m is evaluated at the input
+// pixel u by Horner in xt, with c_m(d, u_y) = sum_b a_((m,b),d) yt(u_y)^b
+// formed once per (tap, input row) and shared by a thread's 8 pixels.
+// Output tiles of 64 x 16 pixels; the reference tile with an r-pixel halo is
+// staged in LDS in FP64; accumulation in FP64.
+#include "common.hpp"
+#include "layout.hpp"
+
+namespace sfft {
+
+struct SubArgs {
+  const void* R;
+  const void* S;
+  void* D;
+  int64_t ld;
+  const double* coef;
+  const double* k2;     // [2DK+1][2DK+1] coefficients of kappa2(xt, yt)
+  double* partials;
+  int W, H, N, DB, want_chi2;
+  double cR, cS, sx, sy;
+};
+
+__device__ __forceinline__ int mono_index(int a, int b) {
+  const int d = a + b;
+  return d * (d + 1) / 2 + b;
+}
+
+template <int L, int DK, typename TIO>
+__global__ __launch_bounds__(128) void k_subtract(SubArgs a) {
+  constexpr int r = (L - 1) / 2;
+  constexpr int NK = (DK + 1) * (DK + 2) / 2;
+  constexpr int TX = kSubTX, TY = kSubTY, P = 8;
+  constexpr int RW = TX + 2 * r, RH = TY + 2 * r;
+  constexpr int NQ = P + 2 * r;
+  __shared__ double Rt[RH][RW + 1];
+  __shared__ double cs[NK * L * L];
+  __shared__ double red[2];
+  const int tid = threadIdx.x;
+  const int W = a.W, H = a.H;
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  for (int i = tid; i < NK * L * L; i += 128) cs[i] = a.coef[i];
+  for (int i = tid; i < RH * RW; i += 128) {
+    const int ly = i / RW, lx = i % RW;
+    int yy = y0 + ly - r, xx = x0 + lx - r;
+    yy %= H; if (yy < 0) yy += H;
+    xx %= W; if (xx < 0) xx += W;
+    Rt[ly][lx] = (double)static_cast<const TIO*>(a.R)[(int64_t)yy * a.ld + xx] - a.cR;
+  }
+  __syncthreads();
+  const int tx = tid & 7, ty = tid >> 3;
+  const int y = y0 + ty;
+  const int xb = x0 + P * tx;
+  double xq[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    int ux = (xb + q - r) % W;
+    if (ux < 0) ux += W;
+    xq[q] = (double)ux * a.sx - 1.0;
+  }
+  double acc[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) acc[p] = 0.0;
+#pragma unroll 1
+  for (int dyi = 0; dyi < L; ++dyi) {
+    const int lr = ty + (L - 1 - dyi);           // local row of u_y = y - dy
+    int uy = (y - (dyi - r)) % H;
+    if (uy < 0) uy += H;
+    const double yt = (double)uy * a.sy - 1.0;
+    double ypw[DK + 1];
+    ypw[0] = 1.0;
+#pragma unroll
+    for (int b = 1; b <= DK; ++b) ypw[b] = ypw[b - 1] * yt;
+    double win[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) win[q] = Rt[lr][P * tx + q];
+#pragma unroll
+    for (int dxi = 0; dxi < L; ++dxi) {
+      const int tap = dyi * L + dxi;
+      double cm[DK + 1];
+#pragma unroll
+      for (int m = 0; m <= DK; ++m) {
+        double s = 0.0;
+#pragma unroll
+        for (int b = 0; b <= DK - m; ++b) s = fma(cs[mono_index(m, b) * L * L + tap], ypw[b], s);
+        cm[m] = s;
+      }
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        const int q = p + (L - 1 - dxi);
+        double w = cm[DK];
+#pragma unroll
+        for (int m = DK - 1; m >= 0; --m) w = fma(w, xq[q], cm[m]);
+        acc[p] = fma(w, win[q], acc[p]);
+      }
+    }
+  }
+  // background, difference, chi2
+  const double yto = (double)y * a.sy - 1.0;
+  const double* bg = a.coef + NK * L * L;
+  const int DB = a.DB;
+  double chi = 0.0;
+  if (y < H) {
+    // per-row background polynomial in xt: coefficients e_k(yt)
+    double ek[5] = {0, 0, 0, 0, 0};
+    {
+      int c = 0;
+      for (int d = 0; d <= DB; ++d)
+        for (int b = 0; b <= d; ++b, ++c) {
+          double ypw = 1.0;
+          for (int t = 0; t < b; ++t) ypw *= yto;
+          ek[d - b] = fma(bg[c], ypw, ek[d - b]);
+        }
+    }
+    double kk[2 * DK + 1];
+    if (a.want_chi2) {
+#pragma unroll
+      for (int e = 0; e <= 2 * DK; ++e) {
+        double s = 0.0;
+        for (int f = 2 * DK; f >= 0; --f) s = fma(s, yto, a.k2[e * (2 * DK + 1) + f]);
+        kk[e] = s;
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int x = xb + p;
+      if (x < W) {
+        const double xt = (double)x * a.sx - 1.0;
+        double bgv = 0.0;
+        for (int k = DB; k >= 0; --k) bgv = fma(bgv, xt, ek[k]);
+        const double sv = (double)static_cast<const TIO*>(a.S)[(int64_t)y * a.ld + x];
+        const double dv = (sv - a.cS) - acc[p] - bgv;
+        static_cast<TIO*>(a.D)[(int64_t)y * a.ld + x] = (TIO)dv;
+        if (a.want_chi2 && x >= r && x < W - r && y >= r && y < H - r) {
+          double k2v = 0.0;
+#pragma unroll
+          for (int e = 2 * DK; e >= 0; --e) k2v = fma(k2v, xt, kk[e]);
+          const double rv = Rt[ty + r][P * tx + p + r] + a.cR;
+          const double var = fmax(sv, 1.0) + k2v * fmax(rv, 1.0);
+          chi = fma(dv, dv / var, chi);
+        }
+      }
+    }
+  }
+  if (a.want_chi2) {
+    chi = wave_sum(chi);
+    if ((tid & 63) == 0) red[tid >> 6] = chi;
+    __syncthreads();
+    if (tid == 0) a.partials[blockIdx.y * gridDim.x + blockIdx.x] = red[0] + red[1];
+  }
+}
+
+// kappa2 polynomial: K2[ai+aj][bi+bj] += sum_d a_(i,d) a_(j,d)
+__global__ __launch_bounds__(256) void k_kappa2(const double* coef, double* k2, int L, int DK) {
+  __shared__ double Q[15][15];
+  const int nK = (DK + 1) * (DK + 2) / 2;
+  const int L2 = L * L;
+  const int tid = threadIdx.x;
+  if (tid < nK * nK) {
+    const int i = tid / nK, j = tid % nK;
+    double s = 0.0;
+    for (int d = 0; d < L2; ++d) s = fma(coef[i * L2 + d], coef[j * L2 + d], s);
+    Q[i][j] = s;
+  }
+  __syncthreads();
+  const int ne = 2 * DK + 1;
+  if (tid < ne * ne) {
+    const int e = tid / ne, f = tid % ne;
+    double s = 0.0;
+    int i = 0;
+    for (int di = 0; di <= DK; ++di)
+      for (int bi = 0; bi <= di; ++bi, ++i) {
+        int j = 0;
+        for (int dj = 0; dj <= DK; ++dj)
+          for (int bj = 0; bj <= dj; ++bj, ++j) {
+            const int ai = di - bi, aj = dj - bj;
+            if (ai + aj == e && bi + bj == f) s += Q[i][j];
+          }
+      }
+    k2[e * ne + f] = s;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_chi2_final(const double* partials, int n, double dof,
+                                                     double* out) {
+  __shared__ double scratch[16];
+  double s = 0.0;
+  // fixed assignment of partials to threads, fixed tree: reproducible
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += partials[i];
+  s = block_sum(s, scratch);
+  if (threadIdx.x == 0) *out = s / dof;
+}
+
+template <int L, int DK>
+static hipError_t launch_sub_ldk(const SubArgs& a, bool f32, dim3 grid, hipStream_t st) {
+  if (f32) hipLaunchKernelGGL((k_subtract<L, DK, float>), grid, dim3(128), 0, st, a);
+  else hipLaunchKernelGGL((k_subtract<L, DK, double>), grid, dim3(128), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int L>
+static hipError_t launch_sub_l(const SubArgs& a, int DK, bool f32, dim3 grid, hipStream_t st) {
+  switch (DK) {
+    case 0: return launch_sub_ldk<L, 0>(a, f32, grid, st);
+    case 1: return launch_sub_ldk<L, 1>(a, f32, grid, st);
+    case 2: return launch_sub_ldk<L, 2>(a, f32, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_subtract(const sfft_desc& d, const void* R, const void* S, const double* coef,
+                           void* D, double* chi2, unsigned char* ws, const Prof* pf,
+                           hipStream_t st) {
+  const Geometry g = make_geometry(d);
+  const Layout l = make_layout(g);
+  SubArgs a{};
+  a.R = R; a.S = S; a.D = D; a.ld = d.ld; a.coef = coef;
+  a.k2 = reinterpret_cast<const double*>(ws + l.kcoef);
+  a.partials = reinterpret_cast<double*>(ws + l.partials);
+  a.W = g.W; a.H = g.H; a.N = g.N; a.DB = g.DB; a.want_chi2 = chi2 != nullptr;
+  a.cR = d.ref_pedestal; a.cS = d.sci_pedestal;
+  a.sx = g.W > 1 ? 2.0 / (double)(g.W - 1) : 0.0;
+  a.sy = g.H > 1 ? 2.0 / (double)(g.H - 1) : 0.0;
+  hipError_t e;
+  if (chi2) {
+    hipLaunchKernelGGL(k_kappa2, dim3(1), dim3(256), 0, st, coef,
+                       reinterpret_cast<double*>(ws + l.kcoef), g.L, g.DK);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  const dim3 grid((g.W + kSubTX - 1) / kSubTX, (g.H + kSubTY - 1) / kSubTY);
+  const bool f32 = d.image_dtype == SFFT_F32;
+  prof_begin(pf, SFFT_PROF_SUBTRACT, st);
+  switch (g.L) {
+    case 1: e = launch_sub_l<1>(a, g.DK, f32, grid, st); break;
+    case 3: e = launch_sub_l<3>(a, g.DK, f32, grid, st); break;
+    case 5: e = launch_sub_l<5>(a, g.DK, f32, grid, st); break;
+    case 7: e = launch_sub_l<7>(a, g.DK, f32, grid, st); break;
+    case 9: e = launch_sub_l<9>(a, g.DK, f32, grid, st); break;
+    case 11: e = launch_sub_l<11>(a, g.DK, f32, grid, st); break;
+    case 13: e = launch_sub_l<13>(a, g.DK, f32, grid, st); break;
+    case 15: e = launch_sub_l<15>(a, g.DK, f32, grid, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  prof_end(pf, SFFT_PROF_SUBTRACT, st);
+  if (e != hipSuccess) return e;
+  if (chi2) {
+    const int r = g.r;
+    const double inner = (double)(g.W - 2 * r) * (double)(g.H - 2 * r);
+    const double dof = inner - (double)g.N;
+    hipLaunchKernelGGL(k_chi2_final, dim3(1), dim3(1024), 0, st,
+                       (const double*)a.partials, l.npartials, dof, chi2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace sfft
