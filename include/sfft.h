@@ -105,9 +105,11 @@ const char* sfft_status_string(sfft_status status);
  * Host-only; needs no device. */
 int64_t sfft_num_unknowns(const sfft_desc* desc);
 
-/* Host-only validation. SFFT_ERR_INVALID_ARG: see sfft_status.
- * SFFT_ERR_UNSUPPORTED: W not a power of two in [16, 4096]; H < 2L or
- * W < 2L; L > 31; DK > 2; reserved != 0. */
+/* Host-only validation of a descriptor for sfft_build_system.
+ * SFFT_ERR_INVALID_ARG: see sfft_status. SFFT_ERR_UNSUPPORTED: L > 15 or
+ * DK > 2 (every call); W odd, not of the form 2^a 3^b 5^c, or outside
+ * [16, 4096], H < 2L or W < 2L (FFT build only: sfft_solve, sfft_subtract
+ * and sfft_build_system_stamps accept any width and height >= L). */
 sfft_status sfft_validate(const sfft_desc* desc);
 
 /* Bytes of device workspace needed by sfft_build_system, sfft_solve and
@@ -154,6 +156,32 @@ sfft_status sfft_subtract(sfft_handle handle, const sfft_desc* desc,
                           void* diff, double* chi2,
                           void* ws, size_t ws_bytes, void* stream);
 
+/* Precision form of the build: the same least-squares problem restricted to
+ * the pixels of n_stamps square stamps of side `size` (odd) centred on
+ * star pixels (the star-stamp mode of SFFT, paper Sec. 1 and Sec. 2.3.2),
+ * with periodic indexing as above. Writes G_s = A_s^T A_s and h_s = A_s^T S'
+ * where A_s holds the design rows of the stamp pixels. The Gram sums run on
+ * the matrix cores: each operand is rounded to FP32 and split as
+ * hi = bf16(a), lo = bf16(a - hi) (round to nearest even), each product is
+ * taken as hi*hi + hi*lo + lo*hi, accumulated in FP32 within a workgroup's
+ * share of the stamps and in FP64 across shares (relative error per entry
+ * about 2^-15 of the sum of absolute products).
+ *   centers : device int32[n_stamps][2] = (x, y) stamp centre pixels
+ *   size    : odd, 1..127, <= min(W, H); n_stamps in [1, 65536]
+ *   G, h    : device, as for sfft_build_system
+ *   ws      : device workspace of at least sfft_stamps_workspace_size bytes;
+ *             it also serves sfft_solve and sfft_subtract for this descriptor
+ * SFFT_ERR_UNSUPPORTED when the planes a Gram tile reads do not fit in LDS
+ * (large stamps with DB = 4). Non-finite pixels near the stamps are flagged
+ * in ws for sfft_solve. The compute field of desc is ignored. */
+sfft_status sfft_stamps_workspace_size(sfft_handle handle, const sfft_desc* desc,
+                                       int32_t n_stamps, int32_t size, size_t* bytes);
+sfft_status sfft_build_system_stamps(sfft_handle handle, const sfft_desc* desc,
+                                     const void* ref, const void* sci,
+                                     const int32_t* centers, int32_t n_stamps, int32_t size,
+                                     double* G, double* h,
+                                     void* ws, size_t ws_bytes, void* stream);
+
 /* Kernel timing hook (measurement support, not part of the method).
  * Kernels / launch groups that can be bracketed by events: */
 typedef enum {
@@ -163,6 +191,7 @@ typedef enum {
   SFFT_PROF_SUBTRACT = 4,     /* convolve-and-subtract + chi2 partials (one kernel) */
   SFFT_PROF_SOLVE = 5,        /* every launch of sfft_solve */
   SFFT_PROF_BUILD = 6,        /* every launch of sfft_build_system */
+  SFFT_PROF_STAMP_GRAM = 7,   /* stamp Gram sums on matrix cores (one kernel) */
   SFFT_PROF_MAX = 8
 } sfft_prof_slot;
 

@@ -359,3 +359,96 @@ def normal_entry(R, L, DK, row, col, ref_pedestal=0.0) -> float:
     a = np.roll(Pi, shift=(d // L - r, d % L - r), axis=(0, 1))
     b = np.roll(Pj, shift=(d2 // L - r, d2 % L - r), axis=(0, 1))
     return float(np.sum(a * b))
+
+
+# ---------------------------------------------------------------------------
+# O3: the least-squares problem restricted to star stamps (precision form)
+# ---------------------------------------------------------------------------
+# The same design matrix as O1, keeping only the rows of pixels that lie in
+# square stamps of side `size` centred on the given pixels (periodic
+# indexing). Its normal equations are the Gram sums G_s = A_s^T A_s,
+# h_s = A_s^T S'_s. The precision form evaluates these sums on matrix cores
+# with each FP32 operand split into two bfloat16 halves; stamp_normal_split
+# gives the exact value of that split-product sum (before any FP32
+# accumulation rounding), and bf16_rne / split_bf16 define the split.
+
+
+def stamp_pixels(W: int, H: int, centers, size: int):
+    """(ys, xs) of every stamp pixel: stamps in the given order, row-major
+    inside a stamp, coordinates wrapped into the image."""
+    centers = np.asarray(centers, dtype=np.int64).reshape(-1, 2)
+    h = size // 2
+    off = np.arange(size) - h
+    ys = (centers[:, 1, None, None] + off[None, :, None]) % H
+    xs = (centers[:, 0, None, None] + off[None, None, :]) % W
+    ys, xs = np.broadcast_arrays(ys, xs)
+    return ys.reshape(-1), xs.reshape(-1)
+
+
+def stamp_design(R, centers, size, L, DK, DB, ref_pedestal=0.0) -> np.ndarray:
+    """A_s: rows of the design matrix at the stamp pixels. Column (i, delta)
+    holds p_i(u) R'(u) at u = x - delta; column c holds q_c(x)."""
+    Rp, _ = _prep(R, None, ref_pedestal, 0.0)
+    H, W = Rp.shape
+    ys, xs = stamp_pixels(W, H, centers, size)
+    P = poly_images(W, H, DK) * Rp
+    Q = poly_images(W, H, DB)
+    cols = []
+    for i in range(P.shape[0]):
+        for dy, dx in zip(*kernel_offsets(L)):
+            cols.append(P[i][(ys - dy) % H, (xs - dx) % W])
+    for c in range(Q.shape[0]):
+        cols.append(Q[c][ys, xs])
+    return np.stack(cols, axis=1)
+
+
+def stamp_normal64(R, S, centers, size, L, DK, DB, ref_pedestal=0.0, sci_pedestal=0.0):
+    """Exact FP64 stamp normal equations (G_s, h_s)."""
+    A = stamp_design(R, centers, size, L, DK, DB, ref_pedestal)
+    _, Sp = _prep(R, S, ref_pedestal, sci_pedestal)
+    ys, xs = stamp_pixels(Sp.shape[1], Sp.shape[0], centers, size)
+    s = Sp[ys, xs]
+    return A.T @ A, A.T @ s
+
+
+def bf16_rne(x) -> np.ndarray:
+    """Round FP32 values to bfloat16 (8 significant bits), ties to even;
+    returned as float32. Finite inputs only."""
+    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+def split_bf16(a):
+    """a (FP32) = hi + lo + e with hi = bf16(a), lo = bf16(a - hi) (a - hi is
+    exact in FP32); |e| <= 2^-16 |a|."""
+    a = np.asarray(a, dtype=np.float32)
+    hi = bf16_rne(a)
+    lo = bf16_rne(a - hi)
+    return hi, lo
+
+
+def stamp_normal_split(R, S, centers, size, L, DK, DB, ref_pedestal=0.0, sci_pedestal=0.0):
+    """The Gram sums the split-product form computes, evaluated exactly:
+    every design value and stamp value is first rounded to FP32, split into
+    (hi, lo), and each product a*b is replaced by hi_a hi_b + hi_a lo_b +
+    lo_a hi_b (the lo*lo term is dropped); all sums in FP64 (exact products).
+    Returns (G, h)."""
+    A = stamp_design(R, centers, size, L, DK, DB, ref_pedestal).astype(np.float32)
+    _, Sp = _prep(R, S, ref_pedestal, sci_pedestal)
+    ys, xs = stamp_pixels(Sp.shape[1], Sp.shape[0], centers, size)
+    s = Sp[ys, xs].astype(np.float32)
+    Ah, Al = (t.astype(np.float64) for t in split_bf16(A))
+    sh, sl = (t.astype(np.float64) for t in split_bf16(s))
+    G = Ah.T @ Ah + Ah.T @ Al + Al.T @ Ah
+    h = Ah.T @ sh + Ah.T @ sl + Al.T @ sh
+    return G, h
+
+
+def stamp_abs_gram(R, S, centers, size, L, DK, DB, ref_pedestal=0.0, sci_pedestal=0.0):
+    """|A_s|^T |A_s| and |A_s|^T |S'_s|: the scale of each Gram entry's
+    rounding-error bound."""
+    A = np.abs(stamp_design(R, centers, size, L, DK, DB, ref_pedestal))
+    _, Sp = _prep(R, S, ref_pedestal, sci_pedestal)
+    ys, xs = stamp_pixels(Sp.shape[1], Sp.shape[0], centers, size)
+    return A.T @ A, A.T @ np.abs(Sp[ys, xs])

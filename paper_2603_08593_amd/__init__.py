@@ -77,7 +77,16 @@ _SIGS = {
     "sfft_solve": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, ctypes.c_int32, _P, _P,
                                   ctypes.c_size_t, _P]),
     "sfft_subtract": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "sfft_stamps_workspace_size": (ctypes.c_int, [_P, ctypes.POINTER(Desc), ctypes.c_int32, ctypes.c_int32,
+                                                  ctypes.POINTER(ctypes.c_size_t)]),
+    "sfft_build_system_stamps": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, ctypes.c_int32,
+                                                ctypes.c_int32, _P, _P, _P, ctypes.c_size_t, _P]),
+    "sfft_profile_events": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
 }
+
+# sfft_prof_slot
+SFFT_PROF_ROW_PASS, SFFT_PROF_COL_PASS, SFFT_PROF_XINV, SFFT_PROF_SUBTRACT = 1, 2, 3, 4
+SFFT_PROF_SOLVE, SFFT_PROF_BUILD, SFFT_PROF_STAMP_GRAM = 5, 6, 7
 
 _lib = None
 
@@ -181,6 +190,27 @@ def sfft_subtract(handle: Handle, desc: Desc, ref, sci, coef, diff, chi2, ws, st
            "sfft_subtract")
 
 
+def sfft_stamps_workspace_size(handle: Handle, desc: Desc, n_stamps: int, size: int) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().sfft_stamps_workspace_size(handle.ptr, ctypes.byref(desc), int(n_stamps), int(size),
+                                            ctypes.byref(n)), "sfft_stamps_workspace_size")
+    return int(n.value)
+
+
+def sfft_build_system_stamps(handle: Handle, desc: Desc, ref, sci, centers, size, G, h, ws, stream=None):
+    """centers: device int32 tensor (n, 2) of (x, y)."""
+    _check(lib().sfft_build_system_stamps(handle.ptr, ctypes.byref(desc), _dp(ref), _dp(sci), _dp(centers),
+                                          int(centers.shape[0]), int(size), _dp(G), _dp(h), _dp(ws),
+                                          ws.numel() * ws.element_size(), _stream_ptr(stream)),
+           "sfft_build_system_stamps")
+
+
+def sfft_profile_events(handle: Handle, slot: int, start_event, stop_event):
+    """Bracket every launch of `slot` with the given hipEvent_t handles (ints or None)."""
+    _check(lib().sfft_profile_events(handle.ptr, int(slot), _P(start_event), _P(stop_event)),
+           "sfft_profile_events")
+
+
 def read_info(info_tensor) -> SolveInfo:
     """Copy a device sfft_solve_info (uint8 tensor) to the host."""
     raw = bytes(info_tensor.cpu().numpy().tobytes())
@@ -202,7 +232,7 @@ class Differencer:
     """Reusable device buffers + handle for one image shape and fit."""
 
     def __init__(self, width, height, L, dk, db, *, image_dtype="float32", compute="fp64",
-                 ref_pedestal=0.0, sci_pedestal=0.0, device="cuda"):
+                 ref_pedestal=0.0, sci_pedestal=0.0, device="cuda", stamps=None):
         import torch
         self.torch = torch
         self.dtype = torch.float32 if image_dtype in ("float32", torch.float32) else torch.float64
@@ -210,12 +240,19 @@ class Differencer:
                               image_dtype=SFFT_F32 if self.dtype == torch.float32 else SFFT_F64,
                               compute=SFFT_COMPUTE_FP32 if compute == "fp32" else SFFT_COMPUTE_FP64,
                               ref_pedestal=ref_pedestal, sci_pedestal=sci_pedestal)
-        st = sfft_validate(self.desc)
-        if st != SFFT_OK:
-            raise SfftError(st, "sfft_validate")
         self.handle = Handle()
         self.N = sfft_num_unknowns(self.desc)
-        nbytes = sfft_workspace_size(self.handle, self.desc)
+        # stamps = (n_stamps, size): size the workspace for the stamp build as well
+        self.stamps = stamps
+        if stamps is None:
+            st = sfft_validate(self.desc)
+            if st != SFFT_OK:
+                raise SfftError(st, "sfft_validate")
+            nbytes = sfft_workspace_size(self.handle, self.desc)
+        else:
+            nbytes = sfft_stamps_workspace_size(self.handle, self.desc, stamps[0], stamps[1])
+            if sfft_validate(self.desc) == SFFT_OK:
+                nbytes = max(nbytes, sfft_workspace_size(self.handle, self.desc))
         dev = torch.device(device)
         N = self.N
         self.buf = Buffers(
@@ -235,6 +272,10 @@ class Differencer:
     def build(self, ref, sci, stream=None):
         b = self.buf
         sfft_build_system(self.handle, self.desc, ref, sci, b.G, b.h, b.ws, stream)
+
+    def build_stamps(self, ref, sci, centers, size, stream=None):
+        b = self.buf
+        sfft_build_system_stamps(self.handle, self.desc, ref, sci, centers, size, b.G, b.h, b.ws, stream)
 
     def solve(self, max_refine=2, stream=None):
         b = self.buf

@@ -8,6 +8,7 @@
 
 #include "common.hpp"
 #include "layout.hpp"
+#include "stamps.hpp"
 
 namespace sfft {
 
@@ -19,7 +20,12 @@ hipError_t launch_solve(const sfft_desc& d, const double* G, const double* h, do
 hipError_t launch_subtract(const sfft_desc& d, const void* R, const void* S, const double* coef,
                            void* D, double* chi2, unsigned char* ws, const Prof* pf,
                            hipStream_t st);
+hipError_t launch_stamps(const sfft_desc& d, const void* R, const void* S, const int32_t* centers,
+                         int nst, int size, double* G, double* hv, unsigned char* ws, int num_cus,
+                         const Prof* pf, hipStream_t st);
 hipError_t prepare_kernel_attributes();
+hipError_t prepare_solve_attributes();
+void prepare_stamp_attributes();
 
 struct Twiddles {
   void* w64 = nullptr;    // cx<double>[n]
@@ -63,7 +69,12 @@ hipError_t get_twiddles(sfft_handle hd, int n, Twiddles& out) {
   return hipSuccess;
 }
 
-bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+bool is_smooth235(int v) {
+  if (v <= 0) return false;
+  for (int f : {2, 3, 5})
+    while (v % f == 0) v /= f;
+  return v == 1;
+}
 
 sfft_status check_device(sfft_handle hd) {
   int dev = -1;
@@ -97,7 +108,10 @@ int64_t sfft_num_unknowns(const sfft_desc* d) {
   return nk * d->L * d->L + nb;
 }
 
-sfft_status sfft_validate(const sfft_desc* d) {
+}  // extern "C"
+
+// argument rules plus the limits of the solve and subtract kernels
+static sfft_status validate_core(const sfft_desc* d) {
   if (!d) return SFFT_ERR_INVALID_ARG;
   if (d->width < 1 || d->height < 1 || d->ld < d->width) return SFFT_ERR_INVALID_ARG;
   if (d->L < 1 || (d->L % 2) == 0) return SFFT_ERR_INVALID_ARG;
@@ -107,10 +121,19 @@ sfft_status sfft_validate(const sfft_desc* d) {
   if (d->compute != SFFT_COMPUTE_FP64 && d->compute != SFFT_COMPUTE_FP32) return SFFT_ERR_INVALID_ARG;
   if (d->reserved != 0) return SFFT_ERR_INVALID_ARG;
   if (!std::isfinite(d->ref_pedestal) || !std::isfinite(d->sci_pedestal)) return SFFT_ERR_INVALID_ARG;
-  if (!is_pow2(d->width) || d->width < 16 || d->width > kMaxW) return SFFT_ERR_UNSUPPORTED;
   if (d->L > 15 || d->dk > 2) return SFFT_ERR_UNSUPPORTED;
-  if (d->width < 2 * d->L || d->height < 2 * d->L) return SFFT_ERR_UNSUPPORTED;
   if ((int64_t)d->height * d->ld > ((int64_t)1 << 40)) return SFFT_ERR_UNSUPPORTED;
+  return SFFT_OK;
+}
+
+extern "C" {
+
+sfft_status sfft_validate(const sfft_desc* d) {
+  const sfft_status s = validate_core(d);
+  if (s != SFFT_OK) return s;
+  if (!is_smooth235(d->width) || (d->width & 1) || d->width < 16 || d->width > kMaxW)
+    return SFFT_ERR_UNSUPPORTED;
+  if (d->width < 2 * d->L || d->height < 2 * d->L) return SFFT_ERR_UNSUPPORTED;
   return SFFT_OK;
 }
 
@@ -123,6 +146,8 @@ sfft_status sfft_create(sfft_handle* out) {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return SFFT_ERR_HIP;
   if (prepare_kernel_attributes() != hipSuccess) return SFFT_ERR_HIP;
+  if (prepare_solve_attributes() != hipSuccess) return SFFT_ERR_HIP;
+  prepare_stamp_attributes();
   sfft_handle h = new (std::nothrow) sfft_handle_s();
   if (!h) return SFFT_ERR_INTERNAL;
   h->device = dev;
@@ -149,9 +174,9 @@ sfft_status sfft_workspace_size(sfft_handle h, const sfft_desc* d, size_t* bytes
   return SFFT_OK;
 }
 
-static sfft_status check_ws(const sfft_desc* d, void* ws, size_t ws_bytes) {
+static sfft_status check_ws(void* ws, size_t ws_bytes, size_t need) {
   if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0) return SFFT_ERR_WORKSPACE;
-  if (ws_bytes < make_layout(make_geometry(*d)).total) return SFFT_ERR_WORKSPACE;
+  if (ws_bytes < need) return SFFT_ERR_WORKSPACE;
   return SFFT_OK;
 }
 
@@ -161,7 +186,7 @@ sfft_status sfft_build_system(sfft_handle h, const sfft_desc* d, const void* ref
   sfft_status s = sfft_validate(d);
   if (s != SFFT_OK) return s;
   if (!ref || !sci || !G || !hv) return SFFT_ERR_INVALID_ARG;
-  if ((s = check_ws(d, ws, ws_bytes)) != SFFT_OK) return s;
+  if ((s = check_ws(ws, ws_bytes, make_layout(make_geometry(*d)).total)) != SFFT_OK) return s;
   if ((s = check_device(h)) != SFFT_OK) return s;
   Twiddles tw, t128;
   if (get_twiddles(h, d->width, tw) != hipSuccess) return SFFT_ERR_HIP;
@@ -177,10 +202,10 @@ sfft_status sfft_solve(sfft_handle h, const sfft_desc* d, const double* G, const
                        double* coef, int32_t max_refine, sfft_solve_info* info, void* ws,
                        size_t ws_bytes, void* stream) {
   if (!h) return SFFT_ERR_INVALID_ARG;
-  sfft_status s = sfft_validate(d);
+  sfft_status s = validate_core(d);
   if (s != SFFT_OK) return s;
   if (!G || !hv || !coef || !info || max_refine < 0 || max_refine > 8) return SFFT_ERR_INVALID_ARG;
-  if ((s = check_ws(d, ws, ws_bytes)) != SFFT_OK) return s;
+  if ((s = check_ws(ws, ws_bytes, make_layout(make_geometry(*d)).solve_end)) != SFFT_OK) return s;
   if ((s = check_device(h)) != SFFT_OK) return s;
   const hipError_t e = launch_solve(*d, G, hv, coef, max_refine, info,
                                     static_cast<unsigned char*>(ws), &h->prof,
@@ -192,14 +217,63 @@ sfft_status sfft_subtract(sfft_handle h, const sfft_desc* d, const void* ref, co
                           const double* coef, void* diff, double* chi2, void* ws, size_t ws_bytes,
                           void* stream) {
   if (!h) return SFFT_ERR_INVALID_ARG;
-  sfft_status s = sfft_validate(d);
+  sfft_status s = validate_core(d);
   if (s != SFFT_OK) return s;
   if (!ref || !sci || !coef || !diff || diff == ref || diff == sci) return SFFT_ERR_INVALID_ARG;
-  if ((s = check_ws(d, ws, ws_bytes)) != SFFT_OK) return s;
+  if ((s = check_ws(ws, ws_bytes, make_layout(make_geometry(*d)).sub_end)) != SFFT_OK) return s;
   if ((s = check_device(h)) != SFFT_OK) return s;
   const hipError_t e = launch_subtract(*d, ref, sci, coef, diff, chi2,
                                        static_cast<unsigned char*>(ws), &h->prof,
                                        static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
+}
+
+// The stamp form needs no FFT: any width; the solve and subtract limits stay.
+static sfft_status validate_stamps(const sfft_desc* d, int32_t n, int32_t size) {
+  sfft_status s = validate_core(d);
+  if (s != SFFT_OK) return s;
+  if (n < 1 || n > kStMaxStamps || size < 1 || (size % 2) == 0 || size > kStMaxSize)
+    return SFFT_ERR_INVALID_ARG;
+  if (size > d->width || size > d->height) return SFFT_ERR_INVALID_ARG;
+  const StampGeom g = make_stamp_geom(*d, size);
+  if (g.nK + g.nB + 1 > kStMaxPlanes) return SFFT_ERR_UNSUPPORTED;
+  if (make_stamp_plan(g, n, 256).lds_bytes > (size_t)kStMaxLds) return SFFT_ERR_UNSUPPORTED;
+  return SFFT_OK;
+}
+
+static size_t stamps_ws_total(const sfft_desc& d, int32_t n, int32_t size, int num_cus) {
+  const StampGeom g = make_stamp_geom(d, size);
+  const size_t sw = make_stamp_plan(g, n, num_cus).ws_bytes;
+  const Layout l = make_layout(make_geometry(d));
+  size_t t = sw;
+  if (l.solve_end > t) t = l.solve_end;
+  if (l.sub_end > t) t = l.sub_end;
+  return t;
+}
+
+sfft_status sfft_stamps_workspace_size(sfft_handle h, const sfft_desc* d, int32_t n_stamps,
+                                       int32_t size, size_t* bytes) {
+  if (!h || !bytes) return SFFT_ERR_INVALID_ARG;
+  const sfft_status s = validate_stamps(d, n_stamps, size);
+  if (s != SFFT_OK) return s;
+  *bytes = stamps_ws_total(*d, n_stamps, size, h->num_cus);
+  return SFFT_OK;
+}
+
+sfft_status sfft_build_system_stamps(sfft_handle h, const sfft_desc* d, const void* ref,
+                                     const void* sci, const int32_t* centers, int32_t n_stamps,
+                                     int32_t size, double* G, double* hv, void* ws,
+                                     size_t ws_bytes, void* stream) {
+  if (!h) return SFFT_ERR_INVALID_ARG;
+  sfft_status s = validate_stamps(d, n_stamps, size);
+  if (s != SFFT_OK) return s;
+  if (!ref || !sci || !centers || !G || !hv) return SFFT_ERR_INVALID_ARG;
+  if ((s = check_ws(ws, ws_bytes, stamps_ws_total(*d, n_stamps, size, h->num_cus))) != SFFT_OK)
+    return s;
+  if ((s = check_device(h)) != SFFT_OK) return s;
+  const hipError_t e = launch_stamps(*d, ref, sci, centers, n_stamps, size, G, hv,
+                                     static_cast<unsigned char*>(ws), h->num_cus, &h->prof,
+                                     static_cast<hipStream_t>(stream));
   return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
 }
 

@@ -41,14 +41,19 @@ __device__ __forceinline__ int pad8(int i) { return i + (i >> 3); }
 __device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
 
 // ---------------------------------------------------------------------------
-// Stockham FFT of length N (power of two, <= 4096) in LDS, 256 threads.
-// buf uses the padded index pad8(i); tw[m] = exp(-2 pi i m / N).
-// Output in natural order.
+// Stockham FFT of length N = 2^a 3^b 5^c (<= 4096) in LDS, 256 threads,
+// stages of radix 8, 4, 2, 3, 5 (host-chosen plan). buf uses the padded index
+// pad8(i); tw[m] = exp(-2 pi i m / N). Output in natural order.
 // ---------------------------------------------------------------------------
+
+struct FftPlan {
+  int nstages;
+  int radix[12];
+};
 
 template <typename T, int R, bool INV, int NQ>
 __device__ __forceinline__ void stockham_pass(cx<T>* buf, const cx<T>* tw, int N, int Ns) {
-  constexpr int MAXB = (NQ / R) > 0 ? (NQ / R) : 1;
+  constexpr int MAXB = (NQ * kRowThreads + R * kRowThreads - 1) / (R * kRowThreads);
   const int nb = N / R;
   const int tstride = N / (Ns * R);
   cx<T> v[MAXB][R];
@@ -56,7 +61,7 @@ __device__ __forceinline__ void stockham_pass(cx<T>* buf, const cx<T>* tw, int N
   for (int t = 0; t < MAXB; ++t) {
     const int j = threadIdx.x + t * kRowThreads;
     if (j < nb) {
-      const int k = j & (Ns - 1);
+      const int k = j % Ns;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[t][r] = buf[pad8(j + r * nb)];
       if (Ns > 1) {
@@ -75,7 +80,7 @@ __device__ __forceinline__ void stockham_pass(cx<T>* buf, const cx<T>* tw, int N
   for (int t = 0; t < MAXB; ++t) {
     const int j = threadIdx.x + t * kRowThreads;
     if (j < nb) {
-      const int k = j & (Ns - 1);
+      const int k = j % Ns;
       const int base = (j - k) * R + k;
 #pragma unroll
       for (int r = 0; r < R; ++r) buf[pad8(base + r * Ns)] = v[t][r];
@@ -84,17 +89,35 @@ __device__ __forceinline__ void stockham_pass(cx<T>* buf, const cx<T>* tw, int N
   __syncthreads();
 }
 
-template <typename T, bool INV, int NQ>
-__device__ void fft_lds(cx<T>* buf, const cx<T>* tw, int N, int logN) {
+template <typename T, bool INV, int NQ, bool MIXED>
+__device__ void fft_lds(cx<T>* buf, const cx<T>* tw, int N, const FftPlan& plan) {
   int Ns = 1;
-  int rem = logN;
-  while (rem >= 3) {
-    stockham_pass<T, 8, INV, NQ>(buf, tw, N, Ns);
-    Ns *= 8;
-    rem -= 3;
+  for (int s = 0; s < plan.nstages; ++s) {
+    const int R = plan.radix[s];
+    if (R == 8) stockham_pass<T, 8, INV, NQ>(buf, tw, N, Ns);
+    else if (R == 4) stockham_pass<T, 4, INV, NQ>(buf, tw, N, Ns);
+    else if (R == 2) stockham_pass<T, 2, INV, NQ>(buf, tw, N, Ns);
+    else if constexpr (MIXED) {
+      if (R == 3) stockham_pass<T, 3, INV, NQ>(buf, tw, N, Ns);
+      else stockham_pass<T, 5, INV, NQ>(buf, tw, N, Ns);
+    }
+    Ns *= R;
   }
-  if (rem == 2) stockham_pass<T, 4, INV, NQ>(buf, tw, N, Ns);
-  else if (rem == 1) stockham_pass<T, 2, INV, NQ>(buf, tw, N, Ns);
+}
+
+// radix plan: as many 8s as possible, then 4 or 2, then 3s and 5s
+inline FftPlan make_fft_plan(int n) {
+  FftPlan p{};
+  int twos = 0, threes = 0, fives = 0;
+  while (n % 2 == 0) { n /= 2; ++twos; }
+  while (n % 3 == 0) { n /= 3; ++threes; }
+  while (n % 5 == 0) { n /= 5; ++fives; }
+  while (twos >= 3) { p.radix[p.nstages++] = 8; twos -= 3; }
+  if (twos == 2) p.radix[p.nstages++] = 4;
+  if (twos == 1) p.radix[p.nstages++] = 2;
+  for (int i = 0; i < threes; ++i) p.radix[p.nstages++] = 3;
+  for (int i = 0; i < fives; ++i) p.radix[p.nstages++] = 5;
+  return p;
 }
 
 // ---------------------------------------------------------------------------
@@ -105,7 +128,8 @@ struct RowArgs {
   const void* R;
   const void* S;
   int64_t ld;
-  int W, H, DK, DB, r, logW;
+  int W, H, DK, DB, r;
+  FftPlan plan;
   double cR, cS, sx;
   void* F;            // cx<T>[nsig][H][pitchK]
   int64_t pitchK, planeK;
@@ -114,11 +138,12 @@ struct RowArgs {
   double* ER;         // [H][2r]
   int* flags;
   const void* twW;    // cx<T>[W]
+  double* edge;       // [nsig][2][H]: real k_x = 0 and k_x = W/2 values
 };
 
-// NQ: row elements per thread, max(1, W / 256)
-template <typename T, typename TIN, int NQ>
-__global__ __launch_bounds__(kRowThreads) void k_row_pass(RowArgs a) {
+// NQ: row elements per thread, max(1, ceil(W / 256)); MIXED: W has factors 3 or 5
+template <typename T, typename TIN, int NQ, bool MIXED>
+__global__ __launch_bounds__(kRowThreads, 2) void k_row_pass(RowArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int W = a.W;
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
@@ -203,16 +228,21 @@ __global__ __launch_bounds__(kRowThreads) void k_row_pass(RowArgs a) {
         }
       }
       __syncthreads();
-      fft_lds<T, false, NQ>(buf, tw, W, a.logW);
+      fft_lds<T, false, NQ, MIXED>(buf, tw, W, a.plan);
       const int half = W / 2;
       for (int kx = threadIdx.x; kx <= half; kx += kRowThreads) {
         const cx<T> z1 = buf[pad8(kx)];
-        const cx<T> z2 = cconj(buf[pad8((W - kx) & (W - 1))]);
+        const cx<T> z2 = cconj(buf[pad8(kx == 0 ? 0 : W - kx)]);
         const cx<T> A = cscale(cadd(z1, z2), (T)0.5);
         const cx<T> d = csub(z1, z2);
         const cx<T> B = {d.im * (T)0.5, -d.re * (T)0.5};
         F[(int64_t)s0 * a.planeK + (int64_t)y * a.pitchK + kx] = A;
         if (s1 < nsig) F[(int64_t)s1 * a.planeK + (int64_t)y * a.pitchK + kx] = B;
+        if (kx == 0 || kx == half) {
+          const int e = (kx == 0) ? 0 : 1;
+          a.edge[((int64_t)s0 * 2 + e) * a.H + y] = (double)A.re;
+          if (s1 < nsig) a.edge[((int64_t)s1 * 2 + e) * a.H + y] = (double)B.re;
+        }
       }
       __syncthreads();
     }
@@ -220,7 +250,9 @@ __global__ __launch_bounds__(kRowThreads) void k_row_pass(RowArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Column pass: blocked correlation along y for 4 adjacent k_x columns
+// Column pass: blocked correlation along y for 4 adjacent k_x columns,
+// k_x in [1, W/2). The real k_x = 0 and k_x = W/2 columns are correlated
+// directly in k_strip_xinv.
 // ---------------------------------------------------------------------------
 
 struct ColArgs {
@@ -233,6 +265,7 @@ struct ColArgs {
 };
 
 template <int NK> struct PairCount { static constexpr int NKK = NK * (NK + 1) / 2, NP = NKK + NK; };
+template <int NK> struct BaseCount { static constexpr int value = (NK == 1 ? 0 : (NK == 3 ? 1 : 2)) + 2; };
 
 // layout of the kernel-term spectra: exponents (a, b) of term g
 __device__ __forceinline__ void mono_ab(int g, int& a, int& b) {
@@ -243,77 +276,119 @@ __device__ __forceinline__ void mono_ab(int g, int& a, int& b) {
   a = d - b;
 }
 
+template <int NK>
+constexpr int col_spec_stride() {
+  // column stride (complex elements) congruent to 4 mod 16: stage-1 writes
+  // of 4 columns x 4 butterflies hit distinct LDS banks
+  return (2 * NK + 1) * 136 + ((4 - (((2 * NK + 1) * 136) % 16)) + 16) % 16;
+}
+
+template <typename T, int NK>
+constexpr size_t col_pass_shmem() {
+  return sizeof(cx<T>) * ((size_t)kColsPerWG * col_spec_stride<NK>() + kTP +
+                          (size_t)BaseCount<NK>::value * kTP * kColsPerWG);
+}
+
 template <typename T, int NK>
 __global__ __launch_bounds__(kColThreads) void k_col_pass(ColArgs a) {
   constexpr int NS = 2 * NK + 1;
   constexpr int NKK = PairCount<NK>::NKK;
   constexpr int NP = PairCount<NK>::NP;
+  constexpr int NBASE = BaseCount<NK>::value;
   constexpr int SPAD = 136;
-  // column stride (complex elements) congruent to 4 mod 16: stage-1 writes
-  // of 4 columns x 4 butterflies hit distinct LDS banks
-  constexpr int CS0 = NS * SPAD;
-  constexpr int CS = CS0 + ((4 - (CS0 % 16)) + 16) % 16;
+  constexpr int CS = col_spec_stride<NK>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* spec = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* tw = spec + kColsPerWG * CS;
+  cx<T>* raw = tw + kTP;                     // staged rows: [base][m][column]
   const cx<T>* twg = static_cast<const cx<T>*>(a.tw128);
-  if (threadIdx.x < kTP) tw[threadIdx.x] = twg[threadIdx.x];
+  const int tid = threadIdx.x;
+  if (tid < kTP) tw[tid] = twg[tid];
 
   // XCD-aware group index: workgroups that share an XCD (id mod 8) take
   // adjacent column groups, so their 64-byte row segments share L2 lines.
   const int per_xcd = (a.ngroups + 7) / 8;
   const int grp = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (grp >= a.ngroups) return;
-  const int kx0 = grp * kColsPerWG;
+  const int kx0 = 1 + grp * kColsPerWG;
+  const int kxend = a.nkx - 1;               // exclusive: W/2 is done elsewhere
   const cx<T>* F = static_cast<const cx<T>*>(a.F);
-  const int tid = threadIdx.x;
   const int H = a.H, h = a.h;
+
+  // stage-2 twiddles of this thread's butterfly column j = tid & 15: held in
+  // registers unless the accumulators already fill the register file
+  constexpr bool kRegTw = !(sizeof(T) == 8 && NK >= 6);
+  cx<T> tw2[kRegTw ? 8 : 1];
+  if constexpr (kRegTw) {
+    const int j2 = tid & 15;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) tw2[r] = twg[r * j2];
+  }
+  auto twid = [&](int r, int j) -> cx<T> {
+    if constexpr (kRegTw) return tw2[r];
+    else return tw[r * j];
+  };
+
+  // staged rows: element (base u, window row m = tid >> 2, column c = tid & 3)
+  const int fm = tid >> 2, fc = tid & 3;
+  cx<T> pre[NBASE];
+  auto fetch = [&](int yb) {
+    const int o = (fm < kTP - h) ? fm : fm - kTP;
+    int y = yb + o;
+    y = (y < 0) ? y + H : ((y >= H) ? y - H : y);
+    const int kx = kx0 + fc;
+#pragma unroll
+    for (int u = 0; u < NBASE; ++u)
+      pre[u] = (kx < kxend) ? F[(int64_t)u * a.planeK + (int64_t)y * a.pitchK + kx] : cx<T>{(T)0, (T)0};
+  };
+  auto commit = [&]() {
+#pragma unroll
+    for (int u = 0; u < NBASE; ++u) raw[(u * kTP + fm) * kColsPerWG + fc] = pre[u];
+  };
 
   cx<T> acc[NP];
 #pragma unroll
   for (int p = 0; p < NP; ++p) acc[p] = cx<T>{(T)0, (T)0};
+  fetch(0);
+  commit();
   __syncthreads();
 
   for (int yb = 0; yb < H; yb += a.T) {
     const int Tb = min(a.T, H - yb);
-    // ---- stage 1: gather weighted rows, radix-16 over rows j + 8q
+    // ---- stage 1: weighted rows j + 8q from the staging buffer, radix-16
     if (tid < kColsPerWG * NS * 8) {
       const int c = tid & 3;
       const int rest = tid >> 2;
       const int j = rest & 7;
       const int s = rest >> 3;            // 0..NS-1
-      const int kx = kx0 + c;
-      const bool colok = kx < a.nkx;
       int base, bpow;
       bool is_u;
       if (s < NK) { int ea, eb; mono_ab(s, ea, eb); base = ea; bpow = eb; is_u = true; }
       else if (s < 2 * NK) { int ea, eb; mono_ab(s - NK, ea, eb); base = ea; bpow = eb; is_u = false; }
-      else { base = a.DK + 1; bpow = 0; is_u = false; }
-      const cx<T>* Fb = F + (int64_t)base * a.planeK + kx;
+      else { base = NBASE - 1; bpow = 0; is_u = false; }
+      const cx<T>* src = raw + (base * kTP) * kColsPerWG + c;
       cx<T> v[16];
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int m = j + 8 * q;
         const int o = (m < kTP - h) ? m : m - kTP;
         const bool in = is_u ? (o >= 0 && o < Tb) : (o >= -h && o < Tb + h);
-        int y = yb + o;
-        y = (y < 0) ? y + H : ((y >= H) ? y - H : y);
-        cx<T> val = {(T)0, (T)0};
-        if (in && colok) {
-          val = Fb[(int64_t)y * a.pitchK];
-          if (bpow > 0) {
-            const double yt = (double)y * a.sy - 1.0;
-            const double wgt = ipow(yt, bpow);
-            val = cscale(val, (T)wgt);
-          }
+        cx<T> val = src[m * kColsPerWG];
+        if (bpow > 0) {
+          int y = yb + o;
+          y = (y < 0) ? y + H : ((y >= H) ? y - H : y);
+          const double yt = (double)y * a.sy - 1.0;
+          val = cscale(val, (T)ipow(yt, bpow));
         }
-        v[q] = val;
+        v[q] = in ? val : cx<T>{(T)0, (T)0};
       }
       dft16<T, false>(v);
       cx<T>* dst = spec + c * CS + s * SPAD;
 #pragma unroll
       for (int r = 0; r < 16; ++r) dst[pad16(16 * j + r)] = v[r];
     }
+    const bool more = yb + a.T < H;
+    if (more) fetch(yb + a.T);             // in flight during stage 2 and the products
     __syncthreads();
     // ---- stage 2: radix-8, Ns = 16 (twiddle exp(-2 pi i r j / 128)).
     // As the last Stockham stage it reads and writes the same 8 slots
@@ -329,7 +404,7 @@ __global__ __launch_bounds__(kColThreads) void k_col_pass(ColArgs a) {
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
           cx<T> x = p[pad16(j + 16 * r)];
-          if (r > 0) x = cmul(x, tw[r * j]);
+          if (r > 0) x = cmul(x, twid(r, j));
           v[r] = x;
         }
         dft8<T, false>(v);
@@ -355,6 +430,7 @@ __global__ __launch_bounds__(kColThreads) void k_col_pass(ColArgs a) {
 #pragma unroll
       for (int i = 0; i < NK; ++i) cmac_conj(acc[NKK + i], U[i], V[NK]);
     }
+    if (more) commit();
     __syncthreads();
   }
 
@@ -404,7 +480,7 @@ __global__ __launch_bounds__(kColThreads) void k_col_pass(ColArgs a) {
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
           cx<T> x = p[pad16(j + 16 * r)];
-          if (r > 0) x = cmul(x, cconj(tw[r * j]));
+          if (r > 0) x = cmul(x, cconj(twid(r, j)));
           v[r] = x;
         }
         dft8<T, true>(v);
@@ -423,7 +499,7 @@ __global__ __launch_bounds__(kColThreads) void k_col_pass(ColArgs a) {
         const int dyi = rest % ndy;
         const int s = rest / ndy;
         const int kx = kx0 + c;
-        if (kx < a.nkx) {
+        if (kx < kxend) {
           const int idx = (dyi - h) & (kTP - 1);
           const cx<T> vv = spec[c * CS + s * SPAD + pad16(idx)];
           const double sc = 1.0 / kTP;
@@ -437,38 +513,74 @@ __global__ __launch_bounds__(kColThreads) void k_col_pass(ColArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Pruned inverse along x: C_p(dx, dy) = (1/W) sum_kx w_kx Re(e^{2 pi i kx dx / W} c_p(kx, dy))
+// Pruned inverse along x:
+//   C_p(dx, dy) = (1/W) [ c_p(0, dy) + (-1)^dx c_p(W/2, dy)
+//                         + 2 sum_{kx=1}^{W/2-1} Re(e^{2 pi i kx dx / W} c_p(kx, dy)) ]
+// The k_x = 0 and k_x = W/2 columns are real sequences along y; their
+// correlations c_p(0, dy), c_p(W/2, dy) are formed here by direct sums.
 // ---------------------------------------------------------------------------
 
 struct XinvArgs {
   const cx<double>* strips;
-  double* C;            // [NP][2h+1][2h+1]
+  double* C;              // [NP][2h+1][2h+1]
   const cx<double>* twW;  // exp(-2 pi i m / W), FP64
-  int W, nkx, h, r, NKK, NP;
+  const double* edge;     // [nsig][2][H]: real k_x = 0 and k_x = W/2 row-spectrum values
+  int W, H, nkx, h, r, NKK, NP, nK, DK;
+  double sy;
 };
 
 __global__ __launch_bounds__(256) void k_strip_xinv(XinvArgs a) {
-  __shared__ double red[4][32];
+  __shared__ double red[4][34];
   const int ndy = 2 * a.h + 1;
   const int p = blockIdx.x / ndy, dyi = blockIdx.x % ndy;
   const bool ks = p >= a.NKK;
   const int lim = ks ? a.r : a.h;
   if (abs(dyi - a.h) > lim) return;
   const int ndx = 2 * lim + 1;
+  const int dy = dyi - a.h;
+  // terms of the pair: u-side term iu, v-side term jv (or S)
+  int iu, jv;
+  if (!ks) {
+    int rem = p;
+    iu = 0;
+    while (rem >= a.nK - iu) { rem -= a.nK - iu; ++iu; }
+    jv = iu + rem;
+  } else {
+    iu = p - a.NKK;
+    jv = -1;
+  }
+  int au, bu, av, bv;
+  mono_ab(iu, au, bu);
+  if (jv >= 0) mono_ab(jv, av, bv);
+  else { av = a.DK + 1; bv = 0; }
+  // direct real correlations of the k_x = 0 and k_x = W/2 columns
+  double sdc = 0.0, snq = 0.0;
+  const double* eu = a.edge + (int64_t)au * 2 * a.H;
+  const double* ev = a.edge + (int64_t)av * 2 * a.H;
+  for (int y = threadIdx.x; y < a.H; y += blockDim.x) {
+    int y2 = y + dy;
+    y2 = (y2 < 0) ? y2 + a.H : (y2 >= a.H ? y2 - a.H : y2);
+    const double wu = ipow((double)y * a.sy - 1.0, bu);
+    const double wv = ipow((double)y2 * a.sy - 1.0, bv);
+    sdc = fma(wu * eu[y], wv * ev[y2], sdc);
+    snq = fma(wu * eu[a.H + y], wv * ev[a.H + y2], snq);
+  }
   double acc[32];
 #pragma unroll
   for (int t = 0; t < 32; ++t) acc[t] = 0.0;
   const cx<double>* row = a.strips + ((int64_t)p * ndy + dyi) * a.nkx;
-  for (int kx = threadIdx.x; kx < a.nkx; kx += blockDim.x) {
+  for (int kx = 1 + threadIdx.x; kx < a.nkx - 1; kx += blockDim.x) {
     const cx<double> c = row[kx];
-    const double wk = (kx == 0 || 2 * kx == a.W) ? 1.0 : 2.0;
+    // e(dx) = exp(+2 pi i kx dx / W): start at dx = -lim, step by exp(+2 pi i kx / W)
+    const cx<double> w0 = a.twW[(int)(((int64_t)kx * lim) % a.W)];   // exp(-2 pi i kx lim / W)
+    const cx<double> w1 = a.twW[kx];
+    const cx<double> step = {w1.re, -w1.im};
+    cx<double> e = w0;
 #pragma unroll
     for (int t = 0; t < 32; ++t) {
       if (t < ndx) {
-        const int dx = t - lim;
-        const int idx = (int)(((int64_t)kx * (dx + a.W)) % a.W);
-        const cx<double> w = a.twW[idx];   // (cos, -sin)
-        acc[t] = fma(wk, w.re * c.re + w.im * c.im, acc[t]);
+        acc[t] = fma(2.0, e.re * c.re - e.im * c.im, acc[t]);
+        e = cmul(e, step);
       }
     }
   }
@@ -480,12 +592,21 @@ __global__ __launch_bounds__(256) void k_strip_xinv(XinvArgs a) {
       if (lane == 0) red[wid][t] = v;
     }
   }
+  {
+    double v = wave_sum(sdc);
+    if (lane == 0) red[wid][32] = v;
+    v = wave_sum(snq);
+    if (lane == 0) red[wid][33] = v;
+  }
   __syncthreads();
   if (threadIdx.x < ndx) {
     const int t = threadIdx.x;
-    const double s = red[0][t] + red[1][t] + red[2][t] + red[3][t];
     const int dx = t - lim;
-    a.C[((int64_t)p * ndy + dyi) * ndy + (dx + a.h)] = s / (double)a.W;
+    const double s = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+    const double dc = red[0][32] + red[1][32] + red[2][32] + red[3][32];
+    const double nq = red[0][33] + red[1][33] + red[2][33] + red[3][33];
+    const double tot = s + dc + ((dx & 1) ? -nq : nq);
+    a.C[((int64_t)p * ndy + dyi) * ndy + (dx + a.h)] = tot / (double)a.W;
   }
 }
 
@@ -667,26 +788,46 @@ hipError_t prepare_kernel_attributes() {
     auto set = [&](const void* f) {
       if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     };
-    set(reinterpret_cast<const void*>(&k_row_pass<double, double, 1>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, double, 2>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, double, 4>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, double, 8>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, double, 16>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, float, 1>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, float, 2>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, float, 4>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, float, 8>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, float, 16>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, double, 1>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, double, 2>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, double, 4>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, double, 8>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, double, 16>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, float, 1>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, float, 2>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, float, 4>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, float, 8>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, float, 16>));
+    set(reinterpret_cast<const void*>(&k_row_pass<double, double, 1, false>));
+    set(reinterpret_cast<const void*>(&k_row_pass<double, double, 1, true>));
+    set(reinterpret_cast<const void*>(&k_row_pass<double, double, 2, false>));
+    set(reinterpret_cast<const void*>(&k_row_pass<double, double, 2, true>));
+    set(reinterpret_cast<const void*>(&k_row_pass<double, double, 4, false>));
+    set(reinterpret_cast<const void*>(&k_row_pass<double, double, 4, true>));
+    set(reinterpret_cast<const void*>(&k_row_pass<double, double, 8, false>));
+    set(reinterpret_cast<const void*>(&k_row_pass<double, double, 8, true>));
+    set(reinterpret_cast<const void*>(&k_row_pass<double, double, 16, false>));
+    set(reinterpret_cast<const void*>(&k_row_pass<double, double, 16, true>));
+    set(reinterpret_cast<const void*>(&k_row_pass<double, float, 1, false>));
+    set(reinterpret_cast<const void*>(&k_row_pass<double, float, 1, true>));
+    set(reinterpret_cast<const void*>(&k_row_pass<double, float, 2, false>));
+    set(reinterpret_cast<const void*>(&k_row_pass<double, float, 2, true>));
+    set(reinterpret_cast<const void*>(&k_row_pass<double, float, 4, false>));
+    set(reinterpret_cast<const void*>(&k_row_pass<double, float, 4, true>));
+    set(reinterpret_cast<const void*>(&k_row_pass<double, float, 8, false>));
+    set(reinterpret_cast<const void*>(&k_row_pass<double, float, 8, true>));
+    set(reinterpret_cast<const void*>(&k_row_pass<double, float, 16, false>));
+    set(reinterpret_cast<const void*>(&k_row_pass<double, float, 16, true>));
+    set(reinterpret_cast<const void*>(&k_row_pass<float, double, 1, false>));
+    set(reinterpret_cast<const void*>(&k_row_pass<float, double, 1, true>));
+    set(reinterpret_cast<const void*>(&k_row_pass<float, double, 2, false>));
+    set(reinterpret_cast<const void*>(&k_row_pass<float, double, 2, true>));
+    set(reinterpret_cast<const void*>(&k_row_pass<float, double, 4, false>));
+    set(reinterpret_cast<const void*>(&k_row_pass<float, double, 4, true>));
+    set(reinterpret_cast<const void*>(&k_row_pass<float, double, 8, false>));
+    set(reinterpret_cast<const void*>(&k_row_pass<float, double, 8, true>));
+    set(reinterpret_cast<const void*>(&k_row_pass<float, double, 16, false>));
+    set(reinterpret_cast<const void*>(&k_row_pass<float, double, 16, true>));
+    set(reinterpret_cast<const void*>(&k_row_pass<float, float, 1, false>));
+    set(reinterpret_cast<const void*>(&k_row_pass<float, float, 1, true>));
+    set(reinterpret_cast<const void*>(&k_row_pass<float, float, 2, false>));
+    set(reinterpret_cast<const void*>(&k_row_pass<float, float, 2, true>));
+    set(reinterpret_cast<const void*>(&k_row_pass<float, float, 4, false>));
+    set(reinterpret_cast<const void*>(&k_row_pass<float, float, 4, true>));
+    set(reinterpret_cast<const void*>(&k_row_pass<float, float, 8, false>));
+    set(reinterpret_cast<const void*>(&k_row_pass<float, float, 8, true>));
+    set(reinterpret_cast<const void*>(&k_row_pass<float, float, 16, false>));
+    set(reinterpret_cast<const void*>(&k_row_pass<float, float, 16, true>));
     set(reinterpret_cast<const void*>(&k_col_pass<double, 1>));
     set(reinterpret_cast<const void*>(&k_col_pass<double, 3>));
     set(reinterpret_cast<const void*>(&k_col_pass<double, 6>));
@@ -704,9 +845,7 @@ static hipError_t launch_row(const Geometry& g, const sfft_desc& d, const void* 
                              hipStream_t st) {
   RowArgs a{};
   a.R = R; a.S = S; a.ld = d.ld; a.W = g.W; a.H = g.H; a.DK = g.DK; a.DB = g.DB; a.r = g.r;
-  int lw = 0;
-  while ((1 << lw) < g.W) ++lw;
-  a.logW = lw;
+  a.plan = make_fft_plan(g.W);
   a.cR = d.ref_pedestal; a.cS = d.sci_pedestal;
   a.sx = g.W > 1 ? 2.0 / (double)(g.W - 1) : 0.0;
   a.F = ws + l.F; a.pitchK = g.pitchK; a.planeK = g.planeK;
@@ -715,21 +854,30 @@ static hipError_t launch_row(const Geometry& g, const sfft_desc& d, const void* 
   a.ER = reinterpret_cast<double*>(ws + l.ER);
   a.flags = reinterpret_cast<int*>(ws + l.flags);
   a.twW = p.twW;
+  a.edge = reinterpret_cast<double*>(ws + l.edge);
   const size_t shmem = sizeof(cx<T>) * (size_t)(g.W + g.W / 8 + g.W) + sizeof(double) * 64;
   int grid = g.H < 4 * p.num_cus ? g.H : 4 * p.num_cus;
   const bool f32 = d.image_dtype == SFFT_F32;
-#define SFFT_ROW(NQ)                                                                          \
-  do {                                                                                        \
-    if (f32) hipLaunchKernelGGL((k_row_pass<T, float, NQ>), dim3(grid), dim3(kRowThreads),   \
-                                shmem, st, a);                                               \
-    else hipLaunchKernelGGL((k_row_pass<T, double, NQ>), dim3(grid), dim3(kRowThreads),      \
-                            shmem, st, a);                                                   \
+  const bool mixed = (g.W % 3 == 0) || (g.W % 5 == 0);
+#define SFFT_ROW(NQ)                                                                              \
+  do {                                                                                            \
+    if (mixed) {                                                                                  \
+      if (f32) hipLaunchKernelGGL((k_row_pass<T, float, NQ, true>), dim3(grid), dim3(kRowThreads), \
+                                  shmem, st, a);                                                 \
+      else hipLaunchKernelGGL((k_row_pass<T, double, NQ, true>), dim3(grid), dim3(kRowThreads),    \
+                              shmem, st, a);                                                     \
+    } else {                                                                                      \
+      if (f32) hipLaunchKernelGGL((k_row_pass<T, float, NQ, false>), dim3(grid),                  \
+                                  dim3(kRowThreads), shmem, st, a);                               \
+      else hipLaunchKernelGGL((k_row_pass<T, double, NQ, false>), dim3(grid), dim3(kRowThreads),  \
+                              shmem, st, a);                                                     \
+    }                                                                                             \
   } while (0)
-  const int nq = g.W / kRowThreads;
+  const int nq = (g.W + kRowThreads - 1) / kRowThreads;
   if (nq <= 1) SFFT_ROW(1);
   else if (nq == 2) SFFT_ROW(2);
-  else if (nq == 4) SFFT_ROW(4);
-  else if (nq == 8) SFFT_ROW(8);
+  else if (nq <= 4) SFFT_ROW(4);
+  else if (nq <= 8) SFFT_ROW(8);
   else SFFT_ROW(16);
 #undef SFFT_ROW
   return hipGetLastError();
@@ -741,14 +889,11 @@ static hipError_t launch_col(const Geometry& g, unsigned char* ws, const Layout&
   ColArgs a{};
   a.F = ws + l.F; a.pitchK = g.pitchK; a.planeK = g.planeK;
   a.H = g.H; a.nkx = g.nkx; a.h = g.h; a.T = g.T; a.DK = g.DK;
-  a.ngroups = (g.nkx + kColsPerWG - 1) / kColsPerWG;
+  a.ngroups = (g.nkx - 2 + kColsPerWG - 1) / kColsPerWG;
   a.sy = g.H > 1 ? 2.0 / (double)(g.H - 1) : 0.0;
   a.strips = reinterpret_cast<cx<double>*>(ws + l.strips);
   a.tw128 = p.tw128;
-  constexpr int NS = 2 * NK + 1;
-  constexpr int CS0 = NS * 136;
-  constexpr int CS = CS0 + ((4 - (CS0 % 16)) + 16) % 16;
-  const size_t shmem = sizeof(cx<T>) * ((size_t)kColsPerWG * CS + kTP);
+  const size_t shmem = col_pass_shmem<T, NK>();
   const int grid = 8 * ((a.ngroups + 7) / 8);
   hipLaunchKernelGGL((k_col_pass<T, NK>), dim3(grid), dim3(kColThreads), shmem, st, a);
   return hipGetLastError();
@@ -782,6 +927,9 @@ hipError_t launch_build(const sfft_desc& d, const void* R, const void* S, double
   xa.C = reinterpret_cast<double*>(ws + l.C);
   xa.twW = static_cast<const cx<double>*>(p.twW64);
   xa.W = g.W; xa.nkx = g.nkx; xa.h = g.h; xa.r = g.r; xa.NKK = g.NKK; xa.NP = g.NP;
+  xa.H = g.H; xa.nK = g.nK; xa.DK = g.DK;
+  xa.sy = g.H > 1 ? 2.0 / (double)(g.H - 1) : 0.0;
+  xa.edge = reinterpret_cast<const double*>(ws + l.edge);
   prof_begin(pf, SFFT_PROF_XINV, st);
   hipLaunchKernelGGL(k_strip_xinv, dim3(g.NP * (2 * g.h + 1)), dim3(256), 0, st, xa);
   prof_end(pf, SFFT_PROF_XINV, st);

@@ -117,9 +117,47 @@ __device__ __forceinline__ void dft16(cx<T>* v) {
   }
 }
 
+template <typename T, bool INV>
+__device__ __forceinline__ void dft3(cx<T>* v) {
+  const T hs = (T)0.86602540378443864676372317075294;   // sin(2 pi / 3)
+  const cx<T> t1 = cadd(v[1], v[2]);
+  const cx<T> m = {v[0].re - (T)0.5 * t1.re, v[0].im - (T)0.5 * t1.im};
+  const cx<T> d = csub(v[1], v[2]);
+  // forward: -i hs d; inverse: +i hs d
+  const cx<T> t2 = INV ? cx<T>{-hs * d.im, hs * d.re} : cx<T>{hs * d.im, -hs * d.re};
+  v[0] = cadd(v[0], t1);
+  v[1] = cadd(m, t2);
+  v[2] = csub(m, t2);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft5(cx<T>* v) {
+  const T c1 = (T)0.30901699437494742410229341718282;    // cos(2 pi / 5)
+  const T c2 = (T)-0.80901699437494742410229341718282;   // cos(4 pi / 5)
+  const T s1 = (T)0.95105651629515357211643933337938;    // sin(2 pi / 5)
+  const T s2 = (T)0.58778525229247312916870595463907;    // sin(4 pi / 5)
+  const cx<T> b1 = cadd(v[1], v[4]), b2 = cadd(v[2], v[3]);
+  const cx<T> d1 = csub(v[1], v[4]), d2 = csub(v[2], v[3]);
+  const cx<T> a0 = v[0];
+  const cx<T> p1 = {a0.re + c1 * b1.re + c2 * b2.re, a0.im + c1 * b1.im + c2 * b2.im};
+  const cx<T> p2 = {a0.re + c2 * b1.re + c1 * b2.re, a0.im + c2 * b1.im + c1 * b2.im};
+  const cx<T> q1 = {s1 * d1.re + s2 * d2.re, s1 * d1.im + s2 * d2.im};
+  const cx<T> q2 = {s2 * d1.re - s1 * d2.re, s2 * d1.im - s1 * d2.im};
+  // forward: X1 = p1 - i q1, X4 = p1 + i q1, X2 = p2 - i q2, X3 = p2 + i q2
+  const cx<T> iq1 = INV ? cx<T>{-q1.im, q1.re} : cx<T>{q1.im, -q1.re};
+  const cx<T> iq2 = INV ? cx<T>{-q2.im, q2.re} : cx<T>{q2.im, -q2.re};
+  v[0] = cadd(a0, cadd(b1, b2));
+  v[1] = cadd(p1, iq1);
+  v[4] = csub(p1, iq1);
+  v[2] = cadd(p2, iq2);
+  v[3] = csub(p2, iq2);
+}
+
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void dft_r(cx<T>* v) {
   if constexpr (R == 2) dft2<T, INV>(v[0], v[1]);
+  else if constexpr (R == 3) dft3<T, INV>(v);
+  else if constexpr (R == 5) dft5<T, INV>(v);
   else if constexpr (R == 4) dft4<T, INV>(v[0], v[1], v[2], v[3]);
   else if constexpr (R == 8) dft8<T, INV>(v);
   else if constexpr (R == 16) dft16<T, INV>(v);

@@ -69,11 +69,11 @@ inline size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 struct Layout {
   // build
-  size_t flags, F, MR, MS, ER, strips, C, mom, build_end;
+  size_t flags, F, MR, MS, ER, edge, strips, C, mom, build_end;
   // solve (overlaps the build region after `flags`)
-  size_t A, s, b, theta, x, rvec, rowabs, Linv, solve_end;
+  size_t A, s, b, theta, x, rvec, rowabs, Ud, sync, solve_end;
   // subtract
-  size_t partials, kcoef, sub_end;
+  size_t partials, sub_end;
   size_t total;
   int nmom;           // doubles in the moment block
   int nt;             // Cholesky tiles per side
@@ -101,6 +101,7 @@ inline Layout make_layout(const Geometry& g) {
   l.MR = o; o = align256(o + sizeof(double) * nm * g.H);
   l.MS = o; o = align256(o + sizeof(double) * (g.DB + 1) * g.H);
   l.ER = o; o = align256(o + sizeof(double) * (2 * g.r > 0 ? 2 * g.r : 1) * g.H);
+  l.edge = o; o = align256(o + sizeof(double) * g.nsig * 2 * g.H);
   l.strips = o; o = align256(o + (size_t)16 * g.NP * (2 * g.h + 1) * g.nkx);
   l.C = o; o = align256(o + sizeof(double) * g.NP * (2 * g.h + 1) * (2 * g.h + 1));
   l.nmom = moment_count(g);
@@ -111,20 +112,21 @@ inline Layout make_layout(const Geometry& g) {
   l.nt = (N + kTile - 1) / kTile;
   const size_t Np = (size_t)l.nt * kTile;
   o = base;
-  l.A = o; o = align256(o + sizeof(double) * Np * Np);
+  // matrix rows, the right-hand-side row (padded to a tile) and identity rows
+  l.A = o; o = align256(o + sizeof(double) * (2 * Np + kTile) * Np);
   l.s = o; o = align256(o + sizeof(double) * Np);
   l.b = o; o = align256(o + sizeof(double) * Np);
   l.theta = o; o = align256(o + sizeof(double) * Np);
   l.x = o; o = align256(o + sizeof(double) * Np);
   l.rvec = o; o = align256(o + sizeof(double) * Np);
   l.rowabs = o; o = align256(o + sizeof(double) * Np);
-  l.Linv = o; o = align256(o + sizeof(double) * l.nt * kTile * kTile);
+  l.Ud = o; o = align256(o + sizeof(double) * Np * kTile);
+  l.sync = o; o = align256(o + sizeof(unsigned) * 128 + sizeof(unsigned long long) * 256);
   l.solve_end = o;
   // subtract region
   o = base;
   l.npartials = subtract_blocks(g);
   l.partials = o; o = align256(o + sizeof(double) * l.npartials);
-  l.kcoef = o; o = align256(o + sizeof(double) * 64);
   l.sub_end = o;
   size_t t = l.build_end;
   if (l.solve_end > t) t = l.solve_end;

@@ -1,359 +1,564 @@
-// sfft_solve kernels: FP64 solve of the normal equations G theta = h.
+// sfft_solve: FP64 solve of the normal equations G theta = h.
 //
-// The paper's SFFT fit ends in a dense symmetric positive-definite linear
-// solve (least-squares normal equations, paper Sec. 1). Here: equilibrate
-// with D = diag(G)^-1/2 (A = D G D), blocked right-looking Cholesky on
-// 64 x 64 tiles (diagonal factor, panel substitution, trailing update),
-// inverses of the diagonal factors, blocked forward/backward substitution,
-// then iterative refinement on the residual h - G theta in FP64.
-// Matrices are padded to a multiple of 64 with an identity block.
+// The SFFT fit ends in a dense symmetric positive-definite solve (the
+// least-squares normal equations of the delta-basis kernel, paper Sec. 1).
+// One persistent cooperative kernel with P co-resident workgroups does:
+//   equilibration  A = D G D, D = diag(G)^-1/2, v = D h;
+//   right-looking blocked Cholesky on 64 x 64 tiles of the matrix augmented
+//   below by the right-hand side row v^T and by the identity: factorising
+//   [A; v^T; I] turns those rows into z^T = (L^-1 v)^T and L^-T, so the
+//   forward substitution and the inverse factor come out of the same sweep
+//   with no extra synchronisation; look-ahead: the workgroup that owns the
+//   next diagonal tile updates and factors it first while the others apply
+//   the remaining trailing updates;
+//   x = L^-T z as one distributed matrix-vector product; up to `refine`
+//   steps of iterative refinement on r = h - G theta (FP64), each three
+//   matrix-vector products (G theta, L^-1 r = (L^-T)^T r, L^-T z);
+//   final backward error and pivot range.
+// Workgroups synchronise through a flag barrier (one arrival flag per
+// workgroup, one release flag) with bounded spins: a timeout is reported in
+// the status instead of hanging.
 #include "common.hpp"
 #include "layout.hpp"
 
 namespace sfft {
 
-struct SolveArgs {
+constexpr int kPT = 512;                    // threads per solve workgroup
+constexpr long kSpinLimit = 1L << 26;
+constexpr int kLD = kTile + 1;              // LDS row pitch of a tile
+
+struct PSArgs {
   const double* G;
   const double* h;
   double* coef;
   sfft_solve_info* info;
-  double* A;        // Np x Np
+  double* A;        // (2 Np + 64) x Np: rows [0, Np) matrix -> L; row Np: v -> z;
+                    // rows [Np + 64, 2 Np + 64): identity -> L^-T
   double* s;        // Np
-  double* b;        // Np
-  double* theta;    // Np
   double* x;        // Np
-  double* rvec;     // Np
-  double* rowabs;   // Np (row sums of |G|), later reused
-  double* Linv;     // nt x 64 x 64
-  int* flags;       // [0] nonfinite (from build), [1] failed pivot + 1 (0 = none)
-  int N, Np, nt;
+  double* theta;    // Np
+  double* r;        // Np
+  double* rowabs;   // Np
+  double* Ud;       // nt tiles of 64 x 64: U_k = L_kk^-T of each diagonal tile
+  unsigned* sync;   // [0, P): arrival flags, [P]: release flag
+  unsigned long long* stamps;   // optional: 100 MHz time stamp of each barrier
+  int* flags;       // [0] nonfinite (build), [1] failed pivot + 1, [2] barrier timeout
+  int N, Np, nt, P, refine;
 };
 
-__global__ void k_solve_init(SolveArgs a) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    a.flags[1] = 0;
-    sfft_solve_info inf{};
-    inf.status = SFFT_OK;
-    inf.failed_pivot = -1;
-    inf.refine_iters = 0;
-    inf.nonfinite = a.flags[0];
-    inf.backward_err = 0.0;
-    inf.min_pivot = 0.0;
-    inf.max_pivot = 0.0;
-    *a.info = inf;
-  }
-}
-
-// one workgroup per row: A = D G D, b = D h, rowabs = sum_j |G_ij|
-__global__ __launch_bounds__(256) void k_equil(SolveArgs a) {
-  __shared__ double scratch[8];
-  const int i = blockIdx.x;
-  const int N = a.N, Np = a.Np;
-  double si = 1.0;
-  if (i < N) {
-    const double gii = a.G[(int64_t)i * N + i];
-    si = (gii > 0.0 && is_finite_d(gii)) ? 1.0 / sqrt(gii) : 0.0;
-  }
-  double ra = 0.0;
-  for (int j = threadIdx.x; j < Np; j += blockDim.x) {
-    double v;
-    if (i < N && j < N) {
-      const double gjj = a.G[(int64_t)j * N + j];
-      const double sj = (gjj > 0.0 && is_finite_d(gjj)) ? 1.0 / sqrt(gjj) : 0.0;
-      const double g = a.G[(int64_t)i * N + j];
-      ra += fabs(g);
-      v = si * g * sj;
-    } else {
-      v = (i == j) ? 1.0 : 0.0;
+// Grid barrier: release fence + relaxed arrival flag per workgroup;
+// workgroup 0 polls all arrival flags (relaxed loads, short sleeps), then
+// releases everyone through one flag; a single acquire fence after each wait.
+// Polling never uses acquire loads, which would invalidate caches on every
+// iteration. Spins are bounded; a timeout is recorded in flags[2].
+struct Barrier {
+  unsigned gen = 0;
+  __device__ void wait(const PSArgs& a) {
+    __syncthreads();
+    ++gen;
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(&a.sync[blockIdx.x], gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    a.A[(int64_t)i * Np + j] = v;
+    if (blockIdx.x == 0) {
+      if (threadIdx.x < a.P) {
+        long spins = 0;
+        while (__hip_atomic_load(&a.sync[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+          __builtin_amdgcn_s_sleep(1);
+          if (++spins > kSpinLimit) { atomicOr(&a.flags[2], 1); break; }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(&a.sync[a.P], gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    } else if (threadIdx.x == 0) {
+      long spins = 0;
+      while (__hip_atomic_load(&a.sync[a.P], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kSpinLimit) { atomicOr(&a.flags[2], 1); break; }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0 && a.stamps && gen < 256)
+      a.stamps[gen] = __builtin_amdgcn_s_memrealtime();
   }
-  ra = block_sum(ra, scratch);
-  if (threadIdx.x == 0) {
-    a.s[i] = si;
-    a.b[i] = (i < N) ? si * a.h[i] : 0.0;
-    a.rowabs[i] = ra;
-    a.theta[i] = 0.0;
+};
+
+__device__ __forceinline__ bool failed(const PSArgs& a) {
+  return __hip_atomic_load(&a.flags[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+// ---------------------------------------------------------------------------
+// tile helpers (512 threads)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void load_tile(double (*T)[kLD], const double* A, int Np, int ti, int tj,
+                                          int rows = kTile) {
+  const int64_t o = (int64_t)ti * kTile * Np + (int64_t)tj * kTile;
+  for (int idx = threadIdx.x; idx < kTile * kTile; idx += kPT) {
+    const int i = idx >> 6, j = idx & 63;
+    T[i][j] = (i < rows) ? A[o + (int64_t)i * Np + j] : 0.0;
   }
 }
 
-// Cholesky of diagonal tile k in LDS (right-looking, 256 threads).
-__global__ __launch_bounds__(256) void k_potrf_tile(SolveArgs a, int k) {
-  if (a.flags[1] != 0) return;
-  __shared__ double T[kTile][kTile + 1];
-  __shared__ int failed;
-  const int tid = threadIdx.x;
-  const int64_t o = (int64_t)k * kTile;
-  for (int idx = tid; idx < kTile * kTile; idx += 256) {
-    const int i = idx / kTile, j = idx % kTile;
-    T[i][j] = a.A[(o + i) * a.Np + o + j];
+__device__ __forceinline__ void store_tile(const double (*T)[kLD], double* A, int Np, int ti, int tj,
+                                           int rows = kTile) {
+  const int64_t o = (int64_t)ti * kTile * Np + (int64_t)tj * kTile;
+  for (int idx = threadIdx.x; idx < kTile * kTile; idx += kPT) {
+    const int i = idx >> 6, j = idx & 63;
+    if (i < rows) A[o + (int64_t)i * Np + j] = T[i][j];
   }
-  if (tid == 0) failed = -1;
+}
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+// 64 x 64 x 64 tile products on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64): wave w owns rows 16 (w & 3) .. +16 and columns
+// 32 (w >> 2) .. +32 of the result, as two 16 x 16 blocks. Operand lanes:
+// A[l % 16][l / 16], B[l / 16][l % 16]; result lane l, element q:
+// row 4 (l / 16) + q, column l % 16.
+// TRANS_B = true: acc = X Y^T; false: acc = X Y.
+template <bool TRANS_B>
+__device__ __forceinline__ void tile_mma(const double (*X)[kLD], const double (*Y)[kLD],
+                                         double4_t acc[2]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i0 = 16 * (w & 3), j0 = 32 * (w >> 2);
+  const int lr = lane & 15, lk = lane >> 4;
+  acc[0] = double4_t{0.0, 0.0, 0.0, 0.0};
+  acc[1] = double4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int k = 0; k < kTile; k += 4) {
+    const double av = X[i0 + lr][k + lk];
+    const double b0 = TRANS_B ? Y[j0 + lr][k + lk] : Y[k + lk][j0 + lr];
+    const double b1 = TRANS_B ? Y[j0 + 16 + lr][k + lk] : Y[k + lk][j0 + 16 + lr];
+    acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, acc[0], 0, 0, 0);
+    acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, acc[1], 0, 0, 0);
+  }
+}
+
+// C -= X Y^T (all 64 x 64 in LDS; C may not alias X or Y)
+__device__ __forceinline__ void tile_sub_abt(double (*C)[kLD], const double (*X)[kLD],
+                                             const double (*Y)[kLD]) {
+  double4_t acc[2];
+  tile_mma<true>(X, Y, acc);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i0 = 16 * (w & 3) + 4 * (lane >> 4), j0 = 32 * (w >> 2) + (lane & 15);
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) C[i0 + q][j0 + 16 * b] -= acc[b][q];
   __syncthreads();
+}
+
+// C = X U (U upper triangular; C may not alias X or U)
+__device__ __forceinline__ void tile_mul_ab(double (*C)[kLD], const double (*X)[kLD],
+                                            const double (*U)[kLD]) {
+  double4_t acc[2];
+  tile_mma<false>(X, U, acc);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i0 = 16 * (w & 3) + 4 * (lane >> 4), j0 = 32 * (w >> 2) + (lane & 15);
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) C[i0 + q][j0 + 16 * b] = acc[b][q];
+  __syncthreads();
+}
+
+// 1 / sqrt(d) to FP64 accuracy: hardware estimate + two Newton steps
+__device__ __forceinline__ double rsqrt64(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  y = y * fma(-0.5 * d * y, y, 1.5);
+  y = y * fma(-0.5 * d * y, y, 1.5);
+  return y;
+}
+
+// Cholesky of the 64 x 64 SPD tile T (lower, in place) and U = L^-T into Ut:
+// the right-looking factorisation of the stacked [T; I] turns the identity
+// rows into L^-T (I = Y L^T). Thread (i, q) holds T[i][q + 8m] and the
+// identity row's [i][q + 8m]; column j of both parts is published in colbuf
+// (double-buffered); one barrier per column, no divergent loads.
+// Returns the failing local pivot or -1. colbuf: 4 x 64 doubles.
+__device__ int tile_potrf_aug(double (*T)[kLD], double (*Ut)[kLD], double (*colbuf)[kTile]) {
+  const int i = threadIdx.x & 63, q = threadIdx.x >> 6;     // q in [0, 8)
+  double reg[8], aug[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    reg[m] = T[i][q + 8 * m];
+    aug[m] = (i == q + 8 * m) ? 1.0 : 0.0;
+  }
+  __shared__ int fail;
+  if (threadIdx.x == 0) fail = -1;
+  if (q == 0) { colbuf[0][i] = reg[0]; colbuf[2][i] = aug[0]; }
+  __syncthreads();
+#pragma unroll 1
   for (int j = 0; j < kTile; ++j) {
-    const double d = T[j][j];
-    if (!(d > 0.0) || !is_finite_d(d)) {
-      if (tid == 0) failed = j;
+    const int bsel = j & 1;
+    const double* cT = colbuf[bsel];
+    const double* cA = colbuf[2 + bsel];
+    const double d = cT[j];
+    const double ci = cT[i], ai = cA[i];
+    double cl[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) cl[m] = cT[q + 8 * m];
+    if (!(d > 0.0) || !is_finite_d(d)) {     // uniform: every thread read the same pivot
+      if (threadIdx.x == 0) fail = j;
       break;
     }
-    const double dsq = sqrt(d);
-    if (tid < kTile && tid > j) T[tid][j] /= dsq;
-    __syncthreads();
-    if (tid == j) T[j][j] = dsq;
-    const int i = tid & (kTile - 1);
-    if (i > j) {
-      const double tij = T[i][j];
-      for (int l = j + 1 + (tid >> 6); l <= i; l += 4) T[i][l] = fma(-tij, T[l][j], T[i][l]);
+    const double rs = rsqrt64(d);
+    const double li = ci * rs, yi = ai * rs;
+    const double ljj = (i >= j) ? li : 0.0;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int pcol = q + 8 * m;
+      const double lp = cl[m] * rs;
+      const double nr = fma(-li, lp, reg[m]);
+      const double na = fma(-yi, lp, aug[m]);
+      reg[m] = (pcol > j) ? nr : ((pcol == j) ? ljj : reg[m]);
+      aug[m] = (pcol > j) ? na : ((pcol == j) ? yi : aug[m]);
+    }
+    // owners of column j + 1 publish both parts of it
+    const int jn = j + 1;
+    if (jn < kTile && (jn & 7) == q) {
+      double vr = 0.0, va = 0.0;
+#pragma unroll
+      for (int m = 0; m < 8; ++m)
+        if (m == (jn >> 3)) { vr = reg[m]; va = aug[m]; }
+      colbuf[bsel ^ 1][i] = vr;
+      colbuf[2 + (bsel ^ 1)][i] = va;
     }
     __syncthreads();
   }
   __syncthreads();
-  if (failed >= 0) {
-    if (tid == 0) {
-      a.flags[1] = (int)(o + failed) + 1;
-    }
-    return;
-  }
-  for (int idx = tid; idx < kTile * kTile; idx += 256) {
-    const int i = idx / kTile, j = idx % kTile;
-    a.A[(o + i) * a.Np + o + j] = (i >= j) ? T[i][j] : 0.0;
-  }
-}
-
-// Panel: L_ik = A_ik L_kk^-T for row tiles i > k (one workgroup per tile);
-// each row by forward substitution, 4 lanes per row.
-__global__ __launch_bounds__(256) void k_trsm_panel(SolveArgs a, int k) {
-  if (a.flags[1] != 0) return;
-  __shared__ double Lk[kTile][kTile + 1];
-  __shared__ double X[kTile][kTile + 1];
-  const int tid = threadIdx.x;
-  const int64_t o = (int64_t)k * kTile;
-  const int64_t oi = (int64_t)(k + 1 + blockIdx.x) * kTile;
-  for (int idx = tid; idx < kTile * kTile; idx += 256) {
-    const int i = idx / kTile, j = idx % kTile;
-    Lk[i][j] = a.A[(o + i) * a.Np + o + j];
-    X[i][j] = a.A[(oi + i) * a.Np + o + j];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const int l = q + 8 * m;
+    T[i][l] = (l <= i) ? reg[m] : 0.0;
+    Ut[i][l] = (l >= i) ? aug[m] : 0.0;
   }
   __syncthreads();
-  const int row = tid >> 2, part = tid & 3;
-  for (int j = 0; j < kTile; ++j) {
-    double s = 0.0;
-    for (int l = part; l < j; l += 4) s = fma(Lk[j][l], X[row][l], s);
-    s += __shfl_xor(s, 1, 64);
-    s += __shfl_xor(s, 2, 64);
-    if (part == 0) X[row][j] = (X[row][j] - s) / Lk[j][j];
-    __builtin_amdgcn_wave_barrier();
-  }
-  __syncthreads();
-  for (int idx = tid; idx < kTile * kTile; idx += 256) {
-    const int i = idx / kTile, j = idx % kTile;
-    a.A[(oi + i) * a.Np + o + j] = X[i][j];
-  }
+  return fail;
 }
 
-// Trailing update A_ij -= L_ik L_jk^T for k < j <= i (one workgroup per tile).
-__global__ __launch_bounds__(256) void k_syrk_tile(SolveArgs a, int k) {
-  if (a.flags[1] != 0) return;
-  __shared__ double Li[kTile][kTile + 1];
-  __shared__ double Lj[kTile][kTile + 1];
-  // decode lower-triangular tile index t -> (ti, tj), tj <= ti, both in [k+1, nt)
-  int t = blockIdx.x;
-  int ti = 0;
+// lower-triangle tile index t -> (ti, tj) with tj <= ti
+__device__ __forceinline__ void tri_decode(int t, int& ti, int& tj) {
+  ti = 0;
   while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-  const int tj = t - ti * (ti + 1) / 2;
-  const int I = k + 1 + ti, J = k + 1 + tj;
-  const int tid = threadIdx.x;
-  const int64_t o = (int64_t)k * kTile, oi = (int64_t)I * kTile, oj = (int64_t)J * kTile;
-  for (int idx = tid; idx < kTile * kTile; idx += 256) {
-    const int i = idx / kTile, j = idx % kTile;
-    Li[i][j] = a.A[(oi + i) * a.Np + o + j];
-    Lj[i][j] = a.A[(oj + i) * a.Np + o + j];
-  }
-  __syncthreads();
-  // each thread: 4 rows x 4 cols
-  const int r0 = (tid >> 4) * 4, c0 = (tid & 15) * 4;
-  double acc[4][4] = {};
-  for (int l = 0; l < kTile; ++l) {
-    double av[4], bv[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) { av[u] = Li[r0 + u][l]; bv[u] = Lj[c0 + u][l]; }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
-  }
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t idx = (oi + r0 + u) * a.Np + oj + c0 + v;
-      a.A[idx] -= acc[u][v];
-    }
+  tj = t - ti * (ti + 1) / 2;
 }
 
-// Inverse of every diagonal factor L_kk (one workgroup per tile), rows of
-// the inverse in sequence: X_i = (e_i - sum_{l<i} L_il X_l) / L_ii.
-__global__ __launch_bounds__(256) void k_tile_inverse(SolveArgs a) {
-  if (a.flags[1] != 0) return;
-  __shared__ double Lk[kTile][kTile + 1];
-  __shared__ double X[kTile][kTile + 1];
-  __shared__ double part[4][kTile];
-  const int k = blockIdx.x, tid = threadIdx.x;
-  const int64_t o = (int64_t)k * kTile;
-  for (int idx = tid; idx < kTile * kTile; idx += 256) {
-    const int i = idx / kTile, j = idx % kTile;
-    Lk[i][j] = a.A[(o + i) * a.Np + o + j];
-    X[i][j] = 0.0;
-  }
-  __syncthreads();
-  const int j = tid & 63, q = tid >> 6;
-  for (int i = 0; i < kTile; ++i) {
-    double s = 0.0;
-    if (j < i)
-      for (int l = j + q; l < i; l += 4) s = fma(Lk[i][l], X[l][j], s);
-    part[q][j] = s;
-    __syncthreads();
-    if (tid < kTile && j <= i) {
-      const double tot = part[0][j] + part[1][j] + part[2][j] + part[3][j];
-      X[i][j] = ((i == j ? 1.0 : 0.0) - tot) / Lk[i][i];
-    }
-    __syncthreads();
-  }
-  double* out = a.Linv + (int64_t)k * kTile * kTile;
-  for (int idx = tid; idx < kTile * kTile; idx += 256) out[idx] = X[idx / kTile][idx % kTile];
+// global row offset of row tile t: [0, nt) matrix, nt: the v row,
+// nt + 1 + i: identity rows of block i
+__device__ __forceinline__ int64_t row_off(int t, int nt, int Np) {
+  return t < nt ? (int64_t)t * kTile : (t == nt ? (int64_t)Np : (int64_t)Np + kTile + (int64_t)(t - nt - 1) * kTile);
 }
 
-// x = A^-1 rhs with A = L L^T: blocked forward then backward substitution
-// using the diagonal inverses. One workgroup of 1024 threads. `mode` 0:
-// theta = s .* x;  mode 1: theta += s .* x (refinement update).
-// rhs_scaled: the right-hand side in the equilibrated system.
-__global__ __launch_bounds__(1024) void k_trsv(SolveArgs a, const double* rhs, int mode) {
-  if (a.flags[1] != 0) return;
-  extern __shared__ double vbuf[];     // Np
-  __shared__ double blk[kTile];
-  const int tid = threadIdx.x, Np = a.Np, nt = a.nt;
-  for (int i = tid; i < Np; i += 1024) vbuf[i] = rhs[i];
-  __syncthreads();
-  const int lane = tid & 63, wid = tid >> 6;    // 16 waves
-  // forward: z_k = Linv_kk (v_k - sum_{j<k} L_kj z_j); the sum is applied eagerly
-  for (int k = 0; k < nt; ++k) {
-    const double* Li = a.Linv + (int64_t)k * kTile * kTile;
-    // row i of the block: wave w handles rows w, w+16, ...
-    for (int i = wid; i < kTile; i += 16) {
-      double s = Li[i * kTile + lane] * vbuf[k * kTile + lane];
-      s = wave_sum(s);
-      if (lane == 0) blk[i] = s;
-    }
-    __syncthreads();
-    if (tid < kTile) vbuf[k * kTile + tid] = blk[tid];
-    __syncthreads();
-    // v_i -= L_i,k z_k for rows i beyond block k
-    for (int i = (k + 1) * kTile + tid; i < Np; i += 1024) {
-      const double* Lr = a.A + (int64_t)i * Np + (int64_t)k * kTile;
-      double s = 0.0;
-#pragma unroll 8
-      for (int l = 0; l < kTile; ++l) s = fma(Lr[l], vbuf[k * kTile + l], s);
-      vbuf[i] -= s;
-    }
-    __syncthreads();
-  }
-  // backward: x_k = Linv_kk^T (z_k - sum_{i>k} L_ik^T x_i)
-  for (int k = nt - 1; k >= 0; --k) {
-    const double* Li = a.Linv + (int64_t)k * kTile * kTile;
-    for (int i = wid; i < kTile; i += 16) {
-      // (Linv^T v)_i = sum_l Linv[l][i] v_l
-      double s = Li[lane * kTile + i] * vbuf[k * kTile + lane];
-      s = wave_sum(s);
-      if (lane == 0) blk[i] = s;
-    }
-    __syncthreads();
-    if (tid < kTile) vbuf[k * kTile + tid] = blk[tid];
-    __syncthreads();
-    // v_j -= L_kj^T x_k for columns j < block k: v_j -= sum_l L[k*64+l][j] x_l
-    for (int jcol = tid; jcol < k * kTile; jcol += 1024) {
-      double s = 0.0;
-#pragma unroll 8
-      for (int l = 0; l < kTile; ++l)
-        s = fma(a.A[(int64_t)(k * kTile + l) * Np + jcol], vbuf[k * kTile + l], s);
-      vbuf[jcol] -= s;
-    }
-    __syncthreads();
-  }
-  for (int i = tid; i < Np; i += 1024) {
-    const double v = a.s[i] * vbuf[i];
-    if (mode == 0) a.theta[i] = v;
-    else a.theta[i] += v;
+__device__ __forceinline__ void load_tile_r(double (*T)[kLD], const double* A, int Np, int64_t r0, int tj,
+                                            int rows = kTile) {
+  for (int idx = threadIdx.x; idx < kTile * kTile; idx += kPT) {
+    const int i = idx >> 6, j = idx & 63;
+    T[i][j] = (i < rows) ? A[(r0 + i) * Np + (int64_t)tj * kTile + j] : 0.0;
   }
 }
 
-// residual: rvec = D (h - G theta) (equilibrated), rowabs kept; one row per wave
-__global__ __launch_bounds__(256) void k_residual(SolveArgs a) {
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= a.Np) return;
-  if (i >= a.N) {
-    if (lane == 0) a.rvec[i] = 0.0;
-    return;
+__device__ __forceinline__ void store_tile_r(const double (*T)[kLD], double* A, int Np, int64_t r0, int tj,
+                                             int rows = kTile) {
+  for (int idx = threadIdx.x; idx < kTile * kTile; idx += kPT) {
+    const int i = idx >> 6, j = idx & 63;
+    if (i < rows) A[(r0 + i) * Np + (int64_t)tj * kTile + j] = T[i][j];
   }
-  double s = 0.0;
-  const double* Gr = a.G + (int64_t)i * a.N;
-  for (int j = lane; j < a.N; j += 64) s = fma(Gr[j], a.theta[j], s);
-  s = wave_sum(s);
-  if (lane == 0) a.rvec[i] = a.s[i] * (a.h[i] - s);
 }
 
-// final: coefficients, backward error, pivot range, status
-__global__ __launch_bounds__(1024) void k_solve_final(SolveArgs a, int refine) {
-  __shared__ double sc[16];
-  const int tid = threadIdx.x;
-  const int N = a.N;
-  const bool failed = a.flags[1] != 0;
-  double rmax = 0.0, tmax = 0.0, hmax = 0.0, gmax = 0.0, pmin = 1e308, pmax = 0.0;
-  for (int i = tid; i < N; i += 1024) {
-    const double si = a.s[i];
-    // rvec holds D (h - G theta) from the last k_residual call
-    const double ri = (si > 0.0) ? fabs(a.rvec[i] / si) : 0.0;
-    rmax = fmax(rmax, ri);
-    tmax = fmax(tmax, fabs(a.theta[i]));
-    hmax = fmax(hmax, fabs(a.h[i]));
-    gmax = fmax(gmax, a.rowabs[i]);
-    if (!failed) {
-      const double p = a.A[(int64_t)i * a.Np + i];
-      pmin = fmin(pmin, p);
-      pmax = fmax(pmax, p);
-    }
-    a.coef[i] = failed ? __builtin_nan("") : a.theta[i];
+// out_i = sum_j U[i][j] in_j with U = L^-T stored in the identity rows
+// (upper triangular: j >= i); one row per wave.
+__device__ void gemv_upper(const PSArgs& a, const double* in, double* out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = kPT / 64;
+  const double* U = a.A + ((int64_t)a.Np + kTile) * a.Np;
+  for (int i = blockIdx.x * nw + wave; i < a.Np; i += a.P * nw) {
+    const double* Ur = U + (int64_t)i * a.Np;
+    double acc = 0.0;
+    for (int j = (i & ~63) + lane; j < a.Np; j += 64) acc = fma(Ur[j], in[j], acc);
+    acc = wave_sum(acc);
+    if (lane == 0) out[i] = acc;
   }
-  auto bmax = [&](double v) {
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    __syncthreads();
-    if ((tid & 63) == 0) sc[tid >> 6] = v;
-    __syncthreads();
-    double m = sc[0];
-    for (int w = 1; w < 16; ++w) m = fmax(m, sc[w]);
-    return m;
-  };
-  rmax = bmax(rmax);
-  tmax = bmax(tmax);
-  hmax = bmax(hmax);
-  gmax = bmax(gmax);
-  pmax = bmax(pmax);
-  pmin = -bmax(-pmin);
-  if (tid == 0) {
-    sfft_solve_info* inf = a.info;
-    // a non-finite input pixel is the root cause of any later failure
-    if (failed) {
-      inf->status = SFFT_ERR_NOT_SPD;
-      inf->failed_pivot = a.flags[1] - 1;
-      inf->backward_err = __builtin_nan("");
+}
+
+// out_j = sum_i U[i][j] in_i (U^T = L^-1, lower): one column per thread
+__device__ void gemv_upper_t(const PSArgs& a, const double* in, double* out) {
+  const double* U = a.A + ((int64_t)a.Np + kTile) * a.Np;
+  for (int j = blockIdx.x * kPT + threadIdx.x; j < a.Np; j += a.P * kPT) {
+    double acc = 0.0;
+    const int iend = j + 1;
+    int i = 0;
+    for (; i + 4 <= iend; i += 4) {
+      const double u0 = U[(int64_t)i * a.Np + j], u1 = U[(int64_t)(i + 1) * a.Np + j];
+      const double u2 = U[(int64_t)(i + 2) * a.Np + j], u3 = U[(int64_t)(i + 3) * a.Np + j];
+      acc = fma(u0, in[i], acc);
+      acc = fma(u1, in[i + 1], acc);
+      acc = fma(u2, in[i + 2], acc);
+      acc = fma(u3, in[i + 3], acc);
+    }
+    for (; i < iend; ++i) acc = fma(U[(int64_t)i * a.Np + j], in[i], acc);
+    out[j] = acc;
+  }
+}
+
+// r = D (h - G theta), one row per wave, rows spread over all workgroups
+__device__ void residual(const PSArgs& a) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = kPT / 64;
+  for (int i = blockIdx.x * nw + wave; i < a.Np; i += a.P * nw) {
+    if (i >= a.N) {
+      if (lane == 0) a.r[i] = 0.0;
+      continue;
+    }
+    const double* Gr = a.G + (int64_t)i * a.N;
+    double sacc = 0.0;
+    for (int j = lane; j < a.N; j += 64) sacc = fma(Gr[j], a.theta[j], sacc);
+    sacc = wave_sum(sacc);
+    if (lane == 0) a.r[i] = a.s[i] * (a.h[i] - sacc);
+  }
+}
+
+__global__ __launch_bounds__(kPT) void k_solve_persistent(PSArgs a) {
+  extern __shared__ __align__(16) double smem[];
+  double (*T0)[kLD] = reinterpret_cast<double (*)[kLD]>(smem);
+  double (*T1)[kLD] = reinterpret_cast<double (*)[kLD]>(smem + kTile * kLD);
+  double (*T2)[kLD] = reinterpret_cast<double (*)[kLD]>(smem + 2 * kTile * kLD);
+  double (*colbuf)[kTile] = reinterpret_cast<double (*)[kTile]>(smem + 3 * kTile * kLD);
+  __shared__ double red[kPT / 64];
+  Barrier bar;
+  const int N = a.N, Np = a.Np, nt = a.nt, P = a.P;
+  const int bid = blockIdx.x;
+  double* v = a.A + (int64_t)Np * Np;                     // row Np: v, then z
+  double* U = a.A + ((int64_t)Np + kTile) * Np;           // identity rows, then L^-T
+
+  // ---- equilibrate: A = D G D (identity padding), v = D h, rowabs, identity rows
+  {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int i = bid * (kPT / 64) + wave; i < Np; i += P * (kPT / 64)) {
+      double si = 1.0;
+      if (i < N) {
+        const double gii = a.G[(int64_t)i * N + i];
+        si = (gii > 0.0 && is_finite_d(gii)) ? 1.0 / sqrt(gii) : 0.0;
+      }
+      double ra = 0.0;
+      for (int j = lane; j < Np; j += 64) {
+        double val;
+        if (i < N && j < N) {
+          const double gjj = a.G[(int64_t)j * N + j];
+          const double sj = (gjj > 0.0 && is_finite_d(gjj)) ? 1.0 / sqrt(gjj) : 0.0;
+          const double g = a.G[(int64_t)i * N + j];
+          ra += fabs(g);
+          val = si * g * sj;
+        } else {
+          val = (i == j) ? 1.0 : 0.0;
+        }
+        a.A[(int64_t)i * Np + j] = val;
+        U[(int64_t)i * Np + j] = (i == j) ? 1.0 : 0.0;
+      }
+      ra = wave_sum(ra);
+      if (lane == 0) {
+        a.s[i] = si;
+        v[i] = (i < N) ? si * a.h[i] : 0.0;
+        a.rowabs[i] = ra;
+      }
+    }
+  }
+  bar.wait(a);
+
+  // ---- factorisation of [A; v^T; I]
+  // factor the tile held in T0 (diagonal tile k) and store it
+  // factor the tile held in T0 (diagonal tile k); store L_kk and U_k = L_kk^-T
+  auto factor_diag = [&](int k) {
+    const int f = tile_potrf_aug(T0, T2, colbuf);
+    if (f >= 0) {
+      if (threadIdx.x == 0) atomicCAS(&a.flags[1], 0, k * kTile + f + 1);
     } else {
-      inf->backward_err = rmax / (gmax * tmax + hmax);
-      inf->min_pivot = pmin;
-      inf->max_pivot = pmax;
-      inf->refine_iters = refine;
+      store_tile(T0, a.A, Np, k, k);
+      for (int idx = threadIdx.x; idx < kTile * kTile; idx += kPT)
+        a.Ud[(int64_t)k * kTile * kTile + idx] = T2[idx >> 6][idx & 63];
     }
-    if (inf->nonfinite) inf->status = SFFT_ERR_NONFINITE;
+    __syncthreads();
+  };
+  if (bid == 0) {
+    load_tile(T0, a.A, Np, 0, 0);
+    __syncthreads();
+    factor_diag(0);
   }
+  bar.wait(a);
+  for (int k = 0; k < nt; ++k) {
+    if (failed(a)) break;
+    // panel: row tiles k+1 .. nt-1 (matrix), nt (v row), nt+1+i for i <= k
+    // (identity rows with nonzero entries in column tile k)
+    {
+      const int nmat = nt - k - 1;
+      const int npanel = nmat + 1 + (k + 1);
+      bool loaded = false;
+      for (int t = bid; t < npanel; t += P) {
+        int rt;
+        if (t < nmat) rt = k + 1 + t;
+        else if (t == nmat) rt = nt;
+        else rt = nt + 1 + (t - nmat - 1);
+        const int rows = (rt == nt) ? 1 : kTile;
+        const int64_t r0 = row_off(rt, nt, Np);
+        if (!loaded) {
+          for (int idx = threadIdx.x; idx < kTile * kTile; idx += kPT)
+            T1[idx >> 6][idx & 63] = a.Ud[(int64_t)k * kTile * kTile + idx];
+          loaded = true;
+        }
+        load_tile_r(T0, a.A, Np, r0, k, rows);
+        __syncthreads();
+        tile_mul_ab(T2, T0, T1);          // X = A_rk L_kk^-T
+        store_tile_r(T2, a.A, Np, r0, k, rows);
+        __syncthreads();
+      }
+    }
+    bar.wait(a);
+    if (k + 1 >= nt) break;
+    // trailing update of column tiles J in (k, nt): rows of the matrix
+    // (J <= I < nt), the v row and the identity rows i <= k; workgroup 0
+    // takes (k+1, k+1) and factors it (look-ahead)
+    const int m = nt - k - 1;
+    const int ntri = m * (m + 1) / 2;
+    const int nv = m;
+    const int naug = (k + 1) * m;
+    const int ntot = ntri + nv + naug;
+    if (bid == 0) {
+      load_tile(T0, a.A, Np, k + 1, k + 1);
+      load_tile(T1, a.A, Np, k + 1, k);
+      __syncthreads();
+      tile_sub_abt(T0, T1, T1);
+      factor_diag(k + 1);
+    }
+    if (P == 1 || bid > 0) {
+      const int first = (P > 1) ? bid - 1 : 0;
+      const int stride = (P > 1) ? P - 1 : 1;
+      for (int t = 1 + first; t < ntot; t += stride) {
+        int rt, J;
+        if (t < ntri) {
+          int ti, tj;
+          tri_decode(t, ti, tj);
+          rt = k + 1 + ti;
+          J = k + 1 + tj;
+        } else if (t < ntri + nv) {
+          rt = nt;
+          J = k + 1 + (t - ntri);
+        } else {
+          const int u = t - ntri - nv;
+          rt = nt + 1 + u / m;
+          J = k + 1 + u % m;
+        }
+        const int rows = (rt == nt) ? 1 : kTile;
+        const int64_t r0 = row_off(rt, nt, Np);
+        load_tile_r(T0, a.A, Np, r0, J, rows);
+        load_tile_r(T1, a.A, Np, r0, k, rows);
+        load_tile(T2, a.A, Np, J, k);
+        __syncthreads();
+        tile_sub_abt(T0, T1, T2);
+        store_tile_r(T0, a.A, Np, r0, J, rows);
+        __syncthreads();
+      }
+    }
+    bar.wait(a);
+  }
+  const bool bad = failed(a);
+  // ---- x = L^-T z, theta = D x, refinement
+  if (!bad) {
+    gemv_upper(a, v, a.x);
+    bar.wait(a);
+    for (int i = bid * kPT + threadIdx.x; i < Np; i += P * kPT) a.theta[i] = a.s[i] * a.x[i];
+    bar.wait(a);
+    for (int it = 0; it < a.refine; ++it) {
+      residual(a);                       // r = D (h - G theta)
+      bar.wait(a);
+      gemv_upper_t(a, a.r, a.x);         // x = L^-1 r
+      bar.wait(a);
+      gemv_upper(a, a.x, a.r);           // r = L^-T x
+      bar.wait(a);
+      for (int i = bid * kPT + threadIdx.x; i < Np; i += P * kPT) a.theta[i] += a.s[i] * a.r[i];
+      bar.wait(a);
+    }
+    residual(a);
+    bar.wait(a);
+  }
+  // ---- final report (workgroup 0)
+  if (bid == 0) {
+    double rmax = 0.0, tmax = 0.0, hmax = 0.0, gmax = 0.0, pmin = 1e308, pmax = 0.0;
+    for (int i = threadIdx.x; i < N; i += kPT) {
+      hmax = fmax(hmax, fabs(a.h[i]));
+      if (!bad) {
+        const double si = a.s[i];
+        rmax = fmax(rmax, si > 0.0 ? fabs(a.r[i] / si) : 0.0);
+        tmax = fmax(tmax, fabs(a.theta[i]));
+        gmax = fmax(gmax, a.rowabs[i]);
+        const double pv = a.A[(int64_t)i * Np + i];
+        pmin = fmin(pmin, pv);
+        pmax = fmax(pmax, pv);
+      }
+      a.coef[i] = bad ? __builtin_nan("") : a.theta[i];
+    }
+    auto bmax = [&](double val) {
+      for (int off = 32; off > 0; off >>= 1) val = fmax(val, __shfl_xor(val, off, 64));
+      __syncthreads();
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = val;
+      __syncthreads();
+      double mm = red[0];
+      for (int w = 1; w < kPT / 64; ++w) mm = fmax(mm, red[w]);
+      return mm;
+    };
+    rmax = bmax(rmax);
+    tmax = bmax(tmax);
+    hmax = bmax(hmax);
+    gmax = bmax(gmax);
+    pmax = bmax(pmax);
+    pmin = -bmax(-pmin);
+    if (threadIdx.x == 0) {
+      sfft_solve_info inf{};
+      inf.nonfinite = a.flags[0];
+      inf.failed_pivot = -1;
+      if (bad) {
+        inf.status = SFFT_ERR_NOT_SPD;
+        inf.failed_pivot = a.flags[1] - 1;
+        inf.backward_err = __builtin_nan("");
+      } else {
+        inf.status = SFFT_OK;
+        inf.backward_err = rmax / (gmax * tmax + hmax);
+        inf.min_pivot = pmin;
+        inf.max_pivot = pmax;
+        inf.refine_iters = a.refine;
+      }
+      if (a.flags[2]) inf.status = SFFT_ERR_INTERNAL;
+      if (inf.nonfinite) inf.status = SFFT_ERR_NONFINITE;
+      *a.info = inf;
+    }
+  }
+}
+
+// clears the arrival / release flags and the barrier time stamps
+__global__ void k_solve_reset(unsigned* sync, int nsync, int* flags) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nsync) sync[i] = 0u;
+  if (i == 0) { flags[1] = 0; flags[2] = 0; }
+}
+
+size_t solve_shmem_bytes() {
+  return sizeof(double) * (3 * kTile * kLD + 4 * kTile);
+}
+
+int solve_workgroups(int nt) {
+  // about one trailing-update tile per workgroup in the first steps, at most 64
+  const int widest = nt * (nt + 1) / 2 + nt;
+  return widest < 64 ? (widest > 1 ? widest : 1) : 64;
+}
+
+hipError_t prepare_solve_attributes() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_solve_persistent),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)solve_shmem_bytes());
 }
 
 hipError_t launch_solve(const sfft_desc& d, const double* G, const double* h, double* coef,
@@ -361,54 +566,29 @@ hipError_t launch_solve(const sfft_desc& d, const double* G, const double* h, do
                         const Prof* pf, hipStream_t st) {
   const Geometry g = make_geometry(d);
   const Layout l = make_layout(g);
-  SolveArgs a{};
+  PSArgs a{};
   a.G = G; a.h = h; a.coef = coef; a.info = info;
   a.A = reinterpret_cast<double*>(ws + l.A);
   a.s = reinterpret_cast<double*>(ws + l.s);
-  a.b = reinterpret_cast<double*>(ws + l.b);
-  a.theta = reinterpret_cast<double*>(ws + l.theta);
   a.x = reinterpret_cast<double*>(ws + l.x);
-  a.rvec = reinterpret_cast<double*>(ws + l.rvec);
+  a.theta = reinterpret_cast<double*>(ws + l.theta);
+  a.r = reinterpret_cast<double*>(ws + l.rvec);
   a.rowabs = reinterpret_cast<double*>(ws + l.rowabs);
-  a.Linv = reinterpret_cast<double*>(ws + l.Linv);
+  a.Ud = reinterpret_cast<double*>(ws + l.Ud);
+  a.sync = reinterpret_cast<unsigned*>(ws + l.sync);
+  a.stamps = reinterpret_cast<unsigned long long*>(ws + l.sync + 512);
   a.flags = reinterpret_cast<int*>(ws + l.flags);
-  a.N = g.N; a.nt = l.nt; a.Np = l.nt * kTile;
-  hipError_t e;
-#define SFFT_CHECK_LAUNCH() do { if ((e = hipGetLastError()) != hipSuccess) return e; } while (0)
+  a.N = g.N; a.nt = l.nt; a.Np = l.nt * kTile; a.refine = max_refine;
+  a.P = solve_workgroups(l.nt);
   prof_begin(pf, SFFT_PROF_SOLVE, st);
-  hipLaunchKernelGGL(k_solve_init, dim3(1), dim3(64), 0, st, a);
-  SFFT_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_equil, dim3(a.Np), dim3(256), 0, st, a);
-  SFFT_CHECK_LAUNCH();
-  for (int k = 0; k < a.nt; ++k) {
-    hipLaunchKernelGGL(k_potrf_tile, dim3(1), dim3(256), 0, st, a, k);
-    SFFT_CHECK_LAUNCH();
-    const int rest = a.nt - k - 1;
-    if (rest > 0) {
-      hipLaunchKernelGGL(k_trsm_panel, dim3(rest), dim3(256), 0, st, a, k);
-      SFFT_CHECK_LAUNCH();
-      hipLaunchKernelGGL(k_syrk_tile, dim3(rest * (rest + 1) / 2), dim3(256), 0, st, a, k);
-      SFFT_CHECK_LAUNCH();
-    }
-  }
-  hipLaunchKernelGGL(k_tile_inverse, dim3(a.nt), dim3(256), 0, st, a);
-  SFFT_CHECK_LAUNCH();
-  const size_t sh = sizeof(double) * a.Np;
-  hipLaunchKernelGGL(k_trsv, dim3(1), dim3(1024), sh, st, a, (const double*)a.b, 0);
-  SFFT_CHECK_LAUNCH();
-  for (int it = 0; it < max_refine; ++it) {
-    hipLaunchKernelGGL(k_residual, dim3((a.Np + 3) / 4), dim3(256), 0, st, a);
-    SFFT_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_trsv, dim3(1), dim3(1024), sh, st, a, (const double*)a.rvec, 1);
-    SFFT_CHECK_LAUNCH();
-  }
-  hipLaunchKernelGGL(k_residual, dim3((a.Np + 3) / 4), dim3(256), 0, st, a);
-  SFFT_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_solve_final, dim3(1), dim3(1024), 0, st, a, max_refine);
-  SFFT_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_solve_reset, dim3(1), dim3(640), 0, st, a.sync, 640, a.flags);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  void* args[] = {&a};
+  e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_solve_persistent), dim3(a.P),
+                                 dim3(kPT), args, (unsigned)solve_shmem_bytes(), st);
   prof_end(pf, SFFT_PROF_SOLVE, st);
-#undef SFFT_CHECK_LAUNCH
-  return hipSuccess;
+  return e;
 }
 
 }  // namespace sfft

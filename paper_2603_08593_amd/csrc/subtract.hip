@@ -19,7 +19,6 @@ struct SubArgs {
   void* D;
   int64_t ld;
   const double* coef;
-  const double* k2;     // [2DK+1][2DK+1] coefficients of kappa2(xt, yt)
   double* partials;
   int W, H, N, DB, want_chi2;
   double cR, cS, sx, sy;
@@ -40,15 +39,47 @@ __global__ __launch_bounds__(128) void k_subtract(SubArgs a) {
   __shared__ double Rt[RH][RW + 1];
   __shared__ double cs[NK * L * L];
   __shared__ double red[2];
+  __shared__ double Qk[NK * NK];
+  __shared__ double K2[(2 * DK + 1) * (2 * DK + 1)];
   const int tid = threadIdx.x;
   const int W = a.W, H = a.H;
   const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
   for (int i = tid; i < NK * L * L; i += 128) cs[i] = a.coef[i];
+  __syncthreads();
+  if (a.want_chi2) {
+    // kappa2(x) = sum_d (sum_i a_(i,d) p_i(x))^2 = sum_{e,f} K2[e][f] xt^e yt^f,
+    // K2[ai+aj][bi+bj] += sum_d a_(i,d) a_(j,d)
+    if (tid < NK * NK) {
+      const int i = tid / NK, j = tid % NK;
+      double sacc = 0.0;
+      for (int dd = 0; dd < L * L; ++dd) sacc = fma(cs[i * L * L + dd], cs[j * L * L + dd], sacc);
+      Qk[tid] = sacc;
+    }
+    __syncthreads();
+    constexpr int NE = 2 * DK + 1;
+    if (tid < NE * NE) {
+      const int e = tid / NE, f = tid % NE;
+      double sacc = 0.0;
+      int i = 0;
+      for (int di = 0; di <= DK; ++di)
+        for (int bi = 0; bi <= di; ++bi, ++i) {
+          int j = 0;
+          for (int dj = 0; dj <= DK; ++dj)
+            for (int bj = 0; bj <= dj; ++bj, ++j)
+              if ((di - bi) + (dj - bj) == e && bi + bj == f) sacc += Qk[i * NK + j];
+        }
+      K2[tid] = sacc;
+    }
+  }
   for (int i = tid; i < RH * RW; i += 128) {
-    const int ly = i / RW, lx = i % RW;
+    const int ly = i / RW, lx = i - (i / RW) * RW;
     int yy = y0 + ly - r, xx = x0 + lx - r;
-    yy %= H; if (yy < 0) yy += H;
-    xx %= W; if (xx < 0) xx += W;
+    yy = (yy < 0) ? yy + H : yy;
+    yy = (yy >= H) ? yy - H : yy;
+    yy = (yy >= H) ? yy - H : yy;
+    xx = (xx < 0) ? xx + W : xx;
+    xx = (xx >= W) ? xx - W : xx;
+    xx = (xx >= W) ? xx - W : xx;
     Rt[ly][lx] = (double)static_cast<const TIO*>(a.R)[(int64_t)yy * a.ld + xx] - a.cR;
   }
   __syncthreads();
@@ -58,8 +89,10 @@ __global__ __launch_bounds__(128) void k_subtract(SubArgs a) {
   double xq[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    int ux = (xb + q - r) % W;
-    if (ux < 0) ux += W;
+    int ux = xb + q - r;
+    ux = (ux < 0) ? ux + W : ux;
+    ux = (ux >= W) ? ux - W : ux;
+    ux = (ux >= W) ? ux - W : ux;
     xq[q] = (double)ux * a.sx - 1.0;
   }
   double acc[P];
@@ -68,8 +101,10 @@ __global__ __launch_bounds__(128) void k_subtract(SubArgs a) {
 #pragma unroll 1
   for (int dyi = 0; dyi < L; ++dyi) {
     const int lr = ty + (L - 1 - dyi);           // local row of u_y = y - dy
-    int uy = (y - (dyi - r)) % H;
-    if (uy < 0) uy += H;
+    int uy = y - (dyi - r);
+    uy = (uy < 0) ? uy + H : uy;
+    uy = (uy >= H) ? uy - H : uy;
+    uy = (uy >= H) ? uy - H : uy;
     const double yt = (double)uy * a.sy - 1.0;
     double ypw[DK + 1];
     ypw[0] = 1.0;
@@ -89,14 +124,16 @@ __global__ __launch_bounds__(128) void k_subtract(SubArgs a) {
         for (int b = 0; b <= DK - m; ++b) s = fma(cs[mono_index(m, b) * L * L + tap], ypw[b], s);
         cm[m] = s;
       }
+      // Horner in xt for all P pixels stage by stage: P independent chains
+      double w[P];
 #pragma unroll
-      for (int p = 0; p < P; ++p) {
-        const int q = p + (L - 1 - dxi);
-        double w = cm[DK];
+      for (int p = 0; p < P; ++p) w[p] = cm[DK];
 #pragma unroll
-        for (int m = DK - 1; m >= 0; --m) w = fma(w, xq[q], cm[m]);
-        acc[p] = fma(w, win[q], acc[p]);
-      }
+      for (int m = DK - 1; m >= 0; --m)
+#pragma unroll
+        for (int p = 0; p < P; ++p) w[p] = fma(w[p], xq[p + (L - 1 - dxi)], cm[m]);
+#pragma unroll
+      for (int p = 0; p < P; ++p) acc[p] = fma(w[p], win[p + (L - 1 - dxi)], acc[p]);
     }
   }
   // background, difference, chi2
@@ -121,7 +158,7 @@ __global__ __launch_bounds__(128) void k_subtract(SubArgs a) {
 #pragma unroll
       for (int e = 0; e <= 2 * DK; ++e) {
         double s = 0.0;
-        for (int f = 2 * DK; f >= 0; --f) s = fma(s, yto, a.k2[e * (2 * DK + 1) + f]);
+        for (int f = 2 * DK; f >= 0; --f) s = fma(s, yto, K2[e * (2 * DK + 1) + f]);
         kk[e] = s;
       }
     }
@@ -151,37 +188,6 @@ __global__ __launch_bounds__(128) void k_subtract(SubArgs a) {
     if ((tid & 63) == 0) red[tid >> 6] = chi;
     __syncthreads();
     if (tid == 0) a.partials[blockIdx.y * gridDim.x + blockIdx.x] = red[0] + red[1];
-  }
-}
-
-// kappa2 polynomial: K2[ai+aj][bi+bj] += sum_d a_(i,d) a_(j,d)
-__global__ __launch_bounds__(256) void k_kappa2(const double* coef, double* k2, int L, int DK) {
-  __shared__ double Q[15][15];
-  const int nK = (DK + 1) * (DK + 2) / 2;
-  const int L2 = L * L;
-  const int tid = threadIdx.x;
-  if (tid < nK * nK) {
-    const int i = tid / nK, j = tid % nK;
-    double s = 0.0;
-    for (int d = 0; d < L2; ++d) s = fma(coef[i * L2 + d], coef[j * L2 + d], s);
-    Q[i][j] = s;
-  }
-  __syncthreads();
-  const int ne = 2 * DK + 1;
-  if (tid < ne * ne) {
-    const int e = tid / ne, f = tid % ne;
-    double s = 0.0;
-    int i = 0;
-    for (int di = 0; di <= DK; ++di)
-      for (int bi = 0; bi <= di; ++bi, ++i) {
-        int j = 0;
-        for (int dj = 0; dj <= DK; ++dj)
-          for (int bj = 0; bj <= dj; ++bj, ++j) {
-            const int ai = di - bi, aj = dj - bj;
-            if (ai + aj == e && bi + bj == f) s += Q[i][j];
-          }
-      }
-    k2[e * ne + f] = s;
   }
 }
 
@@ -219,18 +225,12 @@ hipError_t launch_subtract(const sfft_desc& d, const void* R, const void* S, con
   const Layout l = make_layout(g);
   SubArgs a{};
   a.R = R; a.S = S; a.D = D; a.ld = d.ld; a.coef = coef;
-  a.k2 = reinterpret_cast<const double*>(ws + l.kcoef);
   a.partials = reinterpret_cast<double*>(ws + l.partials);
   a.W = g.W; a.H = g.H; a.N = g.N; a.DB = g.DB; a.want_chi2 = chi2 != nullptr;
   a.cR = d.ref_pedestal; a.cS = d.sci_pedestal;
   a.sx = g.W > 1 ? 2.0 / (double)(g.W - 1) : 0.0;
   a.sy = g.H > 1 ? 2.0 / (double)(g.H - 1) : 0.0;
   hipError_t e;
-  if (chi2) {
-    hipLaunchKernelGGL(k_kappa2, dim3(1), dim3(256), 0, st, coef,
-                       reinterpret_cast<double*>(ws + l.kcoef), g.L, g.DK);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
   const dim3 grid((g.W + kSubTX - 1) / kSubTX, (g.H + kSubTY - 1) / kSubTY);
   const bool f32 = d.image_dtype == SFFT_F32;
   prof_begin(pf, SFFT_PROF_SUBTRACT, st);

@@ -275,7 +275,7 @@ def make_cfg2(index: int = 0, W: int = 2048, H: int = 4096, nstars: int | None =
 def pick_stamps(pair: Pair, n: int = 64, size: int = 41):
     """Stamp centres for the stamp-based fit: the n brightest stars at least
     size//2 + r + 1 px from every edge with no other star brighter than 1% of
-    their flux within 2*size px; ties by catalogue index; centre = nearest
+    their flux within `size` px; ties by catalogue index; centre = nearest
     pixel (round half to even). Returns int32 array (n, 2) of (x, y)."""
     H, W = pair.R.shape
     r = (pair.L - 1) // 2
@@ -288,7 +288,7 @@ def pick_stamps(pair: Pair, n: int = 64, size: int = 41):
         if not (margin <= cx < W - margin and margin <= cy < H - margin):
             continue
         d = np.hypot(xs - xs[k], ys - ys[k])
-        bad = (d < 2 * size) & (fl > 0.01 * fl[k])
+        bad = (d < size) & (fl > 0.01 * fl[k])
         bad[k] = False
         if bad.any():
             continue

@@ -53,7 +53,11 @@ def test_validation_codes():
     assert sf.sfft_validate(sf.make_desc(64, 64, 5, 5, 0)) == sf.SFFT_ERR_INVALID_ARG    # DK > 4
     assert sf.sfft_validate(sf.make_desc(16, 8, 9, 0, 0)) == sf.SFFT_ERR_INVALID_ARG     # L > min(W,H)
     assert sf.sfft_validate(sf.make_desc(64, 64, 5, 0, 0, ld=32)) == sf.SFFT_ERR_INVALID_ARG  # ld < W
-    assert sf.sfft_validate(sf.make_desc(96, 64, 5, 0, 0)) == sf.SFFT_ERR_UNSUPPORTED    # W not 2^k
+    assert sf.sfft_validate(sf.make_desc(112, 64, 5, 0, 0)) == sf.SFFT_ERR_UNSUPPORTED   # 7 | W
+    assert sf.sfft_validate(sf.make_desc(22, 64, 5, 0, 0)) == sf.SFFT_ERR_UNSUPPORTED    # 11 | W
+    assert sf.sfft_validate(sf.make_desc(95, 64, 5, 0, 0)) == sf.SFFT_ERR_UNSUPPORTED    # W odd
+    assert sf.sfft_validate(sf.make_desc(96, 64, 5, 0, 0)) == sf.SFFT_OK                 # 2^5 3
+    assert sf.sfft_validate(sf.make_desc(1500, 64, 5, 0, 0)) == sf.SFFT_OK               # 2^2 3 5^3
     assert sf.sfft_validate(sf.make_desc(64, 64, 5, 3, 0)) == sf.SFFT_ERR_UNSUPPORTED    # DK = 3
     assert sf.sfft_validate(sf.make_desc(64, 64, 17, 0, 0)) == sf.SFFT_ERR_UNSUPPORTED   # L > 15
     assert sf.sfft_validate(sf.make_desc(16, 64, 11, 0, 0)) == sf.SFFT_ERR_UNSUPPORTED   # W < 2L

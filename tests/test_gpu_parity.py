@@ -87,6 +87,10 @@ def test_cfg1_full_path():
     (128, 64, 1, 0, 0, np.float32),       # single tap, constant background
     (16, 48, 3, 0, 2, np.float64),        # smallest width
     (512, 128, 9, 2, 1, np.float32),
+    (96, 80, 5, 1, 1, np.float64),        # W = 2^5 3: radix-3 row FFT
+    (160, 120, 7, 2, 2, np.float32),      # W = 2^5 5: radix-5 row FFT
+    (1500, 40, 3, 1, 1, np.float32),      # W = 2^2 3 5^3: 6 row elements per thread
+    (768, 256, 15, 2, 2, np.float32),     # L = 15, DK = 2 (N = 1356)
 ])
 def test_small_shapes(W, H, L, DK, DB, dtype):
     p = synth.make_pair(W, H, L, DK, DB, seed=1000 + W + H + L, nstars=max(8, W * H // 2000),
