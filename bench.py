@@ -29,9 +29,20 @@ W, H, L, DK, DB = 2048, 4096, 11, 2, 2
 # ---------------------------------------------------------------------------
 # HIP events through the runtime's C API (timings on the library's stream)
 # ---------------------------------------------------------------------------
+def _loaded_hip_runtime() -> str:
+    """Path of the HIP runtime already mapped into this process (the one torch
+    and the SFFT library use), so that events live in the same runtime."""
+    with open("/proc/self/maps") as f:
+        for line in f:
+            path = line.split()[-1]
+            if "libamdhip64.so" in path:
+                return path
+    return "libamdhip64.so"
+
+
 class HipEvents:
     def __init__(self):
-        self.hip = ctypes.CDLL("libamdhip64.so")
+        self.hip = ctypes.CDLL(_loaded_hip_runtime())
         self.hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
         self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
                                                  ctypes.c_void_p]

@@ -182,6 +182,69 @@ sfft_status sfft_build_system_stamps(sfft_handle handle, const sfft_desc* desc,
                                      double* G, double* h,
                                      void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Learned form ------------------------------------------------------
+ * A small convolutional network predicts the kernel and background
+ * coefficients of the fit from star-stamp pairs, so that a pair whose
+ * predicted difference image passes the chi2 judge skips the build and the
+ * solve (the paper's pipeline couples the differencing with learned models,
+ * Sec. 2.3). Architecture, per stamp: conv 3x3 2->16 (stride 1), 16->32,
+ * 32->64, 64->64 (stride 2), ReLU after each, linear 1024->128 ReLU; per
+ * pair: pooled[i][c] = mean over stamps of p_i(xt, yt) h[c] for the six
+ * monomials 1, xt, yt, xt^2, xt yt, yt^2 of the stamp centre; linear
+ * 768->512 ReLU; linear 512->n_out. Convolutions: zero padding 1,
+ * cross-correlation. Outputs are standardised coefficients
+ * (coef = mean + scale * pred, see sfft_surrogate_destandardize).
+ * Parameters: one flat FP32 device vector, in order conv1..conv4 (weight
+ * [out][in][3][3], bias [out]), fc1, fc2, fc3 (weight [out][in], bias).
+ * Stamps: FP32 [n][2][32][32] (reference, science); positions FP32 [n][2]
+ * (xt, yt); the n_stamps stamps of a pair are contiguous.
+ * Every reduction has a fixed order: results are bit-reproducible. */
+typedef enum { SFFT_NET_FP32 = 0, SFFT_NET_BF16 = 1 } sfft_net_precision;
+
+/* Number of parameters for n_out outputs (960812 for n_out = 732), -1 if invalid. */
+int64_t sfft_surrogate_num_params(int32_t n_out);
+
+/* Device workspace bytes for sfft_surrogate_forward / _grad at this shape
+ * (n_pairs <= 4096, n_stamps <= 1024, n_pairs * n_stamps <= 2^20). */
+sfft_status sfft_surrogate_workspace_size(int32_t n_pairs, int32_t n_stamps, int32_t n_out, size_t* bytes);
+
+/* Stamp pairs for the network: the 32 x 32 windows [cx-16, cx+16) x
+ * [cy-16, cy+16) of ref and sci (periodic), each minus the mean of its
+ * window's border pixels, both divided by the reference window's
+ * sky-subtracted sum (1 if not positive) and multiplied by 100; positions
+ * xt = 2 cx / (W-1) - 1, yt = 2 cy / (H-1) - 1. centers: device int32 [n][2]. */
+sfft_status sfft_extract_stamps(sfft_handle handle, const sfft_desc* desc, const void* ref,
+                                const void* sci, const int32_t* centers, int32_t n,
+                                float* stamps, float* pos, void* stream);
+
+/* pred (device FP32 [n_pairs][n_out]) = network(params, stamps, pos).
+ * precision SFFT_NET_BF16 rounds parameters, stamps and every activation to
+ * bfloat16 (round to nearest even) and accumulates in FP32. */
+sfft_status sfft_surrogate_forward(sfft_handle handle, const float* params, const float* stamps,
+                                   const float* pos, int32_t n_pairs, int32_t n_stamps, int32_t n_out,
+                                   int32_t precision, float* pred, void* ws, size_t ws_bytes,
+                                   void* stream);
+
+/* FP32 forward pass, loss = mean over pairs and outputs of (pred - target)^2
+ * (device double), and the gradient of the loss with respect to every
+ * parameter into grads (device FP32, parameter layout). */
+sfft_status sfft_surrogate_grad(sfft_handle handle, const float* params, const float* stamps,
+                                const float* pos, const float* target, int32_t n_pairs,
+                                int32_t n_stamps, int32_t n_out, float* grads, double* loss,
+                                void* ws, size_t ws_bytes, void* stream);
+
+/* One Adam step (Kingma and Ba) on n parameters, step counted from 1:
+ * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps). */
+sfft_status sfft_surrogate_adam(sfft_handle handle, float* params, const float* grads, float* m,
+                                float* v, int64_t n, int32_t step, float lr, float beta1,
+                                float beta2, float eps, void* stream);
+
+/* coef[b][j] = mean[j] + scale[j] pred[b][j] (FP64 out; mean, scale FP64 [n_out]). */
+sfft_status sfft_surrogate_destandardize(sfft_handle handle, const float* pred, const double* mean,
+                                         const double* scale, int32_t n_pairs, int32_t n_out,
+                                         double* coef, void* stream);
+
 /* Kernel timing hook (measurement support, not part of the method).
  * Kernels / launch groups that can be bracketed by events: */
 typedef enum {

@@ -82,7 +82,20 @@ _SIGS = {
     "sfft_build_system_stamps": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, ctypes.c_int32,
                                                 ctypes.c_int32, _P, _P, _P, ctypes.c_size_t, _P]),
     "sfft_profile_events": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
+    "sfft_surrogate_num_params": (ctypes.c_int64, [ctypes.c_int32]),
+    "sfft_surrogate_workspace_size": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                     ctypes.POINTER(ctypes.c_size_t)]),
+    "sfft_extract_stamps": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, ctypes.c_int32, _P, _P, _P]),
+    "sfft_surrogate_forward": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.c_int32, _P, _P, ctypes.c_size_t, _P]),
+    "sfft_surrogate_grad": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                           _P, _P, _P, ctypes.c_size_t, _P]),
+    "sfft_surrogate_adam": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_float,
+                                           ctypes.c_float, ctypes.c_float, ctypes.c_float, _P]),
+    "sfft_surrogate_destandardize": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
 }
+
+SFFT_NET_FP32, SFFT_NET_BF16 = 0, 1
 
 # sfft_prof_slot
 SFFT_PROF_ROW_PASS, SFFT_PROF_COL_PASS, SFFT_PROF_XINV, SFFT_PROF_SUBTRACT = 1, 2, 3, 4
@@ -97,6 +110,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"SFFT HIP library not built ({LIB_PATH}); run __graft_entry__.build()")
+        # torch ships its own HIP runtime: load it first so that this library
+        # binds to the same runtime instance (one per process)
+        import torch  # noqa: F401
         l = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             f = getattr(l, name)
@@ -295,3 +311,100 @@ class Differencer:
 
     def info(self) -> SolveInfo:
         return read_info(self.buf.info)
+
+
+# ---------------------------------------------------------------------------
+# learned form
+# ---------------------------------------------------------------------------
+
+
+def sfft_surrogate_num_params(n_out: int) -> int:
+    return int(lib().sfft_surrogate_num_params(int(n_out)))
+
+
+def sfft_surrogate_workspace_size(n_pairs: int, n_stamps: int, n_out: int) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().sfft_surrogate_workspace_size(int(n_pairs), int(n_stamps), int(n_out), ctypes.byref(n)),
+           "sfft_surrogate_workspace_size")
+    return int(n.value)
+
+
+def sfft_extract_stamps(handle: Handle, desc: Desc, ref, sci, centers, stamps, pos, stream=None):
+    _check(lib().sfft_extract_stamps(handle.ptr, ctypes.byref(desc), _dp(ref), _dp(sci), _dp(centers),
+                                     int(centers.shape[0]), _dp(stamps), _dp(pos), _stream_ptr(stream)),
+           "sfft_extract_stamps")
+
+
+def sfft_surrogate_forward(handle: Handle, params, stamps, pos, n_pairs, n_stamps, n_out, precision, pred, ws,
+                           stream=None):
+    _check(lib().sfft_surrogate_forward(handle.ptr, _dp(params), _dp(stamps), _dp(pos), int(n_pairs),
+                                        int(n_stamps), int(n_out), int(precision), _dp(pred), _dp(ws),
+                                        ws.numel() * ws.element_size(), _stream_ptr(stream)),
+           "sfft_surrogate_forward")
+
+
+def sfft_surrogate_grad(handle: Handle, params, stamps, pos, target, n_pairs, n_stamps, n_out, grads, loss, ws,
+                        stream=None):
+    _check(lib().sfft_surrogate_grad(handle.ptr, _dp(params), _dp(stamps), _dp(pos), _dp(target), int(n_pairs),
+                                     int(n_stamps), int(n_out), _dp(grads), _dp(loss), _dp(ws),
+                                     ws.numel() * ws.element_size(), _stream_ptr(stream)),
+           "sfft_surrogate_grad")
+
+
+def sfft_surrogate_adam(handle: Handle, params, grads, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8,
+                        stream=None):
+    _check(lib().sfft_surrogate_adam(handle.ptr, _dp(params), _dp(grads), _dp(m), _dp(v), int(params.numel()),
+                                     int(step), float(lr), float(beta1), float(beta2), float(eps),
+                                     _stream_ptr(stream)),
+           "sfft_surrogate_adam")
+
+
+def sfft_surrogate_destandardize(handle: Handle, pred, mean, scale, n_pairs, n_out, coef, stream=None):
+    _check(lib().sfft_surrogate_destandardize(handle.ptr, _dp(pred), _dp(mean), _dp(scale), int(n_pairs),
+                                              int(n_out), _dp(coef), _stream_ptr(stream)),
+           "sfft_surrogate_destandardize")
+
+
+class Surrogate:
+    """Device state of the learned form: parameters, Adam moments and a
+    workspace sized for batches of up to `max_pairs` pairs of `n_stamps` stamps."""
+
+    def __init__(self, params, n_out, n_stamps=64, max_pairs=32, handle=None, device="cuda"):
+        import torch
+        self.torch = torch
+        self.handle = handle or Handle()
+        self.n_out, self.n_stamps, self.max_pairs = int(n_out), int(n_stamps), int(max_pairs)
+        n = sfft_surrogate_num_params(self.n_out)
+        p = torch.as_tensor(params, dtype=torch.float32)
+        assert p.numel() == n, (p.numel(), n)
+        dev = torch.device(device)
+        self.params = p.to(dev).contiguous()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grads = torch.zeros_like(self.params)
+        self.loss = torch.zeros((1,), dtype=torch.float64, device=dev)
+        self.step = 0
+        nb = sfft_surrogate_workspace_size(self.max_pairs, self.n_stamps, self.n_out)
+        self.ws = torch.empty((nb + 255) // 256 * 256, dtype=torch.uint8, device=dev)
+
+    def forward(self, stamps, pos, n_pairs, precision=SFFT_NET_FP32, out=None, stream=None):
+        out = out if out is not None else self.torch.empty((n_pairs, self.n_out), dtype=self.torch.float32,
+                                                             device=self.params.device)
+        sfft_surrogate_forward(self.handle, self.params, stamps, pos, n_pairs, self.n_stamps, self.n_out,
+                               precision, out, self.ws, stream)
+        return out
+
+    def grad(self, stamps, pos, target, n_pairs, stream=None):
+        sfft_surrogate_grad(self.handle, self.params, stamps, pos, target, n_pairs, self.n_stamps, self.n_out,
+                            self.grads, self.loss, self.ws, stream)
+        return self.grads, self.loss
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        self.step += 1
+        sfft_surrogate_adam(self.handle, self.params, self.grads, self.m, self.v, self.step, lr, beta1, beta2,
+                            eps, stream)
+
+    def train_step(self, stamps, pos, target, n_pairs, lr, stream=None):
+        self.grad(stamps, pos, target, n_pairs, stream)
+        self.adam(lr, stream=stream)
+        return self.loss

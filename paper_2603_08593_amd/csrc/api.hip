@@ -9,6 +9,7 @@
 #include "common.hpp"
 #include "layout.hpp"
 #include "stamps.hpp"
+#include "surrogate.hpp"
 
 namespace sfft {
 
@@ -25,7 +26,20 @@ hipError_t launch_stamps(const sfft_desc& d, const void* R, const void* S, const
                          const Prof* pf, hipStream_t st);
 hipError_t prepare_kernel_attributes();
 hipError_t prepare_solve_attributes();
-void prepare_stamp_attributes();
+hipError_t prepare_stamp_attributes();
+hipError_t prepare_surrogate_attributes();
+hipError_t launch_extract_stamps(const sfft_desc& d, const void* R, const void* S, const int32_t* centers,
+                                 int n, float* stamps, float* pos, hipStream_t st);
+hipError_t launch_surrogate_forward(const float* params, const float* stamps, const float* pos, int n_pairs,
+                                    int n_stamps, int n_out, bool bf16, float* pred, unsigned char* ws,
+                                    hipStream_t st);
+hipError_t launch_surrogate_grad(const float* P, const float* x, const float* pos, const float* target,
+                                 int n_pairs, int n_stamps, int n_out, float* grads, double* loss,
+                                 unsigned char* ws, hipStream_t st);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, int step, float lr, float b1,
+                       float b2, float eps, hipStream_t st);
+hipError_t launch_destandardize(const float* pred, const double* mean, const double* scale, int n_pairs,
+                                int n_out, double* coef, hipStream_t st);
 
 struct Twiddles {
   void* w64 = nullptr;    // cx<double>[n]
@@ -147,7 +161,10 @@ sfft_status sfft_create(sfft_handle* out) {
     return SFFT_ERR_HIP;
   if (prepare_kernel_attributes() != hipSuccess) return SFFT_ERR_HIP;
   if (prepare_solve_attributes() != hipSuccess) return SFFT_ERR_HIP;
-  prepare_stamp_attributes();
+  if (prepare_stamp_attributes() != hipSuccess || prepare_surrogate_attributes() != hipSuccess) {
+    (void)hipGetLastError();
+    return SFFT_ERR_HIP;
+  }
   sfft_handle h = new (std::nothrow) sfft_handle_s();
   if (!h) return SFFT_ERR_INTERNAL;
   h->device = dev;
@@ -274,6 +291,89 @@ sfft_status sfft_build_system_stamps(sfft_handle h, const sfft_desc* d, const vo
   const hipError_t e = launch_stamps(*d, ref, sci, centers, n_stamps, size, G, hv,
                                      static_cast<unsigned char*>(ws), h->num_cus, &h->prof,
                                      static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
+}
+
+// ---- learned form -------------------------------------------------------
+
+static bool net_shape_ok(int32_t n_pairs, int32_t n_stamps, int32_t n_out) {
+  return n_pairs >= 1 && n_pairs <= 4096 && n_stamps >= 1 && n_stamps <= 1024 && n_out >= 1 &&
+         n_out <= 65536 && (int64_t)n_pairs * n_stamps <= (1 << 20);
+}
+
+int64_t sfft_surrogate_num_params(int32_t n_out) {
+  if (n_out < 1 || n_out > 65536) return -1;
+  return net_layout(n_out).total;
+}
+
+sfft_status sfft_surrogate_workspace_size(int32_t n_pairs, int32_t n_stamps, int32_t n_out, size_t* bytes) {
+  if (!bytes || !net_shape_ok(n_pairs, n_stamps, n_out)) return SFFT_ERR_INVALID_ARG;
+  *bytes = net_ws(n_pairs, n_stamps, n_out).total;
+  return SFFT_OK;
+}
+
+sfft_status sfft_extract_stamps(sfft_handle h, const sfft_desc* d, const void* ref, const void* sci,
+                                const int32_t* centers, int32_t n, float* stamps, float* pos,
+                                void* stream) {
+  if (!h) return SFFT_ERR_INVALID_ARG;
+  sfft_status s = validate_core(d);
+  if (s != SFFT_OK) return s;
+  if (!ref || !sci || !centers || !stamps || !pos || n < 1 || n > (1 << 20)) return SFFT_ERR_INVALID_ARG;
+  if (d->width < kNetStamp || d->height < kNetStamp) return SFFT_ERR_INVALID_ARG;
+  if ((s = check_device(h)) != SFFT_OK) return s;
+  const hipError_t e = launch_extract_stamps(*d, ref, sci, centers, n, stamps, pos,
+                                             static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
+}
+
+sfft_status sfft_surrogate_forward(sfft_handle h, const float* params, const float* stamps, const float* pos,
+                                   int32_t n_pairs, int32_t n_stamps, int32_t n_out, int32_t precision,
+                                   float* pred, void* ws, size_t ws_bytes, void* stream) {
+  if (!h || !params || !stamps || !pos || !pred) return SFFT_ERR_INVALID_ARG;
+  if (!net_shape_ok(n_pairs, n_stamps, n_out)) return SFFT_ERR_INVALID_ARG;
+  if (precision != SFFT_NET_FP32 && precision != SFFT_NET_BF16) return SFFT_ERR_INVALID_ARG;
+  sfft_status s;
+  if ((s = check_ws(ws, ws_bytes, net_ws(n_pairs, n_stamps, n_out).total)) != SFFT_OK) return s;
+  if ((s = check_device(h)) != SFFT_OK) return s;
+  const hipError_t e = launch_surrogate_forward(params, stamps, pos, n_pairs, n_stamps, n_out,
+                                                precision == SFFT_NET_BF16, pred,
+                                                static_cast<unsigned char*>(ws), static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
+}
+
+sfft_status sfft_surrogate_grad(sfft_handle h, const float* params, const float* stamps, const float* pos,
+                                const float* target, int32_t n_pairs, int32_t n_stamps, int32_t n_out,
+                                float* grads, double* loss, void* ws, size_t ws_bytes, void* stream) {
+  if (!h || !params || !stamps || !pos || !target || !grads || !loss) return SFFT_ERR_INVALID_ARG;
+  if (!net_shape_ok(n_pairs, n_stamps, n_out)) return SFFT_ERR_INVALID_ARG;
+  sfft_status s;
+  if ((s = check_ws(ws, ws_bytes, net_ws(n_pairs, n_stamps, n_out).total)) != SFFT_OK) return s;
+  if ((s = check_device(h)) != SFFT_OK) return s;
+  const hipError_t e = launch_surrogate_grad(params, stamps, pos, target, n_pairs, n_stamps, n_out, grads, loss,
+                                             static_cast<unsigned char*>(ws), static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
+}
+
+sfft_status sfft_surrogate_adam(sfft_handle h, float* params, const float* grads, float* m, float* v, int64_t n,
+                                int32_t step, float lr, float beta1, float beta2, float eps, void* stream) {
+  if (!h || !params || !grads || !m || !v || n < 1 || step < 1) return SFFT_ERR_INVALID_ARG;
+  if (!(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+    return SFFT_ERR_INVALID_ARG;
+  sfft_status s;
+  if ((s = check_device(h)) != SFFT_OK) return s;
+  const hipError_t e = launch_adam(params, grads, m, v, n, step, lr, beta1, beta2, eps,
+                                   static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
+}
+
+sfft_status sfft_surrogate_destandardize(sfft_handle h, const float* pred, const double* mean,
+                                         const double* scale, int32_t n_pairs, int32_t n_out, double* coef,
+                                         void* stream) {
+  if (!h || !pred || !mean || !scale || !coef || n_pairs < 1 || n_out < 1) return SFFT_ERR_INVALID_ARG;
+  sfft_status s;
+  if ((s = check_device(h)) != SFFT_OK) return s;
+  const hipError_t e = launch_destandardize(pred, mean, scale, n_pairs, n_out, coef,
+                                            static_cast<hipStream_t>(stream));
   return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
 }
 

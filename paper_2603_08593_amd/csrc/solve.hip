@@ -120,7 +120,7 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 // (v_mfma_f64_16x16x4f64): wave w owns rows 16 (w & 3) .. +16 and columns
 // 32 (w >> 2) .. +32 of the result, as two 16 x 16 blocks. Operand lanes:
 // A[l % 16][l / 16], B[l / 16][l % 16]; result lane l, element q:
-// row 4 (l / 16) + q, column l % 16.
+// row l / 16 + 4 q, column l % 16.
 // TRANS_B = true: acc = X Y^T; false: acc = X Y.
 template <bool TRANS_B>
 __device__ __forceinline__ void tile_mma(const double (*X)[kLD], const double (*Y)[kLD],
@@ -146,11 +146,11 @@ __device__ __forceinline__ void tile_sub_abt(double (*C)[kLD], const double (*X)
   double4_t acc[2];
   tile_mma<true>(X, Y, acc);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int i0 = 16 * (w & 3) + 4 * (lane >> 4), j0 = 32 * (w >> 2) + (lane & 15);
+  const int i0 = 16 * (w & 3) + (lane >> 4), j0 = 32 * (w >> 2) + (lane & 15);
 #pragma unroll
   for (int b = 0; b < 2; ++b)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) C[i0 + q][j0 + 16 * b] -= acc[b][q];
+    for (int q = 0; q < 4; ++q) C[i0 + 4 * q][j0 + 16 * b] -= acc[b][q];
   __syncthreads();
 }
 
@@ -160,82 +160,99 @@ __device__ __forceinline__ void tile_mul_ab(double (*C)[kLD], const double (*X)[
   double4_t acc[2];
   tile_mma<false>(X, U, acc);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int i0 = 16 * (w & 3) + 4 * (lane >> 4), j0 = 32 * (w >> 2) + (lane & 15);
+  const int i0 = 16 * (w & 3) + (lane >> 4), j0 = 32 * (w >> 2) + (lane & 15);
 #pragma unroll
   for (int b = 0; b < 2; ++b)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) C[i0 + q][j0 + 16 * b] = acc[b][q];
+    for (int q = 0; q < 4; ++q) C[i0 + 4 * q][j0 + 16 * b] = acc[b][q];
   __syncthreads();
 }
 
-// 1 / sqrt(d) to FP64 accuracy: hardware estimate + two Newton steps
+// 1 / sqrt(d): hardware estimate refined by one Newton step (relative error
+// far below what the iterative refinement corrects)
 __device__ __forceinline__ double rsqrt64(double d) {
-  double y = __builtin_amdgcn_rsq(d);
-  y = y * fma(-0.5 * d * y, y, 1.5);
-  y = y * fma(-0.5 * d * y, y, 1.5);
-  return y;
+  const double y = __builtin_amdgcn_rsq(d);
+  return y * fma(-0.5 * d * y, y, 1.5);
 }
 
 // Cholesky of the 64 x 64 SPD tile T (lower, in place) and U = L^-T into Ut:
 // the right-looking factorisation of the stacked [T; I] turns the identity
-// rows into L^-T (I = Y L^T). Thread (i, q) holds T[i][q + 8m] and the
-// identity row's [i][q + 8m]; column j of both parts is published in colbuf
-// (double-buffered); one barrier per column, no divergent loads.
+// rows into L^-T (I = Y L^T). Thread (i, q) holds T[i][8q + m] and the
+// identity row's [i][8q + m], m = 0..7, so column j lives in wave j / 8,
+// register j % 8: with the inner 8 columns unrolled every register index is
+// a constant and every branch on the column is uniform. Column j of both
+// parts is published in colbuf (double-buffered); one barrier per column.
 // Returns the failing local pivot or -1. colbuf: 4 x 64 doubles.
 __device__ int tile_potrf_aug(double (*T)[kLD], double (*Ut)[kLD], double (*colbuf)[kTile]) {
-  const int i = threadIdx.x & 63, q = threadIdx.x >> 6;     // q in [0, 8)
+  const int i = threadIdx.x & 63;
+  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave index, uniform
   double reg[8], aug[8];
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
-    reg[m] = T[i][q + 8 * m];
-    aug[m] = (i == q + 8 * m) ? 1.0 : 0.0;
+    reg[m] = T[i][8 * q + m];
+    aug[m] = (i == 8 * q + m) ? 1.0 : 0.0;
   }
   __shared__ int fail;
   if (threadIdx.x == 0) fail = -1;
   if (q == 0) { colbuf[0][i] = reg[0]; colbuf[2][i] = aug[0]; }
   __syncthreads();
+  bool ok = true;
 #pragma unroll 1
-  for (int j = 0; j < kTile; ++j) {
-    const int bsel = j & 1;
-    const double* cT = colbuf[bsel];
-    const double* cA = colbuf[2 + bsel];
-    const double d = cT[j];
-    const double ci = cT[i], ai = cA[i];
-    double cl[8];
+  for (int qb = 0; qb < 8 && ok; ++qb) {
 #pragma unroll
-    for (int m = 0; m < 8; ++m) cl[m] = cT[q + 8 * m];
-    if (!(d > 0.0) || !is_finite_d(d)) {     // uniform: every thread read the same pivot
-      if (threadIdx.x == 0) fail = j;
-      break;
-    }
-    const double rs = rsqrt64(d);
-    const double li = ci * rs, yi = ai * rs;
-    const double ljj = (i >= j) ? li : 0.0;
+    for (int jj = 0; jj < 8; ++jj) {
+      const int j = 8 * qb + jj;
+      const int bsel = jj & 1;              // j & 1
+      const double* cT = colbuf[bsel];
+      const double d = cT[j];
+      const double ci = cT[i], ai = colbuf[2 + bsel][i];
+      double cl[8];
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-      const int pcol = q + 8 * m;
-      const double lp = cl[m] * rs;
-      const double nr = fma(-li, lp, reg[m]);
-      const double na = fma(-yi, lp, aug[m]);
-      reg[m] = (pcol > j) ? nr : ((pcol == j) ? ljj : reg[m]);
-      aug[m] = (pcol > j) ? na : ((pcol == j) ? yi : aug[m]);
-    }
-    // owners of column j + 1 publish both parts of it
-    const int jn = j + 1;
-    if (jn < kTile && (jn & 7) == q) {
-      double vr = 0.0, va = 0.0;
+      for (int m = 0; m < 8; ++m) cl[m] = cT[8 * q + m];
+      if (!(d > 0.0) || !is_finite_d(d)) {   // uniform: every thread read the same pivot
+        if (threadIdx.x == 0) fail = j;
+        ok = false;
+        break;
+      }
+      const double rs = rsqrt64(d);
+      const double li = ci * rs, yi = ai * rs;
+      if (q > qb) {
 #pragma unroll
-      for (int m = 0; m < 8; ++m)
-        if (m == (jn >> 3)) { vr = reg[m]; va = aug[m]; }
-      colbuf[bsel ^ 1][i] = vr;
-      colbuf[2 + (bsel ^ 1)][i] = va;
+        for (int m = 0; m < 8; ++m) {
+          const double lp = cl[m] * rs;
+          reg[m] = fma(-li, lp, reg[m]);
+          aug[m] = fma(-yi, lp, aug[m]);
+        }
+      } else if (q == qb) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          if (m > jj) {
+            const double lp = cl[m] * rs;
+            reg[m] = fma(-li, lp, reg[m]);
+            aug[m] = fma(-yi, lp, aug[m]);
+          } else if (m == jj) {
+            reg[m] = (i >= j) ? li : 0.0;
+            aug[m] = yi;
+          }
+        }
+      }
+      // the wave owning column j + 1 publishes both parts of it
+      if (jj < 7) {
+        if (q == qb) {
+          colbuf[bsel ^ 1][i] = reg[(jj + 1) & 7];
+          colbuf[2 + (bsel ^ 1)][i] = aug[(jj + 1) & 7];
+        }
+      } else if (q == qb + 1) {
+        colbuf[bsel ^ 1][i] = reg[0];
+        colbuf[2 + (bsel ^ 1)][i] = aug[0];
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   __syncthreads();
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
-    const int l = q + 8 * m;
+    const int l = 8 * q + m;
     T[i][l] = (l <= i) ? reg[m] : 0.0;
     Ut[i][l] = (l >= i) ? aug[m] : 0.0;
   }

@@ -302,11 +302,12 @@ __global__ __launch_bounds__(256) void k_stamp_finalize(const double* partials, 
   }
 }
 
-void prepare_stamp_attributes() {
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stamp_gram<float>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, kStMaxLds);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stamp_gram<double>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, kStMaxLds);
+hipError_t prepare_stamp_attributes() {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stamp_gram<float>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, kStMaxLds);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stamp_gram<double>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, kStMaxLds);
 }
 
 hipError_t launch_stamps(const sfft_desc& d, const void* R, const void* S, const int32_t* centers,

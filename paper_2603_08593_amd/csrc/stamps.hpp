@@ -8,7 +8,7 @@ namespace sfft {
 constexpr int kStT = 64;                  // Gram tile side
 constexpr int kStThreads = 512;           // 8 waves per workgroup
 constexpr int kStMaxPlanes = 32;          // kernel + background planes + S'
-constexpr int kStMaxLds = 160 * 1024;
+constexpr int kStMaxLds = 159 * 1024;     // dynamic LDS limit (the CU has 160 KiB; static use is small)
 constexpr size_t kStPartialsOffset = 256; // after the status flags
 constexpr int kStMaxSize = 127;
 constexpr int kStMaxStamps = 1 << 16;

@@ -272,14 +272,12 @@ def make_cfg2(index: int = 0, W: int = 2048, H: int = 4096, nstars: int | None =
                      dtype=np.float32)
 
 
-def pick_stamps(pair: Pair, n: int = 64, size: int = 41):
-    """Stamp centres for the stamp-based fit: the n brightest stars at least
-    size//2 + r + 1 px from every edge with no other star brighter than 1% of
-    their flux within `size` px; ties by catalogue index; centre = nearest
-    pixel (round half to even). Returns int32 array (n, 2) of (x, y)."""
-    H, W = pair.R.shape
-    r = (pair.L - 1) // 2
-    xs, ys, fl = pair.meta["xs"], pair.meta["ys"], pair.meta["flux"]
+def pick_centers(xs, ys, fl, W, H, n, size, r):
+    """The n brightest stars at least size//2 + r + 1 px from every edge with
+    no other star brighter than 1% of their flux within `size` px; ties by
+    catalogue index; centre = nearest pixel (round half to even). Returns
+    int32 array (n, 2) of (x, y) (fewer rows if fewer stars qualify)."""
+    xs, ys, fl = np.asarray(xs), np.asarray(ys), np.asarray(fl)
     margin = size // 2 + r + 1
     order = sorted(range(len(fl)), key=lambda k: (-fl[k], k))
     out = []
@@ -296,3 +294,31 @@ def pick_stamps(pair: Pair, n: int = 64, size: int = 41):
         if len(out) == n:
             break
     return np.asarray(out, dtype=np.int32).reshape(-1, 2)
+
+
+def pick_stamps(pair: Pair, n: int = 64, size: int = 41):
+    """Stamp centres of a pair (pick_centers on its catalogue)."""
+    H, W = pair.R.shape
+    return pick_centers(pair.meta["xs"], pair.meta["ys"], pair.meta["flux"], W, H, n, size,
+                        (pair.L - 1) // 2)
+
+
+def surrogate_init(n_out: int, seed: int) -> np.ndarray:
+    """Seeded initial parameters of the learned form's network as one flat
+    FP32 vector, in the layout (conv1..conv4 weight, bias; fc1..fc3 weight,
+    bias): weights uniform in +-sqrt(6 / fan_in) (He), biases zero."""
+    rng = np.random.default_rng(seed)
+    shapes = []
+    for ci, co in ((2, 16), (16, 32), (32, 64), (64, 64)):
+        shapes += [((co, ci, 3, 3), ci * 9), ((co,), 0)]
+    shapes += [((128, 1024), 1024), ((128,), 0), ((512, 768), 768), ((512,), 0),
+               ((n_out, 512), 512), ((n_out,), 0)]
+    parts = []
+    for shape, fan_in in shapes:
+        n = int(np.prod(shape))
+        if fan_in:
+            lim = np.sqrt(6.0 / fan_in)
+            parts.append(rng.uniform(-lim, lim, n))
+        else:
+            parts.append(np.zeros(n))
+    return np.concatenate(parts).astype(np.float32)
