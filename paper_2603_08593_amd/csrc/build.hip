@@ -17,8 +17,14 @@
 // The kernel-background block and the background blocks are exact
 // polynomial moments of R' and S' with periodic seam corrections (they need
 // no transform).
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
 #include "common.hpp"
 #include "layout.hpp"
+#include "batch.hpp"
 
 namespace sfft {
 
@@ -143,7 +149,7 @@ struct RowArgs {
 
 // NQ: row elements per thread, max(1, ceil(W / 256)); MIXED: W has factors 3 or 5
 template <typename T, typename TIN, int NQ, bool MIXED>
-__global__ __launch_bounds__(kRowThreads, 2) void k_row_pass(RowArgs a) {
+__device__ __forceinline__ void row_pass_body(const RowArgs& a, const VB vb) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int W = a.W;
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
@@ -157,7 +163,7 @@ __global__ __launch_bounds__(kRowThreads, 2) void k_row_pass(RowArgs a) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   cx<T>* F = static_cast<cx<T>*>(a.F);
 
-  for (int y = blockIdx.x; y < a.H; y += gridDim.x) {
+  for (int y = vb.x; y < a.H; y += vb.nx) {
     double rp[MAXQ], sp[MAXQ];
     double mr[9], ms[5];
 #pragma unroll
@@ -249,6 +255,19 @@ __global__ __launch_bounds__(kRowThreads, 2) void k_row_pass(RowArgs a) {
   }
 }
 
+template <typename T, typename TIN, int NQ, bool MIXED>
+__global__ __launch_bounds__(kRowThreads, 2) void k_row_pass(RowArgs a) {
+  row_pass_body<T, TIN, NQ, MIXED>(a, vb_grid());
+}
+
+template <typename T, typename TIN, int NQ, bool MIXED>
+__global__ __launch_bounds__(kRowThreads, 2) void k_row_pass_batch(const RowArgs* args, const BatchTab* tab,
+                                                                  int n) {
+  int item;
+  VB vb;
+  if (batch_locate(tab, n, item, vb)) row_pass_body<T, TIN, NQ, MIXED>(args[item], vb);
+}
+
 // ---------------------------------------------------------------------------
 // Column pass: blocked correlation along y for 4 adjacent k_x columns,
 // k_x in [1, W/2). The real k_x = 0 and k_x = W/2 columns are correlated
@@ -290,7 +309,7 @@ constexpr size_t col_pass_shmem() {
 }
 
 template <typename T, int NK>
-__global__ __launch_bounds__(kColThreads) void k_col_pass(ColArgs a) {
+__device__ __forceinline__ void col_pass_body(const ColArgs& a, const VB vb) {
   constexpr int NS = 2 * NK + 1;
   constexpr int NKK = PairCount<NK>::NKK;
   constexpr int NP = PairCount<NK>::NP;
@@ -308,7 +327,7 @@ __global__ __launch_bounds__(kColThreads) void k_col_pass(ColArgs a) {
   // XCD-aware group index: workgroups that share an XCD (id mod 8) take
   // adjacent column groups, so their 64-byte row segments share L2 lines.
   const int per_xcd = (a.ngroups + 7) / 8;
-  const int grp = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  const int grp = (vb.x & 7) * per_xcd + (vb.x >> 3);
   if (grp >= a.ngroups) return;
   const int kx0 = 1 + grp * kColsPerWG;
   const int kxend = a.nkx - 1;               // exclusive: W/2 is done elsewhere
@@ -512,6 +531,18 @@ __global__ __launch_bounds__(kColThreads) void k_col_pass(ColArgs a) {
   }
 }
 
+template <typename T, int NK>
+__global__ __launch_bounds__(kColThreads) void k_col_pass(ColArgs a) {
+  col_pass_body<T, NK>(a, vb_grid());
+}
+
+template <typename T, int NK>
+__global__ __launch_bounds__(kColThreads) void k_col_pass_batch(const ColArgs* args, const BatchTab* tab, int n) {
+  int item;
+  VB vb;
+  if (batch_locate(tab, n, item, vb)) col_pass_body<T, NK>(args[item], vb);
+}
+
 // ---------------------------------------------------------------------------
 // Pruned inverse along x:
 //   C_p(dx, dy) = (1/W) [ c_p(0, dy) + (-1)^dx c_p(W/2, dy)
@@ -529,10 +560,10 @@ struct XinvArgs {
   double sy;
 };
 
-__global__ __launch_bounds__(256) void k_strip_xinv(XinvArgs a) {
+__device__ __forceinline__ void strip_xinv_body(const XinvArgs& a, const VB vb) {
   __shared__ double red[4][34];
   const int ndy = 2 * a.h + 1;
-  const int p = blockIdx.x / ndy, dyi = blockIdx.x % ndy;
+  const int p = vb.x / ndy, dyi = vb.x % ndy;
   const bool ks = p >= a.NKK;
   const int lim = ks ? a.r : a.h;
   if (abs(dyi - a.h) > lim) return;
@@ -610,6 +641,14 @@ __global__ __launch_bounds__(256) void k_strip_xinv(XinvArgs a) {
   }
 }
 
+__global__ __launch_bounds__(256) void k_strip_xinv(XinvArgs a) { strip_xinv_body(a, vb_grid()); }
+
+__global__ __launch_bounds__(256) void k_strip_xinv_batch(const XinvArgs* args, const BatchTab* tab, int n) {
+  int item;
+  VB vb;
+  if (batch_locate(tab, n, item, vb)) strip_xinv_body(args[item], vb);
+}
+
 // ---------------------------------------------------------------------------
 // Polynomial moments
 // ---------------------------------------------------------------------------
@@ -624,12 +663,12 @@ struct MomArgs {
 };
 
 // One workgroup per moment scalar; fixed-order block sums.
-__global__ __launch_bounds__(256) void k_moments(MomArgs a) {
+__device__ __forceinline__ void moments_body(const MomArgs& a, const VB vb) {
   __shared__ double scratch[8];
   const int nm = a.DK + a.DB + 1;
   const int nM2 = nm * nm, nE = 2 * a.r * nm, nMS = (a.DB + 1) * (a.DB + 1);
   const int np = 2 * a.DB + 1;
-  int id = blockIdx.x;
+  int id = vb.x;
   double s = 0.0;
   if (id < nM2) {
     const int m = id / nm, n = id % nm;
@@ -650,7 +689,15 @@ __global__ __launch_bounds__(256) void k_moments(MomArgs a) {
     for (int y = threadIdx.x; y < a.H; y += blockDim.x) s += ipow((double)y * a.sy - 1.0, id);
   }
   s = block_sum(s, scratch);
-  if (threadIdx.x == 0) a.mom[blockIdx.x] = s;
+  if (threadIdx.x == 0) a.mom[vb.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_moments(MomArgs a) { moments_body(a, vb_grid()); }
+
+__global__ __launch_bounds__(256) void k_moments_batch(const MomArgs* args, const BatchTab* tab, int n) {
+  int item;
+  VB vb;
+  if (batch_locate(tab, n, item, vb)) moments_body(args[item], vb);
 }
 
 // ---------------------------------------------------------------------------
@@ -673,7 +720,7 @@ __device__ __forceinline__ double binom(int n, int k) {
   return b;
 }
 
-__global__ __launch_bounds__(256) void k_kb_assemble(KbArgs a) {
+__device__ __forceinline__ void kb_assemble_body(const KbArgs& a, const VB vb) {
   const int L2 = a.L * a.L;
   const int nKL = a.nK * L2;
   const int nm = a.DK + a.DB + 1;
@@ -682,7 +729,7 @@ __global__ __launch_bounds__(256) void k_kb_assemble(KbArgs a) {
   const double* MSy = E + 2 * a.r * nm;
   const double* Px = MSy + (a.DB + 1) * (a.DB + 1);
   const double* Py = Px + 2 * a.DB + 1;
-  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int tid = vb.x * blockDim.x + threadIdx.x;
   const int nkb = nKL * a.nB;
   if (tid < nkb) {
     const int c = tid % a.nB;
@@ -740,6 +787,14 @@ __global__ __launch_bounds__(256) void k_kb_assemble(KbArgs a) {
   }
 }
 
+__global__ __launch_bounds__(256) void k_kb_assemble(KbArgs a) { kb_assemble_body(a, vb_grid()); }
+
+__global__ __launch_bounds__(256) void k_kb_assemble_batch(const KbArgs* args, const BatchTab* tab, int n) {
+  int item;
+  VB vb;
+  if (batch_locate(tab, n, item, vb)) kb_assemble_body(args[item], vb);
+}
+
 // ---------------------------------------------------------------------------
 // Kernel-kernel block and kernel RHS from the correlation lags
 // ---------------------------------------------------------------------------
@@ -755,11 +810,11 @@ __device__ __forceinline__ int pair_index(int i, int j, int nK) {
   return i * nK - i * (i - 1) / 2 + (j - i);
 }
 
-__global__ __launch_bounds__(256) void k_gather_kk(GatherArgs a) {
+__device__ __forceinline__ void gather_kk_body(const GatherArgs& a, const VB vb) {
   const int L2 = a.L * a.L;
   const int nKL = a.nK * L2;
-  const int row = blockIdx.y;
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = vb.y;
+  const int col = vb.x * blockDim.x + threadIdx.x;
   const int ndy = 2 * a.h + 1;
   const int i = row / L2, d = row % L2;
   const int dy = d / a.L - a.r, dx = d % a.L - a.r;
@@ -775,6 +830,14 @@ __global__ __launch_bounds__(256) void k_gather_kk(GatherArgs a) {
     const int p = a.NKK + i;
     a.hv[row] = a.C[((int64_t)p * ndy + (dy + a.h)) * ndy + (dx + a.h)];
   }
+}
+
+__global__ __launch_bounds__(256) void k_gather_kk(GatherArgs a) { gather_kk_body(a, vb_grid()); }
+
+__global__ __launch_bounds__(256) void k_gather_kk_batch(const GatherArgs* args, const BatchTab* tab, int n) {
+  int item;
+  VB vb;
+  if (batch_locate(tab, n, item, vb)) gather_kk_body(args[item], vb);
 }
 
 // ---------------------------------------------------------------------------
@@ -834,15 +897,19 @@ hipError_t prepare_kernel_attributes() {
     set(reinterpret_cast<const void*>(&k_col_pass<float, 1>));
     set(reinterpret_cast<const void*>(&k_col_pass<float, 3>));
     set(reinterpret_cast<const void*>(&k_col_pass<float, 6>));
+    set(reinterpret_cast<const void*>(&k_row_pass_batch<float, float, 8, true>));
+    set(reinterpret_cast<const void*>(&k_col_pass_batch<float, 1>));
+    set(reinterpret_cast<const void*>(&k_col_pass_batch<float, 3>));
+    set(reinterpret_cast<const void*>(&k_col_pass_batch<float, 6>));
     return e;
   }();
   return once;
 }
 
-template <typename T>
-static hipError_t launch_row(const Geometry& g, const sfft_desc& d, const void* R, const void* S,
-                             unsigned char* ws, const Layout& l, const BuildPlan& p,
-                             hipStream_t st) {
+// ---- argument builders (shared by the single-pair and batched launches) ----
+
+static RowArgs make_row_args(const Geometry& g, const sfft_desc& d, const void* R, const void* S,
+                             unsigned char* ws, const Layout& l, const BuildPlan& p) {
   RowArgs a{};
   a.R = R; a.S = S; a.ld = d.ld; a.W = g.W; a.H = g.H; a.DK = g.DK; a.DB = g.DB; a.r = g.r;
   a.plan = make_fft_plan(g.W);
@@ -855,7 +922,74 @@ static hipError_t launch_row(const Geometry& g, const sfft_desc& d, const void* 
   a.flags = reinterpret_cast<int*>(ws + l.flags);
   a.twW = p.twW;
   a.edge = reinterpret_cast<double*>(ws + l.edge);
-  const size_t shmem = sizeof(cx<T>) * (size_t)(g.W + g.W / 8 + g.W) + sizeof(double) * 64;
+  return a;
+}
+
+template <typename T>
+static size_t row_shmem(int W) {
+  return sizeof(cx<T>) * (size_t)(W + W / 8 + W) + sizeof(double) * 64;
+}
+
+static ColArgs make_col_args(const Geometry& g, unsigned char* ws, const Layout& l, const BuildPlan& p) {
+  ColArgs a{};
+  a.F = ws + l.F; a.pitchK = g.pitchK; a.planeK = g.planeK;
+  a.H = g.H; a.nkx = g.nkx; a.h = g.h; a.T = g.T; a.DK = g.DK;
+  a.ngroups = (g.nkx - 2 + kColsPerWG - 1) / kColsPerWG;
+  a.sy = g.H > 1 ? 2.0 / (double)(g.H - 1) : 0.0;
+  a.strips = reinterpret_cast<cx<double>*>(ws + l.strips);
+  a.tw128 = p.tw128;
+  return a;
+}
+
+static int col_grid(const ColArgs& a) { return 8 * ((a.ngroups + 7) / 8); }
+
+static XinvArgs make_xinv_args(const Geometry& g, unsigned char* ws, const Layout& l, const BuildPlan& p) {
+  XinvArgs xa{};
+  xa.strips = reinterpret_cast<const cx<double>*>(ws + l.strips);
+  xa.C = reinterpret_cast<double*>(ws + l.C);
+  xa.twW = static_cast<const cx<double>*>(p.twW64);
+  xa.W = g.W; xa.nkx = g.nkx; xa.h = g.h; xa.r = g.r; xa.NKK = g.NKK; xa.NP = g.NP;
+  xa.H = g.H; xa.nK = g.nK; xa.DK = g.DK;
+  xa.sy = g.H > 1 ? 2.0 / (double)(g.H - 1) : 0.0;
+  xa.edge = reinterpret_cast<const double*>(ws + l.edge);
+  return xa;
+}
+
+static MomArgs make_mom_args(const Geometry& g, unsigned char* ws, const Layout& l) {
+  MomArgs ma{};
+  ma.MR = reinterpret_cast<const double*>(ws + l.MR);
+  ma.MS = reinterpret_cast<const double*>(ws + l.MS);
+  ma.ER = reinterpret_cast<const double*>(ws + l.ER);
+  ma.mom = reinterpret_cast<double*>(ws + l.mom);
+  ma.W = g.W; ma.H = g.H; ma.DK = g.DK; ma.DB = g.DB; ma.r = g.r;
+  ma.sx = g.W > 1 ? 2.0 / (double)(g.W - 1) : 0.0;
+  ma.sy = g.H > 1 ? 2.0 / (double)(g.H - 1) : 0.0;
+  return ma;
+}
+
+static KbArgs make_kb_args(const Geometry& g, const MomArgs& ma, double* G, double* hv) {
+  KbArgs ka{};
+  ka.mom = ma.mom; ka.MR = ma.MR; ka.ER = ma.ER; ka.G = G; ka.hv = hv;
+  ka.W = g.W; ka.H = g.H; ka.L = g.L; ka.r = g.r; ka.DK = g.DK; ka.DB = g.DB;
+  ka.nK = g.nK; ka.nB = g.nB; ka.N = g.N; ka.sx = ma.sx; ka.sy = ma.sy;
+  return ka;
+}
+
+static int kb_grid(const Geometry& g) { return (g.nK * g.L * g.L * g.nB + g.nB * g.nB + 255) / 256; }
+
+static GatherArgs make_gather_args(const Geometry& g, const XinvArgs& xa, double* G, double* hv) {
+  GatherArgs ga{};
+  ga.C = xa.C; ga.G = G; ga.hv = hv; ga.L = g.L; ga.r = g.r; ga.h = g.h;
+  ga.nK = g.nK; ga.NKK = g.NKK; ga.N = g.N;
+  return ga;
+}
+
+template <typename T>
+static hipError_t launch_row(const Geometry& g, const sfft_desc& d, const void* R, const void* S,
+                             unsigned char* ws, const Layout& l, const BuildPlan& p,
+                             hipStream_t st) {
+  const RowArgs a = make_row_args(g, d, R, S, ws, l, p);
+  const size_t shmem = row_shmem<T>(g.W);
   int grid = g.H < 4 * p.num_cus ? g.H : 4 * p.num_cus;
   const bool f32 = d.image_dtype == SFFT_F32;
   const bool mixed = (g.W % 3 == 0) || (g.W % 5 == 0);
@@ -886,16 +1020,8 @@ static hipError_t launch_row(const Geometry& g, const sfft_desc& d, const void* 
 template <typename T, int NK>
 static hipError_t launch_col(const Geometry& g, unsigned char* ws, const Layout& l,
                              const BuildPlan& p, hipStream_t st) {
-  ColArgs a{};
-  a.F = ws + l.F; a.pitchK = g.pitchK; a.planeK = g.planeK;
-  a.H = g.H; a.nkx = g.nkx; a.h = g.h; a.T = g.T; a.DK = g.DK;
-  a.ngroups = (g.nkx - 2 + kColsPerWG - 1) / kColsPerWG;
-  a.sy = g.H > 1 ? 2.0 / (double)(g.H - 1) : 0.0;
-  a.strips = reinterpret_cast<cx<double>*>(ws + l.strips);
-  a.tw128 = p.tw128;
-  const size_t shmem = col_pass_shmem<T, NK>();
-  const int grid = 8 * ((a.ngroups + 7) / 8);
-  hipLaunchKernelGGL((k_col_pass<T, NK>), dim3(grid), dim3(kColThreads), shmem, st, a);
+  const ColArgs a = make_col_args(g, ws, l, p);
+  hipLaunchKernelGGL((k_col_pass<T, NK>), dim3(col_grid(a)), dim3(kColThreads), (col_pass_shmem<T, NK>()), st, a);
   return hipGetLastError();
 }
 
@@ -922,42 +1048,194 @@ hipError_t launch_build(const sfft_desc& d, const void* R, const void* S, double
   }
   prof_end(pf, SFFT_PROF_COL_PASS, st);
   if (e != hipSuccess) return e;
-  XinvArgs xa{};
-  xa.strips = reinterpret_cast<const cx<double>*>(ws + l.strips);
-  xa.C = reinterpret_cast<double*>(ws + l.C);
-  xa.twW = static_cast<const cx<double>*>(p.twW64);
-  xa.W = g.W; xa.nkx = g.nkx; xa.h = g.h; xa.r = g.r; xa.NKK = g.NKK; xa.NP = g.NP;
-  xa.H = g.H; xa.nK = g.nK; xa.DK = g.DK;
-  xa.sy = g.H > 1 ? 2.0 / (double)(g.H - 1) : 0.0;
-  xa.edge = reinterpret_cast<const double*>(ws + l.edge);
+  const XinvArgs xa = make_xinv_args(g, ws, l, p);
   prof_begin(pf, SFFT_PROF_XINV, st);
   hipLaunchKernelGGL(k_strip_xinv, dim3(g.NP * (2 * g.h + 1)), dim3(256), 0, st, xa);
   prof_end(pf, SFFT_PROF_XINV, st);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  MomArgs ma{};
-  ma.MR = reinterpret_cast<const double*>(ws + l.MR);
-  ma.MS = reinterpret_cast<const double*>(ws + l.MS);
-  ma.ER = reinterpret_cast<const double*>(ws + l.ER);
-  ma.mom = reinterpret_cast<double*>(ws + l.mom);
-  ma.W = g.W; ma.H = g.H; ma.DK = g.DK; ma.DB = g.DB; ma.r = g.r;
-  ma.sx = g.W > 1 ? 2.0 / (double)(g.W - 1) : 0.0;
-  ma.sy = g.H > 1 ? 2.0 / (double)(g.H - 1) : 0.0;
+  const MomArgs ma = make_mom_args(g, ws, l);
   hipLaunchKernelGGL(k_moments, dim3(l.nmom), dim3(256), 0, st, ma);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  KbArgs ka{};
-  ka.mom = ma.mom; ka.MR = ma.MR; ka.ER = ma.ER; ka.G = G; ka.hv = hv;
-  ka.W = g.W; ka.H = g.H; ka.L = g.L; ka.r = g.r; ka.DK = g.DK; ka.DB = g.DB;
-  ka.nK = g.nK; ka.nB = g.nB; ka.N = g.N; ka.sx = ma.sx; ka.sy = ma.sy;
-  const int nkb = g.nK * g.L * g.L * g.nB + g.nB * g.nB;
-  hipLaunchKernelGGL(k_kb_assemble, dim3((nkb + 255) / 256), dim3(256), 0, st, ka);
+  const KbArgs ka = make_kb_args(g, ma, G, hv);
+  hipLaunchKernelGGL(k_kb_assemble, dim3(kb_grid(g)), dim3(256), 0, st, ka);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  GatherArgs ga{};
-  ga.C = xa.C; ga.G = G; ga.hv = hv; ga.L = g.L; ga.r = g.r; ga.h = g.h;
-  ga.nK = g.nK; ga.NKK = g.NKK; ga.N = g.N;
+  const GatherArgs ga = make_gather_args(g, xa, G, hv);
   const int nKL = g.nK * g.L * g.L;
   hipLaunchKernelGGL(k_gather_kk, dim3((nKL + 255) / 256, nKL), dim3(256), 0, st, ga);
   prof_end(pf, SFFT_PROF_BUILD, st);
   return hipGetLastError();
 }
+
+// ---------------------------------------------------------------------------
+// Batched build: every phase is one launch over all items of the batch. A
+// flat grid is split into per-item block ranges (BatchTab); the argument
+// structures of every item live in device memory owned by the batch plan.
+// Items share the compute precision (FP32 spectra), the image type (FP32),
+// the kernel degree and a row length of at most 2048 (one row-pass
+// instantiation, radix 2/3/4/5/8).
+// ---------------------------------------------------------------------------
+
+struct BuildBatchHost {
+  int n = 0, nK = 0;
+  std::vector<RowArgs> row;
+  std::vector<ColArgs> col;
+  std::vector<XinvArgs> xinv;
+  std::vector<MomArgs> mom;
+  std::vector<KbArgs> kb;
+  std::vector<GatherArgs> gat;
+  std::vector<int*> flags;
+  std::vector<BatchTab> trow, tcol, txinv, tmom, tkb, tgat;
+  int brow = 0, bcol = 0, bxinv = 0, bmom = 0, bkb = 0, bgat = 0;   // total blocks per phase
+  size_t row_shmem = 0;
+};
+
+struct BuildBatchDev {
+  RowArgs* row;
+  ColArgs* col;
+  XinvArgs* xinv;
+  MomArgs* mom;
+  KbArgs* kb;
+  GatherArgs* gat;
+  int* const* flags;
+  BatchTab *trow, *tcol, *txinv, *tmom, *tkb, *tgat;
+};
+
+struct BuildBatch {
+  BuildBatchHost h;
+  BuildBatchDev d{};
+};
+
+__global__ void k_fill_flags_batch(int* const* flags, int n) {
+  const int i = blockIdx.x;
+  if (i < n && threadIdx.x < 64) flags[i][threadIdx.x] = 0;
+}
+
+static void tab_push(std::vector<BatchTab>& t, int& total, int nx, int ny) {
+  BatchTab b{};
+  b.start = total; b.nx = nx; b.ny = ny;
+  t.push_back(b);
+  total += nx * ny;
+}
+
+static hipError_t plan_build_batch(const BuildItem* items, int n, const BuildPlan* plans, int rows_per_block,
+                                   BuildBatchHost& h) {
+  h = BuildBatchHost{};
+  h.n = n;
+  for (int k = 0; k < n; ++k) {
+    const BuildItem& it = items[k];
+    const Geometry g = make_geometry(it.d);
+    const Layout l = make_layout(g);
+    if (!g.fp32 || it.d.image_dtype != SFFT_F32 || g.W > 2048) return hipErrorInvalidValue;
+    if (k > 0 && g.nK != h.nK) return hipErrorInvalidValue;
+    h.nK = g.nK;
+    h.row.push_back(make_row_args(g, it.d, it.R, it.S, it.ws, l, plans[k]));
+    const int rpb = rows_per_block > 0 ? rows_per_block : 4;
+    tab_push(h.trow, h.brow, (g.H + rpb - 1) / rpb, 1);
+    h.row_shmem = std::max(h.row_shmem, row_shmem<float>(g.W));
+    const ColArgs ca = make_col_args(g, it.ws, l, plans[k]);
+    h.col.push_back(ca);
+    tab_push(h.tcol, h.bcol, col_grid(ca), 1);
+    const XinvArgs xa = make_xinv_args(g, it.ws, l, plans[k]);
+    h.xinv.push_back(xa);
+    tab_push(h.txinv, h.bxinv, g.NP * (2 * g.h + 1), 1);
+    const MomArgs ma = make_mom_args(g, it.ws, l);
+    h.mom.push_back(ma);
+    tab_push(h.tmom, h.bmom, l.nmom, 1);
+    h.kb.push_back(make_kb_args(g, ma, it.G, it.hv));
+    tab_push(h.tkb, h.bkb, kb_grid(g), 1);
+    h.gat.push_back(make_gather_args(g, xa, it.G, it.hv));
+    const int nKL = g.nK * g.L * g.L;
+    tab_push(h.tgat, h.bgat, (nKL + 255) / 256, nKL);
+    h.flags.push_back(reinterpret_cast<int*>(it.ws + l.flags));
+  }
+  return hipSuccess;
+}
+
+hipError_t build_batch_launch(const BuildBatch* b, const Prof* pf, hipStream_t st) {
+  const BuildBatchHost& h = b->h;
+  const BuildBatchDev& d = b->d;
+  hipError_t e;
+  prof_begin(pf, SFFT_PROF_BUILD, st);
+  hipLaunchKernelGGL(k_fill_flags_batch, dim3(h.n), dim3(64), 0, st, d.flags, h.n);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  prof_begin(pf, SFFT_PROF_ROW_PASS, st);
+  hipLaunchKernelGGL((k_row_pass_batch<float, float, 8, true>), dim3(h.brow), dim3(kRowThreads), h.row_shmem,
+                     st, d.row, d.trow, h.n);
+  prof_end(pf, SFFT_PROF_ROW_PASS, st);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  prof_begin(pf, SFFT_PROF_COL_PASS, st);
+  switch (h.nK) {
+    case 1: hipLaunchKernelGGL((k_col_pass_batch<float, 1>), dim3(h.bcol), dim3(kColThreads),
+                               (col_pass_shmem<float, 1>()), st, d.col, d.tcol, h.n); break;
+    case 3: hipLaunchKernelGGL((k_col_pass_batch<float, 3>), dim3(h.bcol), dim3(kColThreads),
+                               (col_pass_shmem<float, 3>()), st, d.col, d.tcol, h.n); break;
+    case 6: hipLaunchKernelGGL((k_col_pass_batch<float, 6>), dim3(h.bcol), dim3(kColThreads),
+                               (col_pass_shmem<float, 6>()), st, d.col, d.tcol, h.n); break;
+    default: return hipErrorInvalidValue;
+  }
+  prof_end(pf, SFFT_PROF_COL_PASS, st);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  prof_begin(pf, SFFT_PROF_XINV, st);
+  hipLaunchKernelGGL(k_strip_xinv_batch, dim3(h.bxinv), dim3(256), 0, st, d.xinv, d.txinv, h.n);
+  prof_end(pf, SFFT_PROF_XINV, st);
+  hipLaunchKernelGGL(k_moments_batch, dim3(h.bmom), dim3(256), 0, st, d.mom, d.tmom, h.n);
+  hipLaunchKernelGGL(k_kb_assemble_batch, dim3(h.bkb), dim3(256), 0, st, d.kb, d.tkb, h.n);
+  hipLaunchKernelGGL(k_gather_kk_batch, dim3(h.bgat), dim3(256), 0, st, d.gat, d.tgat, h.n);
+  prof_end(pf, SFFT_PROF_BUILD, st);
+  return hipGetLastError();
+}
+
+// device copies of the host tables, carved from one allocation
+static size_t dev_bytes(const BuildBatchHost& h) {
+  const size_t n = (size_t)h.n;
+  size_t o = 0;
+  auto add = [&](size_t b) { o = align256(o) + b; };
+  add(n * sizeof(RowArgs)); add(n * sizeof(ColArgs)); add(n * sizeof(XinvArgs)); add(n * sizeof(MomArgs));
+  add(n * sizeof(KbArgs)); add(n * sizeof(GatherArgs)); add(n * sizeof(int*));
+  for (int t = 0; t < 6; ++t) add(n * sizeof(BatchTab));
+  return align256(o);
+}
+
+static hipError_t upload(const BuildBatchHost& h, unsigned char* dev, BuildBatchDev& d) {
+  std::vector<unsigned char> blob(dev_bytes(h));
+  size_t o = 0;
+  auto put = [&](const void* src, size_t b) {
+    o = align256(o);
+    std::memcpy(blob.data() + o, src, b);
+    unsigned char* p = dev + o;
+    o += b;
+    return p;
+  };
+  const size_t n = (size_t)h.n;
+  d.row = reinterpret_cast<RowArgs*>(put(h.row.data(), n * sizeof(RowArgs)));
+  d.col = reinterpret_cast<ColArgs*>(put(h.col.data(), n * sizeof(ColArgs)));
+  d.xinv = reinterpret_cast<XinvArgs*>(put(h.xinv.data(), n * sizeof(XinvArgs)));
+  d.mom = reinterpret_cast<MomArgs*>(put(h.mom.data(), n * sizeof(MomArgs)));
+  d.kb = reinterpret_cast<KbArgs*>(put(h.kb.data(), n * sizeof(KbArgs)));
+  d.gat = reinterpret_cast<GatherArgs*>(put(h.gat.data(), n * sizeof(GatherArgs)));
+  d.flags = reinterpret_cast<int* const*>(put(h.flags.data(), n * sizeof(int*)));
+  d.trow = reinterpret_cast<BatchTab*>(put(h.trow.data(), n * sizeof(BatchTab)));
+  d.tcol = reinterpret_cast<BatchTab*>(put(h.tcol.data(), n * sizeof(BatchTab)));
+  d.txinv = reinterpret_cast<BatchTab*>(put(h.txinv.data(), n * sizeof(BatchTab)));
+  d.tmom = reinterpret_cast<BatchTab*>(put(h.tmom.data(), n * sizeof(BatchTab)));
+  d.tkb = reinterpret_cast<BatchTab*>(put(h.tkb.data(), n * sizeof(BatchTab)));
+  d.tgat = reinterpret_cast<BatchTab*>(put(h.tgat.data(), n * sizeof(BatchTab)));
+  return hipMemcpy(dev, blob.data(), blob.size(), hipMemcpyHostToDevice);
+}
+
+BuildBatch* build_batch_create(const BuildItem* items, int n, const BuildPlan* plans, int rows_per_block,
+                               hipError_t* err) {
+  BuildBatch* b = new (std::nothrow) BuildBatch();
+  if (!b) { *err = hipErrorOutOfMemory; return nullptr; }
+  *err = plan_build_batch(items, n, plans, rows_per_block, b->h);
+  if (*err != hipSuccess) { delete b; return nullptr; }
+  return b;
+}
+
+size_t build_batch_dev_bytes(const BuildBatch* b) { return dev_bytes(b->h); }
+
+hipError_t build_batch_upload(BuildBatch* b, unsigned char* dev) { return upload(b->h, dev, b->d); }
+
+void build_batch_destroy(BuildBatch* b) { delete b; }
 
 }  // namespace sfft

@@ -193,6 +193,42 @@ __device__ __forceinline__ double load_pix(const void* p, int64_t idx) {
   return (double)static_cast<const T*>(p)[idx];
 }
 
+// ---------------------------------------------------------------------------
+// Virtual block index: a kernel body sees (x, y) within its own grid
+// (nx, ny); the single-problem kernel passes blockIdx / gridDim, the batched
+// kernel maps its flat block index to (item, local block) through a table of
+// per-item block ranges.
+// ---------------------------------------------------------------------------
+
+struct VB {
+  int x, y, nx, ny;
+};
+
+__device__ __forceinline__ VB vb_grid() {
+  return VB{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, (int)gridDim.y};
+}
+
+struct BatchTab {
+  int start, nx, ny, pad;   // first flat block of the item, its grid
+};
+
+// Locates the item of flat block blockIdx.x (tab sorted by start, n >= 1).
+// Returns false for blocks past the item's own grid.
+__device__ __forceinline__ bool batch_locate(const BatchTab* tab, int n, int& item, VB& vb) {
+  const int b = (int)blockIdx.x;
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tab[mid].start <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  item = lo;
+  const int local = b - tab[lo].start;
+  const int nx = tab[lo].nx, ny = tab[lo].ny;
+  vb = VB{local % nx, local / nx, nx, ny};
+  return local < nx * ny;
+}
+
 // polynomial monomial tables: exponent pairs of the layout order, up to D = 4
 struct MonoTable {
   int n;

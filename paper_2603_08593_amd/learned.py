@@ -1,0 +1,123 @@
+"""Learned form: training of the coefficient network with the library's own
+forward, backward and Adam kernels, and gated inference with the chi2 judge.
+
+A pair is differenced with the predicted coefficients first; when the
+difference image's reduced chi2 exceeds the threshold (1.05), the full
+build + solve runs and the pair is differenced again with its own fit.
+Every step runs in the HIP library (argument marshalling only here).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import (SFFT_NET_BF16, SFFT_NET_FP32, Differencer, Handle, Surrogate, make_desc,
+               sfft_extract_stamps, sfft_surrogate_destandardize, SFFT_F32, SFFT_F64)
+
+N_STAMPS = 64
+STAMP = 32
+
+
+@dataclass
+class Standardizer:
+    """Per-coefficient affine map between coefficients and network outputs:
+    coef = mean + scale * pred."""
+    mean: np.ndarray
+    scale: np.ndarray
+
+    @staticmethod
+    def fit(thetas: np.ndarray) -> "Standardizer":
+        t = np.asarray(thetas, dtype=np.float64)
+        mean = t.mean(axis=0)
+        scale = t.std(axis=0)
+        scale = np.where(scale > 1e-12 * max(float(np.abs(t).max()), 1e-300), scale, 1.0)
+        return Standardizer(mean, scale)
+
+    def forward(self, thetas):
+        return (np.asarray(thetas, np.float64) - self.mean) / self.scale
+
+
+def save_weights(path, params, std: Standardizer, **meta):
+    np.savez(path, params=np.asarray(params, np.float32), mean=std.mean, scale=std.scale,
+             **{k: np.asarray(v) for k, v in meta.items()})
+
+
+def load_weights(path):
+    z = np.load(path, allow_pickle=False)
+    meta = {k: z[k] for k in z.files if k not in ("params", "mean", "scale")}
+    return z["params"], Standardizer(z["mean"], z["scale"]), meta
+
+
+def train(net: Surrogate, stamps, pos, targets, *, epochs: int, batch: int, lr: float, seed: int = 0,
+          lr_final: float | None = None, log=None):
+    """Adam on mini-batches of pairs. stamps (N, S, 2, 32, 32), pos (N, S, 2),
+    targets (N, n_out) standardised: FP32 device tensors. Cosine learning-rate
+    decay to lr_final. Returns the mean loss of every epoch."""
+    import torch
+    N = stamps.shape[0]
+    rng = np.random.default_rng(seed)
+    steps_per_epoch = N // batch
+    total = epochs * steps_per_epoch
+    lr_final = lr * 0.05 if lr_final is None else lr_final
+    history = []
+    step = 0
+    for ep in range(epochs):
+        perm = torch.from_numpy(rng.permutation(N)).to(stamps.device)
+        acc = torch.zeros((), dtype=torch.float64, device=stamps.device)
+        for k in range(steps_per_epoch):
+            idx = perm[k * batch:(k + 1) * batch]
+            x = stamps.index_select(0, idx).contiguous()
+            p = pos.index_select(0, idx).contiguous()
+            t = targets.index_select(0, idx).contiguous()
+            cur = lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * step / max(total, 1)))
+            loss = net.train_step(x, p, t, batch, cur)
+            acc += loss[0]
+            step += 1
+        history.append(float(acc.item()) / max(steps_per_epoch, 1))
+        if log:
+            log(f"epoch {ep + 1}/{epochs}: train loss {history[-1]:.4f}")
+    return history
+
+
+class GatedDifferencer:
+    """Difference one pair with the network's coefficients, falling back to
+    the full fit when the chi2 judge rejects them."""
+
+    def __init__(self, width, height, L, dk, db, params, std: Standardizer, *, threshold=1.05,
+                 precision=SFFT_NET_BF16, image_dtype="float32", n_stamps=N_STAMPS, device="cuda"):
+        import torch
+        self.torch = torch
+        self.diff = Differencer(width, height, L, dk, db, image_dtype=image_dtype, device=device)
+        self.net = Surrogate(params, self.diff.N, n_stamps=n_stamps, max_pairs=1, handle=self.diff.handle,
+                             device=device)
+        self.threshold = float(threshold)
+        self.precision = precision
+        self.n_stamps = n_stamps
+        dev = torch.device(device)
+        self.mean = torch.as_tensor(std.mean, dtype=torch.float64, device=dev)
+        self.scale = torch.as_tensor(std.scale, dtype=torch.float64, device=dev)
+        self.stamps = torch.empty((n_stamps, 2, STAMP, STAMP), dtype=torch.float32, device=dev)
+        self.pos = torch.empty((n_stamps, 2), dtype=torch.float32, device=dev)
+        self.pred = torch.empty((1, self.diff.N), dtype=torch.float32, device=dev)
+        self.coef_pred = torch.empty((self.diff.N,), dtype=torch.float64, device=dev)
+
+    def predict(self, R, S, centers, stream=None):
+        """Network coefficients for the pair (device FP64 [N]); asynchronous."""
+        d = self.diff
+        sfft_extract_stamps(d.handle, d.desc, R, S, centers, self.stamps, self.pos, stream)
+        self.net.forward(self.stamps, self.pos, 1, precision=self.precision, out=self.pred, stream=stream)
+        sfft_surrogate_destandardize(d.handle, self.pred, self.mean, self.scale, 1, d.N, self.coef_pred, stream)
+        return self.coef_pred
+
+    def run(self, R, S, centers, max_refine=1, stream=None):
+        """Returns (accepted, chi2 of the prediction, final chi2)."""
+        d = self.diff
+        self.predict(R, S, centers, stream)
+        d.subtract(R, S, coef=self.coef_pred, stream=stream)
+        chi_pred = float(d.buf.chi2.item())          # the judge's decision needs the value on the host
+        if chi_pred <= self.threshold:
+            return True, chi_pred, chi_pred
+        d.run(R, S, max_refine=max_refine, stream=stream)
+        return False, chi_pred, float(d.buf.chi2.item())
