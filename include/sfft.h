@@ -156,6 +156,51 @@ sfft_status sfft_subtract(sfft_handle handle, const sfft_desc* desc,
                           void* diff, double* chi2,
                           void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Batched form ------------------------------------------------------
+ * All pairs of an exposure (equal-size CCDs and uneven cutouts, possibly
+ * different L) differenced together: every phase of build, solve and
+ * subtract is one launch over all items (per-item block ranges in one grid;
+ * the solve runs one team of co-resident workgroups per item; the subtract
+ * is one launch per distinct L), and the whole sequence can be captured in
+ * one HIP graph. The row-pass rows per workgroup and the solve team size
+ * come from an autotuner (sfft_batch_tune), remembered per batch
+ * composition and device in the handle and, when the environment variable
+ * SFFT_TUNE_CACHE names a file, across processes.
+ * Restrictions: compute SFFT_COMPUTE_FP32, image_dtype SFFT_F32, width <=
+ * 2048, one DK for all items, n <= number of CUs (else
+ * SFFT_ERR_UNSUPPORTED). Each item carries its own buffers, exactly as the
+ * single-pair calls take them; chi2 is required. */
+typedef struct {
+  sfft_desc desc;
+  const void* ref;
+  const void* sci;
+  void* diff;
+  double* G;
+  double* h;
+  double* coef;
+  sfft_solve_info* info;
+  double* chi2;
+  void* ws;                   /* >= sfft_workspace_size(desc) bytes, 256-byte aligned */
+  size_t ws_bytes;
+} sfft_batch_item;
+
+typedef struct sfft_batch_s* sfft_batch;
+
+/* Validates the items and builds the per-phase tables on the device (blocking
+ * copies; not inside a stream capture). The items array is copied. */
+sfft_status sfft_batch_create(sfft_handle handle, const sfft_batch_item* items, int32_t n,
+                              int32_t max_refine, sfft_batch* out);
+/* build + solve + subtract (+ chi2) of every item, stream-ordered. */
+sfft_status sfft_batch_run(sfft_batch batch, void* stream);
+/* The same, captured into a HIP graph on the first call and replayed
+ * (stream must not be the null stream). */
+sfft_status sfft_batch_run_graph(sfft_batch batch, void* stream);
+/* Times each candidate configuration on the stream (runs the batch several
+ * times; results of the last run are valid), keeps the fastest. Either out
+ * pointer may be NULL. */
+sfft_status sfft_batch_tune(sfft_batch batch, void* stream, int32_t* rows_per_block, int32_t* team);
+sfft_status sfft_batch_destroy(sfft_batch batch);
+
 /* Precision form of the build: the same least-squares problem restricted to
  * the pixels of n_stamps square stamps of side `size` (odd) centred on
  * star pixels (the star-stamp mode of SFFT, paper Sec. 1 and Sec. 2.3.2),

@@ -64,6 +64,22 @@ class SolveInfo(ctypes.Structure):
 
 SOLVE_INFO_BYTES = ctypes.sizeof(SolveInfo)
 
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [
+        ("desc", Desc),
+        ("ref", ctypes.c_void_p),
+        ("sci", ctypes.c_void_p),
+        ("diff", ctypes.c_void_p),
+        ("G", ctypes.c_void_p),
+        ("h", ctypes.c_void_p),
+        ("coef", ctypes.c_void_p),
+        ("info", ctypes.c_void_p),
+        ("chi2", ctypes.c_void_p),
+        ("ws", ctypes.c_void_p),
+        ("ws_bytes", ctypes.c_size_t),
+    ]
+
 # name -> (restype, argtypes)
 _P = ctypes.c_void_p
 _SIGS = {
@@ -82,6 +98,12 @@ _SIGS = {
     "sfft_build_system_stamps": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, ctypes.c_int32,
                                                 ctypes.c_int32, _P, _P, _P, ctypes.c_size_t, _P]),
     "sfft_profile_events": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
+    "sfft_batch_create": (ctypes.c_int, [_P, ctypes.POINTER(BatchItem), ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.POINTER(_P)]),
+    "sfft_batch_run": (ctypes.c_int, [_P, _P]),
+    "sfft_batch_run_graph": (ctypes.c_int, [_P, _P]),
+    "sfft_batch_tune": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "sfft_batch_destroy": (ctypes.c_int, [_P]),
     "sfft_surrogate_num_params": (ctypes.c_int64, [ctypes.c_int32]),
     "sfft_surrogate_workspace_size": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                      ctypes.POINTER(ctypes.c_size_t)]),
@@ -408,3 +430,81 @@ class Surrogate:
         self.grad(stamps, pos, target, n_pairs, stream)
         self.adam(lr, stream=stream)
         return self.loss
+
+
+# ---------------------------------------------------------------------------
+# batched form
+# ---------------------------------------------------------------------------
+
+
+class Batch:
+    """Device buffers and an sfft_batch for a list of pair shapes.
+
+    shapes: list of (width, height, L); dk, db common; FP32 images and
+    FP32 spectra (the batched form's precision)."""
+
+    def __init__(self, shapes, dk=2, db=2, max_refine=1, handle=None, device="cuda"):
+        import torch
+        self.torch = torch
+        self.handle = handle or Handle()
+        dev = torch.device(device)
+        self.items = []
+        self.bufs = []
+        arr = (BatchItem * len(shapes))()
+        for k, (W, H, L) in enumerate(shapes):
+            desc = make_desc(W, H, L, dk, db, image_dtype=SFFT_F32, compute=SFFT_COMPUTE_FP32)
+            N = sfft_num_unknowns(desc)
+            nb = sfft_workspace_size(self.handle, desc)
+            b = Buffers(G=torch.empty((N, N), dtype=torch.float64, device=dev),
+                        h=torch.empty((N,), dtype=torch.float64, device=dev),
+                        coef=torch.empty((N,), dtype=torch.float64, device=dev),
+                        info=torch.zeros((64,), dtype=torch.uint8, device=dev),
+                        diff=torch.empty((H, W), dtype=torch.float32, device=dev),
+                        chi2=torch.zeros((1,), dtype=torch.float64, device=dev),
+                        ws=torch.empty((nb + 255) // 256 * 256, dtype=torch.uint8, device=dev))
+            b.ref = torch.zeros((H, W), dtype=torch.float32, device=dev)
+            b.sci = torch.zeros((H, W), dtype=torch.float32, device=dev)
+            b.desc = desc
+            self.bufs.append(b)
+            it = arr[k]
+            it.desc = desc
+            it.ref, it.sci, it.diff = b.ref.data_ptr(), b.sci.data_ptr(), b.diff.data_ptr()
+            it.G, it.h, it.coef = b.G.data_ptr(), b.h.data_ptr(), b.coef.data_ptr()
+            it.info, it.chi2 = b.info.data_ptr(), b.chi2.data_ptr()
+            it.ws, it.ws_bytes = b.ws.data_ptr(), b.ws.numel()
+        self._arr = arr
+        ptr = _P()
+        _check(lib().sfft_batch_create(self.handle.ptr, arr, len(shapes), int(max_refine), ctypes.byref(ptr)),
+               "sfft_batch_create")
+        self._b = ptr
+
+    def load(self, k, ref, sci):
+        """Copy pair k's images into the batch's resident input buffers."""
+        self.bufs[k].ref.copy_(ref)
+        self.bufs[k].sci.copy_(sci)
+
+    def run(self, stream=None):
+        _check(lib().sfft_batch_run(self._b, _stream_ptr(stream)), "sfft_batch_run")
+
+    def run_graph(self, stream=None):
+        _check(lib().sfft_batch_run_graph(self._b, _stream_ptr(stream)), "sfft_batch_run_graph")
+
+    def tune(self, stream=None):
+        rpb, team = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().sfft_batch_tune(self._b, _stream_ptr(stream), ctypes.byref(rpb), ctypes.byref(team)),
+               "sfft_batch_tune")
+        return int(rpb.value), int(team.value)
+
+    def info(self, k) -> SolveInfo:
+        return read_info(self.bufs[k].info)
+
+    def close(self):
+        if getattr(self, "_b", None):
+            lib().sfft_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,13 +1,21 @@
 // Host side of the C ABI declared in include/sfft.h: handle and plan tables,
 // argument validation, workspace sizing and kernel dispatch.
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <map>
+#include <sstream>
+#include <string>
 #include <mutex>
 #include <new>
 #include <vector>
+#include <algorithm>
 
 #include "common.hpp"
 #include "layout.hpp"
+#include "batch.hpp"
 #include "stamps.hpp"
 #include "surrogate.hpp"
 
@@ -53,6 +61,23 @@ struct sfft_handle_s {
   int num_cus = 0;
   std::map<int, sfft::Twiddles> tw;   // keyed by transform length
   sfft::Prof prof{};                  // timing events per sfft_prof_slot
+  std::map<std::string, std::pair<int, int>> tuned;   // batch key -> (rows per block, solve team)
+  char arch[64] = {0};
+};
+
+struct sfft_batch_s {
+  sfft_handle handle = nullptr;
+  std::vector<sfft_batch_item> items;
+  int max_refine = 2;
+  int rows_per_block = 4, team = 0;
+  std::string key;
+  sfft::BuildBatch* build = nullptr;
+  sfft::SolveBatch* solve = nullptr;
+  sfft::SubBatch* sub = nullptr;
+  void* dev = nullptr;
+  size_t dev_bytes = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -169,6 +194,9 @@ sfft_status sfft_create(sfft_handle* out) {
   if (!h) return SFFT_ERR_INTERNAL;
   h->device = dev;
   h->num_cus = cus;
+  hipDeviceProp_t prop{};
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    std::snprintf(h->arch, sizeof h->arch, "%s", prop.gcnArchName);
   *out = h;
   return SFFT_OK;
 }
@@ -375,6 +403,222 @@ sfft_status sfft_surrogate_destandardize(sfft_handle h, const float* pred, const
   const hipError_t e = launch_destandardize(pred, mean, scale, n_pairs, n_out, coef,
                                             static_cast<hipStream_t>(stream));
   return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
+}
+
+// ---- batched form ---------------------------------------------------------
+
+static void batch_release(sfft_batch b) {
+  if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  if (b->build) { build_batch_destroy(b->build); b->build = nullptr; }
+  if (b->solve) { solve_batch_destroy(b->solve); b->solve = nullptr; }
+  if (b->sub) { sub_batch_destroy(b->sub); b->sub = nullptr; }
+  if (b->dev) { (void)hipFree(b->dev); b->dev = nullptr; }
+  b->dev_bytes = 0;
+}
+
+// (re)build the per-phase tables for the given tunables and upload them
+static sfft_status batch_plan(sfft_batch b, int rows_per_block, int team) {
+  batch_release(b);
+  const int n = (int)b->items.size();
+  std::vector<BuildItem> bi(n);
+  std::vector<SolveItem> si(n);
+  std::vector<SubItem> ui(n);
+  std::vector<BuildPlan> plans(n);
+  for (int k = 0; k < n; ++k) {
+    const sfft_batch_item& it = b->items[k];
+    Twiddles tw, t128;
+    if (get_twiddles(b->handle, it.desc.width, tw) != hipSuccess) return SFFT_ERR_HIP;
+    if (get_twiddles(b->handle, kTP, t128) != hipSuccess) return SFFT_ERR_HIP;
+    plans[k] = BuildPlan{tw.w32, tw.w64, t128.w32, b->handle->num_cus};
+    unsigned char* ws = static_cast<unsigned char*>(it.ws);
+    bi[k] = BuildItem{it.desc, it.ref, it.sci, it.G, it.h, ws};
+    si[k] = SolveItem{it.desc, it.G, it.h, it.coef, it.info, ws};
+    ui[k] = SubItem{it.desc, it.ref, it.sci, it.coef, it.diff, it.chi2, ws};
+  }
+  hipError_t e;
+  b->build = build_batch_create(bi.data(), n, plans.data(), rows_per_block, &e);
+  if (!b->build) return e == hipErrorInvalidValue ? SFFT_ERR_UNSUPPORTED : SFFT_ERR_HIP;
+  b->solve = solve_batch_create(si.data(), n, b->max_refine, team, b->handle->num_cus, &e);
+  if (!b->solve) return e == hipErrorInvalidValue ? SFFT_ERR_UNSUPPORTED : SFFT_ERR_HIP;
+  b->sub = sub_batch_create(ui.data(), n, &e);
+  if (!b->sub) return e == hipErrorInvalidValue ? SFFT_ERR_UNSUPPORTED : SFFT_ERR_HIP;
+  const size_t o1 = align256(build_batch_dev_bytes(b->build));
+  const size_t o2 = o1 + align256(solve_batch_dev_bytes(b->solve));
+  b->dev_bytes = o2 + align256(sub_batch_dev_bytes(b->sub));
+  if (hipMalloc(&b->dev, b->dev_bytes) != hipSuccess) { b->dev = nullptr; return SFFT_ERR_HIP; }
+  unsigned char* d = static_cast<unsigned char*>(b->dev);
+  if (build_batch_upload(b->build, d) != hipSuccess || solve_batch_upload(b->solve, d + o1) != hipSuccess ||
+      sub_batch_upload(b->sub, d + o2) != hipSuccess)
+    return SFFT_ERR_HIP;
+  b->rows_per_block = rows_per_block;
+  b->team = solve_batch_team(b->solve);
+  return SFFT_OK;
+}
+
+static std::string batch_key(sfft_handle h, const std::vector<sfft_batch_item>& items) {
+  std::map<std::string, int> count;
+  for (const auto& it : items) {
+    const sfft_desc& d = it.desc;
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "%dx%d:L%d:DK%d:DB%d:%s", d.width, d.height, d.L, d.dk, d.db,
+                  d.compute == SFFT_COMPUTE_FP32 ? "fp32" : "fp64");
+    count[buf] += 1;
+  }
+  std::ostringstream os;
+  os << h->arch;
+  for (const auto& kv : count) os << "|" << kv.second << "*" << kv.first;
+  return os.str();
+}
+
+static const char* tune_cache_path() { return std::getenv("SFFT_TUNE_CACHE"); }
+
+static bool tune_cache_lookup(sfft_handle h, const std::string& key, int& rpb, int& team) {
+  auto it = h->tuned.find(key);
+  if (it != h->tuned.end()) { rpb = it->second.first; team = it->second.second; return true; }
+  const char* path = tune_cache_path();
+  if (!path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[4096];
+  bool found = false;
+  while (std::fgets(line, sizeof line, f)) {
+    char k[3900];
+    int a = 0, b = 0;
+    if (std::sscanf(line, "%3899s %d %d", k, &a, &b) == 3 && key == k) { rpb = a; team = b; found = true; }
+  }
+  std::fclose(f);
+  if (found) h->tuned[key] = {rpb, team};
+  return found;
+}
+
+static void tune_cache_store(sfft_handle h, const std::string& key, int rpb, int team) {
+  h->tuned[key] = {rpb, team};
+  const char* path = tune_cache_path();
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d %d\n", key.c_str(), rpb, team);
+  std::fclose(f);
+}
+
+sfft_status sfft_batch_create(sfft_handle h, const sfft_batch_item* items, int32_t n, int32_t max_refine,
+                              sfft_batch* out) {
+  if (!h || !items || !out || n < 1 || n > 4096 || max_refine < 0 || max_refine > 8) return SFFT_ERR_INVALID_ARG;
+  *out = nullptr;
+  sfft_status s;
+  if ((s = check_device(h)) != SFFT_OK) return s;
+  for (int k = 0; k < n; ++k) {
+    const sfft_batch_item& it = items[k];
+    if ((s = sfft_validate(&it.desc)) != SFFT_OK) return s;
+    if (!it.ref || !it.sci || !it.diff || !it.G || !it.h || !it.coef || !it.info || !it.chi2)
+      return SFFT_ERR_INVALID_ARG;
+    if (it.diff == it.ref || it.diff == it.sci) return SFFT_ERR_INVALID_ARG;
+    if ((s = check_ws(it.ws, it.ws_bytes, make_layout(make_geometry(it.desc)).total)) != SFFT_OK) return s;
+    if (it.desc.compute != SFFT_COMPUTE_FP32 || it.desc.image_dtype != SFFT_F32 || it.desc.width > 2048)
+      return SFFT_ERR_UNSUPPORTED;
+    if (it.desc.dk != items[0].desc.dk) return SFFT_ERR_UNSUPPORTED;
+  }
+  if (n > h->num_cus) return SFFT_ERR_UNSUPPORTED;     // one solve workgroup per CU at least
+  sfft_batch b = new (std::nothrow) sfft_batch_s();
+  if (!b) return SFFT_ERR_INTERNAL;
+  b->handle = h;
+  b->items.assign(items, items + n);
+  b->max_refine = max_refine;
+  b->key = batch_key(h, b->items);
+  int rpb = 4, team = 0;
+  (void)tune_cache_lookup(h, b->key, rpb, team);
+  if ((s = batch_plan(b, rpb, team)) != SFFT_OK) {
+    batch_release(b);
+    delete b;
+    return s;
+  }
+  *out = b;
+  return SFFT_OK;
+}
+
+static sfft_status batch_launch(sfft_batch b, hipStream_t st, const Prof* pf) {
+  if (build_batch_launch(b->build, pf, st) != hipSuccess) return SFFT_ERR_HIP;
+  if (solve_batch_launch(b->solve, pf, st) != hipSuccess) return SFFT_ERR_HIP;
+  if (sub_batch_launch(b->sub, pf, st) != hipSuccess) return SFFT_ERR_HIP;
+  return SFFT_OK;
+}
+
+sfft_status sfft_batch_run(sfft_batch b, void* stream) {
+  if (!b) return SFFT_ERR_INVALID_ARG;
+  sfft_status s;
+  if ((s = check_device(b->handle)) != SFFT_OK) return s;
+  return batch_launch(b, static_cast<hipStream_t>(stream), &b->handle->prof);
+}
+
+sfft_status sfft_batch_run_graph(sfft_batch b, void* stream) {
+  if (!b || !stream) return SFFT_ERR_INVALID_ARG;
+  sfft_status s;
+  if ((s = check_device(b->handle)) != SFFT_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (!b->exec) {
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return SFFT_ERR_HIP;
+    const sfft_status ls = batch_launch(b, st, nullptr);
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(st, &g);
+    if (ls != SFFT_OK || ce != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      return ls != SFFT_OK ? ls : SFFT_ERR_HIP;
+    }
+    b->graph = g;
+    if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+      b->exec = nullptr;
+      return SFFT_ERR_HIP;
+    }
+  }
+  return hipGraphLaunch(b->exec, st) == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
+}
+
+// Autotuner: times the whole batch for each candidate (row-pass rows per
+// workgroup x solve team size) with events on the stream, keeps the fastest,
+// and records it in the handle (and in $SFFT_TUNE_CACHE when set).
+sfft_status sfft_batch_tune(sfft_batch b, void* stream, int32_t* rows_per_block, int32_t* team) {
+  if (!b) return SFFT_ERR_INVALID_ARG;
+  sfft_status s;
+  if ((s = check_device(b->handle)) != SFFT_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int n = (int)b->items.size();
+  const int cus = b->handle->num_cus > 0 ? b->handle->num_cus : 256;
+  std::vector<int> teams;
+  for (int t = 1; t <= 64 && t * n <= cus; t *= 2) teams.push_back(t);
+  if (cus / n > 0 && (teams.empty() || teams.back() != std::min(64, cus / n))) teams.push_back(std::min(64, cus / n));
+  const int rpbs[] = {2, 4, 8, 16};
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return SFFT_ERR_HIP;
+  float best = 1e30f;
+  int brpb = 4, bteam = teams.empty() ? 1 : teams.back();
+  for (int rpb : rpbs)
+    for (int t : teams) {
+      if ((s = batch_plan(b, rpb, t)) != SFFT_OK) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return s; }
+      float ms = 0.f;
+      for (int rep = 0; rep < 2; ++rep) {
+        (void)hipEventRecord(e0, st);
+        if ((s = batch_launch(b, st, nullptr)) != SFFT_OK) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return s; }
+        (void)hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return SFFT_ERR_HIP; }
+        (void)hipEventElapsedTime(&ms, e0, e1);
+      }
+      if (ms < best) { best = ms; brpb = rpb; bteam = t; }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if ((s = batch_plan(b, brpb, bteam)) != SFFT_OK) return s;
+  tune_cache_store(b->handle, b->key, brpb, bteam);
+  if (rows_per_block) *rows_per_block = brpb;
+  if (team) *team = bteam;
+  return SFFT_OK;
+}
+
+sfft_status sfft_batch_destroy(sfft_batch b) {
+  if (!b) return SFFT_ERR_INVALID_ARG;
+  batch_release(b);
+  delete b;
+  return SFFT_OK;
 }
 
 sfft_status sfft_profile_events(sfft_handle h, int32_t slot, void* start_event, void* stop_event) {

@@ -26,4 +26,39 @@ hipError_t build_batch_upload(BuildBatch* b, unsigned char* dev);
 hipError_t build_batch_launch(const BuildBatch* b, const Prof* pf, hipStream_t st);
 void build_batch_destroy(BuildBatch* b);
 
+struct SolveItem {
+  sfft_desc d;
+  const double* G;
+  const double* h;
+  double* coef;
+  sfft_solve_info* info;
+  unsigned char* ws;
+};
+
+struct SolveBatch;
+SolveBatch* solve_batch_create(const SolveItem* items, int n, int max_refine, int P, int num_cus,
+                               hipError_t* err);
+size_t solve_batch_dev_bytes(const SolveBatch* b);
+hipError_t solve_batch_upload(SolveBatch* b, unsigned char* dev);
+hipError_t solve_batch_launch(const SolveBatch* b, const Prof* pf, hipStream_t st);
+int solve_batch_team(const SolveBatch* b);
+void solve_batch_destroy(SolveBatch* b);
+
+struct SubItem {
+  sfft_desc d;
+  const void* R;
+  const void* S;
+  const double* coef;
+  void* D;
+  double* chi2;
+  unsigned char* ws;
+};
+
+struct SubBatch;
+SubBatch* sub_batch_create(const SubItem* items, int n, hipError_t* err);
+size_t sub_batch_dev_bytes(const SubBatch* b);
+hipError_t sub_batch_upload(SubBatch* b, unsigned char* dev);
+hipError_t sub_batch_launch(const SubBatch* b, const Prof* pf, hipStream_t st);
+void sub_batch_destroy(SubBatch* b);
+
 }  // namespace sfft

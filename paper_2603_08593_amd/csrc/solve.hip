@@ -18,6 +18,10 @@
 // Workgroups synchronise through a flag barrier (one arrival flag per
 // workgroup, one release flag) with bounded spins: a timeout is reported in
 // the status instead of hanging.
+#include <new>
+#include <vector>
+
+#include "batch.hpp"
 #include "common.hpp"
 #include "layout.hpp"
 
@@ -53,14 +57,15 @@ struct PSArgs {
 // iteration. Spins are bounded; a timeout is recorded in flags[2].
 struct Barrier {
   unsigned gen = 0;
+  int bid = 0;        // workgroup index within the solve's team
   __device__ void wait(const PSArgs& a) {
     __syncthreads();
     ++gen;
     if (threadIdx.x == 0) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      __hip_atomic_store(&a.sync[blockIdx.x], gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&a.sync[bid], gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (blockIdx.x == 0) {
+    if (bid == 0) {
       if (threadIdx.x < a.P) {
         long spins = 0;
         while (__hip_atomic_load(&a.sync[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
@@ -83,7 +88,7 @@ struct Barrier {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
-    if (blockIdx.x == 0 && threadIdx.x == 0 && a.stamps && gen < 256)
+    if (bid == 0 && threadIdx.x == 0 && a.stamps && gen < 256)
       a.stamps[gen] = __builtin_amdgcn_s_memrealtime();
   }
 };
@@ -291,11 +296,11 @@ __device__ __forceinline__ void store_tile_r(const double (*T)[kLD], double* A, 
 
 // out_i = sum_j U[i][j] in_j with U = L^-T stored in the identity rows
 // (upper triangular: j >= i); one row per wave.
-__device__ void gemv_upper(const PSArgs& a, const double* in, double* out) {
+__device__ void gemv_upper(const PSArgs& a, const double* in, double* out, int bid) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nw = kPT / 64;
   const double* U = a.A + ((int64_t)a.Np + kTile) * a.Np;
-  for (int i = blockIdx.x * nw + wave; i < a.Np; i += a.P * nw) {
+  for (int i = bid * nw + wave; i < a.Np; i += a.P * nw) {
     const double* Ur = U + (int64_t)i * a.Np;
     double acc = 0.0;
     for (int j = (i & ~63) + lane; j < a.Np; j += 64) acc = fma(Ur[j], in[j], acc);
@@ -305,9 +310,9 @@ __device__ void gemv_upper(const PSArgs& a, const double* in, double* out) {
 }
 
 // out_j = sum_i U[i][j] in_i (U^T = L^-1, lower): one column per thread
-__device__ void gemv_upper_t(const PSArgs& a, const double* in, double* out) {
+__device__ void gemv_upper_t(const PSArgs& a, const double* in, double* out, int bid) {
   const double* U = a.A + ((int64_t)a.Np + kTile) * a.Np;
-  for (int j = blockIdx.x * kPT + threadIdx.x; j < a.Np; j += a.P * kPT) {
+  for (int j = bid * kPT + threadIdx.x; j < a.Np; j += a.P * kPT) {
     double acc = 0.0;
     const int iend = j + 1;
     int i = 0;
@@ -325,10 +330,10 @@ __device__ void gemv_upper_t(const PSArgs& a, const double* in, double* out) {
 }
 
 // r = D (h - G theta), one row per wave, rows spread over all workgroups
-__device__ void residual(const PSArgs& a) {
+__device__ void residual(const PSArgs& a, int bid) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nw = kPT / 64;
-  for (int i = blockIdx.x * nw + wave; i < a.Np; i += a.P * nw) {
+  for (int i = bid * nw + wave; i < a.Np; i += a.P * nw) {
     if (i >= a.N) {
       if (lane == 0) a.r[i] = 0.0;
       continue;
@@ -341,7 +346,7 @@ __device__ void residual(const PSArgs& a) {
   }
 }
 
-__global__ __launch_bounds__(kPT) void k_solve_persistent(PSArgs a) {
+__device__ __forceinline__ void solve_body(const PSArgs& a, const int bid) {
   extern __shared__ __align__(16) double smem[];
   double (*T0)[kLD] = reinterpret_cast<double (*)[kLD]>(smem);
   double (*T1)[kLD] = reinterpret_cast<double (*)[kLD]>(smem + kTile * kLD);
@@ -349,8 +354,8 @@ __global__ __launch_bounds__(kPT) void k_solve_persistent(PSArgs a) {
   double (*colbuf)[kTile] = reinterpret_cast<double (*)[kTile]>(smem + 3 * kTile * kLD);
   __shared__ double red[kPT / 64];
   Barrier bar;
+  bar.bid = bid;
   const int N = a.N, Np = a.Np, nt = a.nt, P = a.P;
-  const int bid = blockIdx.x;
   double* v = a.A + (int64_t)Np * Np;                     // row Np: v, then z
   double* U = a.A + ((int64_t)Np + kTile) * Np;           // identity rows, then L^-T
 
@@ -486,21 +491,21 @@ __global__ __launch_bounds__(kPT) void k_solve_persistent(PSArgs a) {
   const bool bad = failed(a);
   // ---- x = L^-T z, theta = D x, refinement
   if (!bad) {
-    gemv_upper(a, v, a.x);
+    gemv_upper(a, v, a.x, bid);
     bar.wait(a);
     for (int i = bid * kPT + threadIdx.x; i < Np; i += P * kPT) a.theta[i] = a.s[i] * a.x[i];
     bar.wait(a);
     for (int it = 0; it < a.refine; ++it) {
-      residual(a);                       // r = D (h - G theta)
+      residual(a, bid);                  // r = D (h - G theta)
       bar.wait(a);
-      gemv_upper_t(a, a.r, a.x);         // x = L^-1 r
+      gemv_upper_t(a, a.r, a.x, bid);    // x = L^-1 r
       bar.wait(a);
-      gemv_upper(a, a.x, a.r);           // r = L^-T x
+      gemv_upper(a, a.x, a.r, bid);      // r = L^-T x
       bar.wait(a);
       for (int i = bid * kPT + threadIdx.x; i < Np; i += P * kPT) a.theta[i] += a.s[i] * a.r[i];
       bar.wait(a);
     }
-    residual(a);
+    residual(a, bid);
     bar.wait(a);
   }
   // ---- final report (workgroup 0)
@@ -556,6 +561,13 @@ __global__ __launch_bounds__(kPT) void k_solve_persistent(PSArgs a) {
   }
 }
 
+__global__ __launch_bounds__(kPT) void k_solve_persistent(PSArgs a) { solve_body(a, blockIdx.x); }
+
+// one team of P co-resident workgroups per item (every item planned with the same P)
+__global__ __launch_bounds__(kPT) void k_solve_batch(const PSArgs* args, int P) {
+  solve_body(args[blockIdx.x / P], blockIdx.x % P);
+}
+
 // clears the arrival / release flags and the barrier time stamps
 __global__ void k_solve_reset(unsigned* sync, int nsync, int* flags) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -574,13 +586,15 @@ int solve_workgroups(int nt) {
 }
 
 hipError_t prepare_solve_attributes() {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_solve_persistent),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_solve_persistent),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)solve_shmem_bytes());
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_solve_batch),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)solve_shmem_bytes());
 }
 
-hipError_t launch_solve(const sfft_desc& d, const double* G, const double* h, double* coef,
-                        int max_refine, sfft_solve_info* info, unsigned char* ws,
-                        const Prof* pf, hipStream_t st) {
+static PSArgs make_solve_args(const sfft_desc& d, const double* G, const double* h, double* coef,
+                              int max_refine, sfft_solve_info* info, unsigned char* ws, int P) {
   const Geometry g = make_geometry(d);
   const Layout l = make_layout(g);
   PSArgs a{};
@@ -596,7 +610,14 @@ hipError_t launch_solve(const sfft_desc& d, const double* G, const double* h, do
   a.stamps = reinterpret_cast<unsigned long long*>(ws + l.sync + 512);
   a.flags = reinterpret_cast<int*>(ws + l.flags);
   a.N = g.N; a.nt = l.nt; a.Np = l.nt * kTile; a.refine = max_refine;
-  a.P = solve_workgroups(l.nt);
+  a.P = P > 0 ? P : solve_workgroups(l.nt);
+  return a;
+}
+
+hipError_t launch_solve(const sfft_desc& d, const double* G, const double* h, double* coef,
+                        int max_refine, sfft_solve_info* info, unsigned char* ws,
+                        const Prof* pf, hipStream_t st) {
+  PSArgs a = make_solve_args(d, G, h, coef, max_refine, info, ws, 0);
   prof_begin(pf, SFFT_PROF_SOLVE, st);
   hipLaunchKernelGGL(k_solve_reset, dim3(1), dim3(640), 0, st, a.sync, 640, a.flags);
   hipError_t e = hipGetLastError();
@@ -607,5 +628,63 @@ hipError_t launch_solve(const sfft_desc& d, const double* G, const double* h, do
   prof_end(pf, SFFT_PROF_SOLVE, st);
   return e;
 }
+
+// ---- batched solve: n teams of P workgroups in one launch ----
+
+__global__ void k_solve_reset_batch(const PSArgs* args) {
+  const PSArgs& a = args[blockIdx.x];
+  for (int i = threadIdx.x; i < 640; i += blockDim.x) a.sync[i] = 0u;
+  if (threadIdx.x == 0) { a.flags[1] = 0; a.flags[2] = 0; }
+}
+
+struct SolveBatch {
+  std::vector<PSArgs> args;
+  PSArgs* dev = nullptr;
+  int P = 1;
+};
+
+// Team size: every team must be co-resident (one solve workgroup per CU),
+// so n * P <= number of CUs.
+SolveBatch* solve_batch_create(const SolveItem* items, int n, int max_refine, int P, int num_cus,
+                               hipError_t* err) {
+  const int cus = num_cus > 0 ? num_cus : 256;
+  if (P <= 0) P = cus / n;
+  if (P > 64) P = 64;
+  if (P < 1 || (int64_t)P * n > cus) { *err = hipErrorInvalidValue; return nullptr; }
+  SolveBatch* b = new (std::nothrow) SolveBatch();
+  if (!b) { *err = hipErrorOutOfMemory; return nullptr; }
+  b->P = P;
+  for (int k = 0; k < n; ++k) {
+    const SolveItem& it = items[k];
+    b->args.push_back(make_solve_args(it.d, it.G, it.h, it.coef, max_refine, it.info, it.ws, P));
+  }
+  *err = hipSuccess;
+  return b;
+}
+
+size_t solve_batch_dev_bytes(const SolveBatch* b) { return align256(b->args.size() * sizeof(PSArgs)); }
+
+hipError_t solve_batch_upload(SolveBatch* b, unsigned char* dev) {
+  b->dev = reinterpret_cast<PSArgs*>(dev);
+  return hipMemcpy(dev, b->args.data(), b->args.size() * sizeof(PSArgs), hipMemcpyHostToDevice);
+}
+
+hipError_t solve_batch_launch(const SolveBatch* b, const Prof* pf, hipStream_t st) {
+  const int n = (int)b->args.size();
+  prof_begin(pf, SFFT_PROF_SOLVE, st);
+  hipLaunchKernelGGL(k_solve_reset_batch, dim3(n), dim3(256), 0, st, (const PSArgs*)b->dev);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // a plain launch (capturable in a graph): n * P <= CUs with one workgroup
+  // per CU keeps every team resident; the barrier spins are bounded anyway
+  hipLaunchKernelGGL(k_solve_batch, dim3(n * b->P), dim3(kPT), solve_shmem_bytes(), st,
+                     (const PSArgs*)b->dev, b->P);
+  prof_end(pf, SFFT_PROF_SOLVE, st);
+  return hipGetLastError();
+}
+
+int solve_batch_team(const SolveBatch* b) { return b->P; }
+
+void solve_batch_destroy(SolveBatch* b) { delete b; }
 
 }  // namespace sfft

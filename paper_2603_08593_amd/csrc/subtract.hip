@@ -8,6 +8,11 @@
 // formed once per (tap, input row) and shared by a thread's 8 pixels.
 // Output tiles of 64 x 16 pixels; the reference tile with an r-pixel halo is
 // staged in LDS in FP64; accumulation in FP64.
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "batch.hpp"
 #include "common.hpp"
 #include "layout.hpp"
 
@@ -30,7 +35,7 @@ __device__ __forceinline__ int mono_index(int a, int b) {
 }
 
 template <int L, int DK, typename TIO>
-__global__ __launch_bounds__(128) void k_subtract(SubArgs a) {
+__device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
   constexpr int r = (L - 1) / 2;
   constexpr int NK = (DK + 1) * (DK + 2) / 2;
   constexpr int TX = kSubTX, TY = kSubTY, P = 8;
@@ -43,7 +48,7 @@ __global__ __launch_bounds__(128) void k_subtract(SubArgs a) {
   __shared__ double K2[(2 * DK + 1) * (2 * DK + 1)];
   const int tid = threadIdx.x;
   const int W = a.W, H = a.H;
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  const int x0 = vb.x * TX, y0 = vb.y * TY;
   for (int i = tid; i < NK * L * L; i += 128) cs[i] = a.coef[i];
   __syncthreads();
   if (a.want_chi2) {
@@ -187,8 +192,20 @@ __global__ __launch_bounds__(128) void k_subtract(SubArgs a) {
     chi = wave_sum(chi);
     if ((tid & 63) == 0) red[tid >> 6] = chi;
     __syncthreads();
-    if (tid == 0) a.partials[blockIdx.y * gridDim.x + blockIdx.x] = red[0] + red[1];
+    if (tid == 0) a.partials[vb.y * vb.nx + vb.x] = red[0] + red[1];
   }
+}
+
+template <int L, int DK, typename TIO>
+__global__ __launch_bounds__(128) void k_subtract(SubArgs a) {
+  subtract_body<L, DK, TIO>(a, vb_grid());
+}
+
+template <int L, int DK, typename TIO>
+__global__ __launch_bounds__(128) void k_subtract_batch(const SubArgs* args, const BatchTab* tab, int n) {
+  int item;
+  VB vb;
+  if (batch_locate(tab, n, item, vb)) subtract_body<L, DK, TIO>(args[item], vb);
 }
 
 __global__ __launch_bounds__(1024) void k_chi2_final(const double* partials, int n, double dof,
@@ -218,18 +235,31 @@ static hipError_t launch_sub_l(const SubArgs& a, int DK, bool f32, dim3 grid, hi
   }
 }
 
-hipError_t launch_subtract(const sfft_desc& d, const void* R, const void* S, const double* coef,
-                           void* D, double* chi2, unsigned char* ws, const Prof* pf,
-                           hipStream_t st) {
+static SubArgs make_sub_args(const sfft_desc& d, const void* R, const void* S, const double* coef, void* D,
+                             bool want_chi2, unsigned char* ws) {
   const Geometry g = make_geometry(d);
   const Layout l = make_layout(g);
   SubArgs a{};
   a.R = R; a.S = S; a.D = D; a.ld = d.ld; a.coef = coef;
   a.partials = reinterpret_cast<double*>(ws + l.partials);
-  a.W = g.W; a.H = g.H; a.N = g.N; a.DB = g.DB; a.want_chi2 = chi2 != nullptr;
+  a.W = g.W; a.H = g.H; a.N = g.N; a.DB = g.DB; a.want_chi2 = want_chi2;
   a.cR = d.ref_pedestal; a.cS = d.sci_pedestal;
   a.sx = g.W > 1 ? 2.0 / (double)(g.W - 1) : 0.0;
   a.sy = g.H > 1 ? 2.0 / (double)(g.H - 1) : 0.0;
+  return a;
+}
+
+static double chi2_dof(const Geometry& g) {
+  const double inner = (double)(g.W - 2 * g.r) * (double)(g.H - 2 * g.r);
+  return inner - (double)g.N;
+}
+
+hipError_t launch_subtract(const sfft_desc& d, const void* R, const void* S, const double* coef,
+                           void* D, double* chi2, unsigned char* ws, const Prof* pf,
+                           hipStream_t st) {
+  const Geometry g = make_geometry(d);
+  const Layout l = make_layout(g);
+  const SubArgs a = make_sub_args(d, R, S, coef, D, chi2 != nullptr, ws);
   hipError_t e;
   const dim3 grid((g.W + kSubTX - 1) / kSubTX, (g.H + kSubTY - 1) / kSubTY);
   const bool f32 = d.image_dtype == SFFT_F32;
@@ -248,14 +278,156 @@ hipError_t launch_subtract(const sfft_desc& d, const void* R, const void* S, con
   prof_end(pf, SFFT_PROF_SUBTRACT, st);
   if (e != hipSuccess) return e;
   if (chi2) {
-    const int r = g.r;
-    const double inner = (double)(g.W - 2 * r) * (double)(g.H - 2 * r);
-    const double dof = inner - (double)g.N;
     hipLaunchKernelGGL(k_chi2_final, dim3(1), dim3(1024), 0, st,
-                       (const double*)a.partials, l.npartials, dof, chi2);
+                       (const double*)a.partials, l.npartials, chi2_dof(g), chi2);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
 }
+
+// ---- batched subtract: one launch per kernel size L in the batch (the
+// kernel-size loop is unrolled at compile time), then one chi2 launch ----
+
+struct Chi2Item {
+  const double* partials;
+  double* out;
+  double dof;
+  int n;
+};
+
+__global__ __launch_bounds__(1024) void k_chi2_final_batch(const Chi2Item* items) {
+  __shared__ double scratch[16];
+  const Chi2Item& it = items[blockIdx.x];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < it.n; i += blockDim.x) s += it.partials[i];
+  s = block_sum(s, scratch);
+  if (threadIdx.x == 0) *it.out = s / it.dof;
+}
+
+struct SubBatch {
+  int n = 0, DK = 0;
+  bool f32 = true;
+  std::vector<int> Ls;                       // distinct kernel sizes
+  std::vector<std::vector<SubArgs>> args;    // per size
+  std::vector<std::vector<BatchTab>> tabs;   // per size
+  std::vector<int> blocks;                   // per size
+  std::vector<Chi2Item> chi;
+  std::vector<SubArgs*> dargs;
+  std::vector<BatchTab*> dtabs;
+  Chi2Item* dchi = nullptr;
+};
+
+SubBatch* sub_batch_create(const SubItem* items, int n, hipError_t* err) {
+  SubBatch* b = new (std::nothrow) SubBatch();
+  if (!b) { *err = hipErrorOutOfMemory; return nullptr; }
+  b->n = n;
+  for (int k = 0; k < n; ++k) {
+    const SubItem& it = items[k];
+    const Geometry g = make_geometry(it.d);
+    const bool f32 = it.d.image_dtype == SFFT_F32;
+    if ((k > 0 && (g.DK != b->DK || f32 != b->f32)) || !it.chi2) {
+      delete b;
+      *err = hipErrorInvalidValue;
+      return nullptr;
+    }
+    b->DK = g.DK;
+    b->f32 = f32;
+    int slot = -1;
+    for (size_t q = 0; q < b->Ls.size(); ++q)
+      if (b->Ls[q] == g.L) slot = (int)q;
+    if (slot < 0) {
+      slot = (int)b->Ls.size();
+      b->Ls.push_back(g.L);
+      b->args.emplace_back();
+      b->tabs.emplace_back();
+      b->blocks.push_back(0);
+    }
+    b->args[slot].push_back(make_sub_args(it.d, it.R, it.S, it.coef, it.D, true, it.ws));
+    BatchTab t{};
+    t.start = b->blocks[slot];
+    t.nx = (g.W + kSubTX - 1) / kSubTX;
+    t.ny = (g.H + kSubTY - 1) / kSubTY;
+    b->tabs[slot].push_back(t);
+    b->blocks[slot] += t.nx * t.ny;
+    const Layout l = make_layout(g);
+    Chi2Item c{};
+    c.partials = reinterpret_cast<const double*>(it.ws + l.partials);
+    c.out = it.chi2;
+    c.dof = chi2_dof(g);
+    c.n = l.npartials;
+    b->chi.push_back(c);
+  }
+  *err = hipSuccess;
+  return b;
+}
+
+size_t sub_batch_dev_bytes(const SubBatch* b) {
+  size_t o = 0;
+  for (size_t q = 0; q < b->Ls.size(); ++q) {
+    o = align256(o) + b->args[q].size() * sizeof(SubArgs);
+    o = align256(o) + b->tabs[q].size() * sizeof(BatchTab);
+  }
+  o = align256(o) + b->chi.size() * sizeof(Chi2Item);
+  return align256(o);
+}
+
+hipError_t sub_batch_upload(SubBatch* b, unsigned char* dev) {
+  std::vector<unsigned char> blob(sub_batch_dev_bytes(b));
+  size_t o = 0;
+  auto put = [&](const void* src, size_t bytes) {
+    o = align256(o);
+    std::memcpy(blob.data() + o, src, bytes);
+    unsigned char* p = dev + o;
+    o += bytes;
+    return p;
+  };
+  b->dargs.clear();
+  b->dtabs.clear();
+  for (size_t q = 0; q < b->Ls.size(); ++q) {
+    b->dargs.push_back(reinterpret_cast<SubArgs*>(put(b->args[q].data(), b->args[q].size() * sizeof(SubArgs))));
+    b->dtabs.push_back(reinterpret_cast<BatchTab*>(put(b->tabs[q].data(), b->tabs[q].size() * sizeof(BatchTab))));
+  }
+  b->dchi = reinterpret_cast<Chi2Item*>(put(b->chi.data(), b->chi.size() * sizeof(Chi2Item)));
+  return hipMemcpy(dev, blob.data(), blob.size(), hipMemcpyHostToDevice);
+}
+
+template <int L>
+static void sub_batch_l(const SubBatch* b, int q, hipStream_t st) {
+  const int n = (int)b->args[q].size();
+  const dim3 grid(b->blocks[q]);
+#define SFFT_SB(DKV)                                                                                 \
+  do {                                                                                               \
+    if (b->f32) hipLaunchKernelGGL((k_subtract_batch<L, DKV, float>), grid, dim3(128), 0, st,        \
+                                   (const SubArgs*)b->dargs[q], (const BatchTab*)b->dtabs[q], n);     \
+    else hipLaunchKernelGGL((k_subtract_batch<L, DKV, double>), grid, dim3(128), 0, st,              \
+                            (const SubArgs*)b->dargs[q], (const BatchTab*)b->dtabs[q], n);            \
+  } while (0)
+  if (b->DK == 0) SFFT_SB(0);
+  else if (b->DK == 1) SFFT_SB(1);
+  else SFFT_SB(2);
+#undef SFFT_SB
+}
+
+hipError_t sub_batch_launch(const SubBatch* b, const Prof* pf, hipStream_t st) {
+  prof_begin(pf, SFFT_PROF_SUBTRACT, st);
+  for (size_t q = 0; q < b->Ls.size(); ++q) {
+    switch (b->Ls[q]) {
+      case 1: sub_batch_l<1>(b, (int)q, st); break;
+      case 3: sub_batch_l<3>(b, (int)q, st); break;
+      case 5: sub_batch_l<5>(b, (int)q, st); break;
+      case 7: sub_batch_l<7>(b, (int)q, st); break;
+      case 9: sub_batch_l<9>(b, (int)q, st); break;
+      case 11: sub_batch_l<11>(b, (int)q, st); break;
+      case 13: sub_batch_l<13>(b, (int)q, st); break;
+      case 15: sub_batch_l<15>(b, (int)q, st); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+  prof_end(pf, SFFT_PROF_SUBTRACT, st);
+  hipLaunchKernelGGL(k_chi2_final_batch, dim3(b->n), dim3(1024), 0, st, (const Chi2Item*)b->dchi);
+  return hipGetLastError();
+}
+
+void sub_batch_destroy(SubBatch* b) { delete b; }
 
 }  // namespace sfft

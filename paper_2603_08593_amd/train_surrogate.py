@@ -67,7 +67,7 @@ def evaluate(net_params, std, test_indices, torch, threshold=1.05, log=_log):
     d = g.diff
     trivial = torch.as_tensor(std.mean, dtype=torch.float64, device="cuda")
     acc_net = acc_triv = 0
-    chi_net, chi_triv, chi_plain = [], [], []
+    chi_net, chi_triv, chi_plain, chi_final = [], [], [], []
     t_gated = t_plain = 0.0
     n = 0
     for k in test_indices:
@@ -88,6 +88,7 @@ def evaluate(net_params, std, test_indices, torch, threshold=1.05, log=_log):
         t_gated += time.perf_counter() - t
         acc_net += ok
         chi_net.append(cp)
+        chi_final.append(cf)
         d.subtract(R, S, coef=trivial)
         ct2 = float(d.buf.chi2.item())
         chi_triv.append(ct2)
@@ -97,7 +98,7 @@ def evaluate(net_params, std, test_indices, torch, threshold=1.05, log=_log):
             log(f"  eval {n} pairs: net accepted {acc_net}, trivial accepted {acc_triv}")
     return dict(pairs=n, accept_net=acc_net / max(n, 1), accept_trivial=acc_triv / max(n, 1),
                 median_chi2_net=float(np.median(chi_net)), median_chi2_trivial=float(np.median(chi_triv)),
-                median_chi2_plain=float(np.median(chi_plain)),
+                median_chi2_plain=float(np.median(chi_plain)), max_chi2_final=float(np.max(chi_final)),
                 pairs_per_s_gated=n / t_gated if t_gated else None,
                 pairs_per_s_plain=n / t_plain if t_plain else None)
 
@@ -145,8 +146,9 @@ def main(argv=None):
     t0 = time.perf_counter()
     hist = []
     for ep in range(a.epochs):
-        h = train(net, Xtr, Ptr, Ttr, epochs=1, batch=a.batch, lr=a.lr * (0.5 * (1 + np.cos(np.pi * ep / a.epochs))),
-                  seed=a.seed + ep)
+        lr0 = a.lr * 0.5 * (1 + np.cos(np.pi * ep / a.epochs))
+        lr1 = a.lr * max(0.5 * (1 + np.cos(np.pi * (ep + 1) / a.epochs)), 0.02)
+        h = train(net, Xtr, Ptr, Ttr, epochs=1, batch=a.batch, lr=lr0, lr_final=lr1, seed=a.seed + ep)
         hist.append((h[0], val_loss()))
         _log(f"epoch {ep + 1}/{a.epochs}: train {hist[-1][0]:.4f} val {hist[-1][1]:.4f} "
              f"({time.perf_counter() - t0:.0f} s)")

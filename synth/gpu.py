@@ -135,3 +135,67 @@ def make_learned_pair(index: int, W: int = 2048, H: int = 4096, nstars: int = 30
     S = torch.poisson(torch.clamp(S_model, min=0.0), generator=g).to(torch.float32)
     meta = dict(seed=seed, f0=f0, grad=tuple(gxy), sky_R=sky_R, sky_S=sky_S, **kmeta)
     return dict(R=R, S=S, theta=pack_theta(a, b), xs=xs, ys=ys, flux=fl, meta=meta)
+
+
+CFG_BATCH = 4
+
+
+def smooth235(lo: int, hi: int):
+    """Even {2,3,5}-smooth integers in [lo, hi]."""
+    out = []
+    for v in range(lo + (lo & 1), hi + 1, 2):
+        x = v
+        for f in (2, 3, 5):
+            while x % f == 0:
+                x //= f
+        if x == 1:
+            out.append(v)
+    return out
+
+
+def batch_shapes(n_ccd: int = 60, n_cut: int = 40):
+    """Shapes (W, H, L) of one exposure: n_ccd 2048 x 4096 CCD pairs and n_cut
+    cutouts with {2,3,5}-smooth W in [512, 1536] and H in [512, 2048]; L is 11
+    or 15 with equal probability, all drawn from the exposure's seed."""
+    rng = np.random.Generator(np.random.PCG64(seed_for(CFG_BATCH, 0)))
+    ws = smooth235(512, 1536)
+    hs = smooth235(512, 2048)
+    shapes = []
+    for k in range(n_ccd + n_cut):
+        L = 11 if rng.uniform() < 0.5 else 15
+        if k < n_ccd:
+            shapes.append((2048, 4096, L))
+        else:
+            shapes.append((int(rng.choice(ws)), int(rng.choice(hs)), L))
+    return shapes
+
+
+def make_batch_pair(index: int, W: int, H: int, L: int, device="cuda"):
+    """Pair `index` of the batched-form exposure: the one-CCD recipe (Moffat
+    beta = 3, FWHM 3.5 -> 5.0 px along y, ~3000 stars per 2048 x 4096 at the
+    same density, flux log-uniform 1e2..1e6, sky U[800, 1500]) with a planted
+    two-Gaussian DK = 2 kernel of size L and a quadratic background."""
+    import torch
+    from . import random_planted_kernel
+    seed = seed_for(CFG_BATCH, 1 + index)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nstars = max(8, int(round(3000 * (W * H) / (2048 * 4096))))
+    xs = rng.uniform(0, W, nstars)
+    ys = rng.uniform(0, H, nstars)
+    fl = np.exp(rng.uniform(math.log(1e2), math.log(1e6), nstars))
+    fw = 3.5 + 1.5 * ys / max(H - 1, 1)
+    sky_R = float(rng.uniform(800, 1500))
+    sky_S = float(rng.uniform(800, 1500))
+    a, kmeta = random_planted_kernel(rng, L, 2, s=float(rng.uniform(0.8, 1.2)))
+    b = np.zeros(6)
+    b[0] = sky_S - float(a[0].sum()) * sky_R
+    for c, (ea, eb) in enumerate(mono_exponents(2)):
+        if c > 0:
+            b[c] = rng.uniform(-20, 20) if ea + eb == 1 else rng.uniform(-10, 10)
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    R_model = sky_R + render_moffat(W, H, xs, ys, fl, fw, device=device)
+    S_model = plant(R_model, a, b, 2, 2)
+    R = torch.poisson(R_model, generator=g).to(torch.float32)
+    S = torch.poisson(torch.clamp(S_model, min=0.0), generator=g).to(torch.float32)
+    return dict(R=R, S=S, theta=pack_theta(a, b), xs=xs, ys=ys, flux=fl, meta=dict(seed=seed, **kmeta))
