@@ -160,15 +160,15 @@ sfft_status sfft_subtract(sfft_handle handle, const sfft_desc* desc,
  * All pairs of an exposure (equal-size CCDs and uneven cutouts, possibly
  * different L) differenced together: every phase of build, solve and
  * subtract is one launch over all items (per-item block ranges in one grid;
- * the solve runs one team of co-resident workgroups per item; the subtract
+ * the solve runs teams of co-resident workgroups over a queue of the items,
+ * largest first; the subtract
  * is one launch per distinct L), and the whole sequence can be captured in
  * one HIP graph. The row-pass rows per workgroup and the solve team size
  * come from an autotuner (sfft_batch_tune), remembered per batch
  * composition and device in the handle and, when the environment variable
  * SFFT_TUNE_CACHE names a file, across processes.
  * Restrictions: compute SFFT_COMPUTE_FP32, image_dtype SFFT_F32, width <=
- * 2048, one DK for all items, n <= number of CUs (else
- * SFFT_ERR_UNSUPPORTED). Each item carries its own buffers, exactly as the
+ * 2048, one DK for all items (else SFFT_ERR_UNSUPPORTED); n <= 4096. Each item carries its own buffers, exactly as the
  * single-pair calls take them; chi2 is required. */
 typedef struct {
   sfft_desc desc;
@@ -226,6 +226,21 @@ sfft_status sfft_build_system_stamps(sfft_handle handle, const sfft_desc* desc,
                                      const int32_t* centers, int32_t n_stamps, int32_t size,
                                      double* G, double* h,
                                      void* ws, size_t ws_bytes, void* stream);
+
+/* Least-squares background for given kernel coefficients: with the kernel
+ * part of coef (indices < n(DK) L^2) held fixed, overwrite the background
+ * part with b = G_bb^-1 (h_b - G_kb^T a), the exact minimiser of the problem
+ * above over the background alone (the kernel-background block, background
+ * block and background right-hand side, from polynomial moments of R' and S'
+ * with periodic seam corrections; no transforms). Used by the learned form:
+ * stamp pairs carry no information on the two images' sky levels.
+ *   coef : device, N doubles (kernel part read, background part written;
+ *          NaN if the background block is not positive definite)
+ *   G, h : device scratch, N*N and N doubles (only the blocks named are written)
+ *   ws   : device workspace of at least sfft_workspace_size bytes */
+sfft_status sfft_refit_background(sfft_handle handle, const sfft_desc* desc, const void* ref,
+                                  const void* sci, double* coef, double* G, double* h,
+                                  void* ws, size_t ws_bytes, void* stream);
 
 /* ---- Learned form ------------------------------------------------------
  * A small convolutional network predicts the kernel and background

@@ -93,6 +93,8 @@ _SIGS = {
     "sfft_solve": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, ctypes.c_int32, _P, _P,
                                   ctypes.c_size_t, _P]),
     "sfft_subtract": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "sfft_refit_background": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, _P, _P, _P, ctypes.c_size_t,
+                                             _P]),
     "sfft_stamps_workspace_size": (ctypes.c_int, [_P, ctypes.POINTER(Desc), ctypes.c_int32, ctypes.c_int32,
                                                   ctypes.POINTER(ctypes.c_size_t)]),
     "sfft_build_system_stamps": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, ctypes.c_int32,
@@ -310,6 +312,16 @@ class Differencer:
     def build(self, ref, sci, stream=None):
         b = self.buf
         sfft_build_system(self.handle, self.desc, ref, sci, b.G, b.h, b.ws, stream)
+
+    def refit_background(self, ref, sci, coef=None, stream=None):
+        """Overwrite the background part of coef with the least-squares
+        background for its kernel part (sfft_refit_background)."""
+        b = self.buf
+        c = b.coef if coef is None else coef
+        _check(lib().sfft_refit_background(self.handle.ptr, ctypes.byref(self.desc), _dp(ref), _dp(sci), _dp(c),
+                                           _dp(b.G), _dp(b.h), _dp(b.ws), b.ws.numel() * b.ws.element_size(),
+                                           _stream_ptr(stream)),
+               "sfft_refit_background")
 
     def build_stamps(self, ref, sci, centers, size, stream=None):
         b = self.buf

@@ -32,6 +32,8 @@ hipError_t launch_subtract(const sfft_desc& d, const void* R, const void* S, con
 hipError_t launch_stamps(const sfft_desc& d, const void* R, const void* S, const int32_t* centers,
                          int nst, int size, double* G, double* hv, unsigned char* ws, int num_cus,
                          const Prof* pf, hipStream_t st);
+hipError_t launch_bg_refit(const sfft_desc& d, const void* R, const void* S, double* coef, double* G,
+                           double* hv, unsigned char* ws, const BuildPlan& p, hipStream_t st);
 hipError_t prepare_kernel_attributes();
 hipError_t prepare_solve_attributes();
 hipError_t prepare_stamp_attributes();
@@ -322,6 +324,21 @@ sfft_status sfft_build_system_stamps(sfft_handle h, const sfft_desc* d, const vo
   return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
 }
 
+sfft_status sfft_refit_background(sfft_handle h, const sfft_desc* d, const void* ref, const void* sci,
+                                  double* coef, double* G, double* hv, void* ws, size_t ws_bytes,
+                                  void* stream) {
+  if (!h) return SFFT_ERR_INVALID_ARG;
+  sfft_status s = validate_core(d);
+  if (s != SFFT_OK) return s;
+  if (!ref || !sci || !coef || !G || !hv) return SFFT_ERR_INVALID_ARG;
+  if ((s = check_ws(ws, ws_bytes, make_layout(make_geometry(*d)).build_end)) != SFFT_OK) return s;
+  if ((s = check_device(h)) != SFFT_OK) return s;
+  BuildPlan p{nullptr, nullptr, nullptr, h->num_cus};
+  const hipError_t e = launch_bg_refit(*d, ref, sci, coef, G, hv, static_cast<unsigned char*>(ws), p,
+                                       static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
+}
+
 // ---- learned form -------------------------------------------------------
 
 static bool net_shape_ok(int32_t n_pairs, int32_t n_stamps, int32_t n_out) {
@@ -519,7 +536,6 @@ sfft_status sfft_batch_create(sfft_handle h, const sfft_batch_item* items, int32
       return SFFT_ERR_UNSUPPORTED;
     if (it.desc.dk != items[0].desc.dk) return SFFT_ERR_UNSUPPORTED;
   }
-  if (n > h->num_cus) return SFFT_ERR_UNSUPPORTED;     // one solve workgroup per CU at least
   sfft_batch b = new (std::nothrow) sfft_batch_s();
   if (!b) return SFFT_ERR_INTERNAL;
   b->handle = h;
@@ -584,9 +600,13 @@ sfft_status sfft_batch_tune(sfft_batch b, void* stream, int32_t* rows_per_block,
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int n = (int)b->items.size();
   const int cus = b->handle->num_cus > 0 ? b->handle->num_cus : 256;
+  // solve team sizes: one team per item (CUs / n) and larger teams that
+  // work through a queue of items (fewer concurrent teams)
   std::vector<int> teams;
-  for (int t = 1; t <= 64 && t * n <= cus; t *= 2) teams.push_back(t);
-  if (cus / n > 0 && (teams.empty() || teams.back() != std::min(64, cus / n))) teams.push_back(std::min(64, cus / n));
+  const int one_each = std::max(1, std::min(64, cus / n));
+  teams.push_back(one_each);
+  for (int t : {4, 8, 16, 32, 64})
+    if (t > one_each && t <= cus) teams.push_back(t);
   const int rpbs[] = {2, 4, 8, 16};
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return SFFT_ERR_HIP;

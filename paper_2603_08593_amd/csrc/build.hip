@@ -841,6 +841,109 @@ __global__ __launch_bounds__(256) void k_gather_kk_batch(const GatherArgs* args,
 }
 
 // ---------------------------------------------------------------------------
+// Background refit for a given kernel (learned form): the least-squares
+// background given fixed kernel coefficients a is b = G_bb^-1 (h_b - G_kb^T a),
+// with G_kb, G_bb and h_b exactly the blocks the build assembles from
+// polynomial moments; only the row moments are needed, not the spectra.
+// ---------------------------------------------------------------------------
+
+template <typename TIN>
+__global__ __launch_bounds__(kRowThreads) void k_row_moments(RowArgs a) {
+  __shared__ double red[kRowThreads / 64][16];
+  const int W = a.W;
+  const int nm = a.DK + a.DB + 1;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int y = blockIdx.x; y < a.H; y += gridDim.x) {
+    double mr[9], ms[5];
+#pragma unroll
+    for (int m = 0; m < 9; ++m) mr[m] = 0.0;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) ms[m] = 0.0;
+    bool bad = false;
+    for (int x = threadIdx.x; x < W; x += kRowThreads) {
+      const double rv = load_pix<TIN>(a.R, (int64_t)y * a.ld + x) - a.cR;
+      const double sv = load_pix<TIN>(a.S, (int64_t)y * a.ld + x) - a.cS;
+      bad |= !(is_finite_d(rv) && is_finite_d(sv));
+      const double xt = (double)x * a.sx - 1.0;
+      double pw = 1.0;
+#pragma unroll
+      for (int m = 0; m < 9; ++m) {
+        if (m < nm) mr[m] = fma(pw, rv, mr[m]);
+        if (m <= a.DB && m < 5) ms[m] = fma(pw, sv, ms[m]);
+        pw *= xt;
+      }
+      if (x < a.r) a.ER[(int64_t)y * 2 * a.r + x] = rv;
+      if (x >= W - a.r) a.ER[(int64_t)y * 2 * a.r + a.r + (x - (W - a.r))] = rv;
+    }
+    if (bad) atomicOr(a.flags, 1);
+#pragma unroll
+    for (int m = 0; m < 9; ++m) {
+      const double v = wave_sum(mr[m]);
+      if (lane == 0) red[wid][m] = v;
+    }
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const double v = wave_sum(ms[m]);
+      if (lane == 0) red[wid][9 + m] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 16) {
+      const int m = threadIdx.x;
+      double sum = 0.0;
+      for (int w = 0; w < kRowThreads / 64; ++w) sum += red[w][m];
+      if (m < nm) a.MR[(int64_t)m * a.H + y] = sum;
+      else if (m >= 9 && m - 9 <= a.DB) a.MS[(int64_t)(m - 9) * a.H + y] = sum;
+    }
+    __syncthreads();
+  }
+}
+
+// b = G_bb^-1 (h_b - G_kb^T a): one workgroup; FP64 dot products in a fixed
+// order, Cholesky of the (at most 15 x 15) background block by one thread
+__global__ __launch_bounds__(256) void k_bg_refit(const double* G, const double* hv, double* coef, int N,
+                                                  int nKL, int nB) {
+  __shared__ double red[4];
+  __shared__ double rhs[15];
+  __shared__ double M[15][15];
+  for (int c = 0; c < nB; ++c) {
+    double s = 0.0;
+    for (int row = threadIdx.x; row < nKL; row += 256) s += G[(int64_t)row * N + nKL + c] * coef[row];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) rhs[c] = hv[nKL + c] - s;
+  }
+  for (int t = threadIdx.x; t < nB * nB; t += 256)
+    M[t / nB][t % nB] = G[(int64_t)(nKL + t / nB) * N + nKL + t % nB];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // Cholesky M = L L^T in place (lower), then two substitutions
+    bool ok = true;
+    for (int j = 0; j < nB && ok; ++j) {
+      double d = M[j][j];
+      for (int k = 0; k < j; ++k) d -= M[j][k] * M[j][k];
+      if (!(d > 0.0)) { ok = false; break; }
+      M[j][j] = sqrt(d);
+      for (int i = j + 1; i < nB; ++i) {
+        double v = M[i][j];
+        for (int k = 0; k < j; ++k) v -= M[i][k] * M[j][k];
+        M[i][j] = v / M[j][j];
+      }
+    }
+    double y[15];
+    for (int i = 0; i < nB; ++i) {
+      double v = rhs[i];
+      for (int k = 0; k < i; ++k) v -= M[i][k] * y[k];
+      y[i] = ok ? v / M[i][i] : 0.0;
+    }
+    for (int i = nB - 1; i >= 0; --i) {
+      double v = y[i];
+      for (int k = i + 1; k < nB; ++k) v -= M[k][i] * y[k];
+      coef[nKL + i] = ok ? v / M[i][i] : __builtin_nan("");
+      y[i] = ok ? v / M[i][i] : 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
 
@@ -1182,6 +1285,27 @@ hipError_t build_batch_launch(const BuildBatch* b, const Prof* pf, hipStream_t s
   hipLaunchKernelGGL(k_kb_assemble_batch, dim3(h.bkb), dim3(256), 0, st, d.kb, d.tkb, h.n);
   hipLaunchKernelGGL(k_gather_kk_batch, dim3(h.bgat), dim3(256), 0, st, d.gat, d.tgat, h.n);
   prof_end(pf, SFFT_PROF_BUILD, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_bg_refit(const sfft_desc& d, const void* R, const void* S, double* coef, double* G,
+                           double* hv, unsigned char* ws, const BuildPlan& p, hipStream_t st) {
+  const Geometry g = make_geometry(d);
+  const Layout l = make_layout(g);
+  const RowArgs ra = make_row_args(g, d, R, S, ws, l, p);
+  const int grid = g.H < 4 * p.num_cus ? g.H : 4 * p.num_cus;
+  if (d.image_dtype == SFFT_F32)
+    hipLaunchKernelGGL(k_row_moments<float>, dim3(grid), dim3(kRowThreads), 0, st, ra);
+  else
+    hipLaunchKernelGGL(k_row_moments<double>, dim3(grid), dim3(kRowThreads), 0, st, ra);
+  hipError_t e;
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const MomArgs ma = make_mom_args(g, ws, l);
+  hipLaunchKernelGGL(k_moments, dim3(l.nmom), dim3(256), 0, st, ma);
+  const KbArgs ka = make_kb_args(g, ma, G, hv);
+  hipLaunchKernelGGL(k_kb_assemble, dim3(kb_grid(g)), dim3(256), 0, st, ka);
+  hipLaunchKernelGGL(k_bg_refit, dim3(1), dim3(256), 0, st, (const double*)G, (const double*)hv, coef, g.N,
+                     g.nK * g.L * g.L, g.nB);
   return hipGetLastError();
 }
 

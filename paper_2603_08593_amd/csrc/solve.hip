@@ -18,6 +18,7 @@
 // Workgroups synchronise through a flag barrier (one arrival flag per
 // workgroup, one release flag) with bounded spins: a timeout is reported in
 // the status instead of hanging.
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -563,9 +564,12 @@ __device__ __forceinline__ void solve_body(const PSArgs& a, const int bid) {
 
 __global__ __launch_bounds__(kPT) void k_solve_persistent(PSArgs a) { solve_body(a, blockIdx.x); }
 
-// one team of P co-resident workgroups per item (every item planned with the same P)
-__global__ __launch_bounds__(kPT) void k_solve_batch(const PSArgs* args, int P) {
-  solve_body(args[blockIdx.x / P], blockIdx.x % P);
+// T teams of P co-resident workgroups; team t solves items t, t + T, ...
+// (a static work queue over items ordered by decreasing size, every item
+// planned with the same P)
+__global__ __launch_bounds__(kPT) void k_solve_batch(const PSArgs* args, const int* order, int n, int P, int T) {
+  const int team = blockIdx.x / P, bid = blockIdx.x % P;
+  for (int q = team; q < n; q += T) solve_body(args[order[q]], bid);
 }
 
 // clears the arrival / release flags and the barrier time stamps
@@ -639,34 +643,46 @@ __global__ void k_solve_reset_batch(const PSArgs* args) {
 
 struct SolveBatch {
   std::vector<PSArgs> args;
+  std::vector<int> order;     // items by decreasing number of unknowns
   PSArgs* dev = nullptr;
-  int P = 1;
+  int* dorder = nullptr;
+  int P = 1, T = 1;
 };
 
-// Team size: every team must be co-resident (one solve workgroup per CU),
-// so n * P <= number of CUs.
+// Team size P and team count T: every workgroup of every team must be
+// co-resident (one solve workgroup per CU), so T * P <= number of CUs;
+// T <= n. P = 0 picks P = CUs / n (one team per item when they fit).
 SolveBatch* solve_batch_create(const SolveItem* items, int n, int max_refine, int P, int num_cus,
                                hipError_t* err) {
   const int cus = num_cus > 0 ? num_cus : 256;
-  if (P <= 0) P = cus / n;
+  if (P <= 0) P = std::max(1, cus / n);
   if (P > 64) P = 64;
-  if (P < 1 || (int64_t)P * n > cus) { *err = hipErrorInvalidValue; return nullptr; }
+  if (P < 1 || P > cus) { *err = hipErrorInvalidValue; return nullptr; }
   SolveBatch* b = new (std::nothrow) SolveBatch();
   if (!b) { *err = hipErrorOutOfMemory; return nullptr; }
   b->P = P;
+  b->T = std::min(n, cus / P);
   for (int k = 0; k < n; ++k) {
     const SolveItem& it = items[k];
     b->args.push_back(make_solve_args(it.d, it.G, it.h, it.coef, max_refine, it.info, it.ws, P));
+    b->order.push_back(k);
   }
+  std::stable_sort(b->order.begin(), b->order.end(),
+                   [&](int x, int y) { return b->args[x].N > b->args[y].N; });
   *err = hipSuccess;
   return b;
 }
 
-size_t solve_batch_dev_bytes(const SolveBatch* b) { return align256(b->args.size() * sizeof(PSArgs)); }
+size_t solve_batch_dev_bytes(const SolveBatch* b) {
+  return align256(b->args.size() * sizeof(PSArgs)) + align256(b->order.size() * sizeof(int));
+}
 
 hipError_t solve_batch_upload(SolveBatch* b, unsigned char* dev) {
   b->dev = reinterpret_cast<PSArgs*>(dev);
-  return hipMemcpy(dev, b->args.data(), b->args.size() * sizeof(PSArgs), hipMemcpyHostToDevice);
+  b->dorder = reinterpret_cast<int*>(dev + align256(b->args.size() * sizeof(PSArgs)));
+  hipError_t e = hipMemcpy(dev, b->args.data(), b->args.size() * sizeof(PSArgs), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  return hipMemcpy(b->dorder, b->order.data(), b->order.size() * sizeof(int), hipMemcpyHostToDevice);
 }
 
 hipError_t solve_batch_launch(const SolveBatch* b, const Prof* pf, hipStream_t st) {
@@ -675,10 +691,10 @@ hipError_t solve_batch_launch(const SolveBatch* b, const Prof* pf, hipStream_t s
   hipLaunchKernelGGL(k_solve_reset_batch, dim3(n), dim3(256), 0, st, (const PSArgs*)b->dev);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // a plain launch (capturable in a graph): n * P <= CUs with one workgroup
+  // a plain launch (capturable in a graph): T * P <= CUs with one workgroup
   // per CU keeps every team resident; the barrier spins are bounded anyway
-  hipLaunchKernelGGL(k_solve_batch, dim3(n * b->P), dim3(kPT), solve_shmem_bytes(), st,
-                     (const PSArgs*)b->dev, b->P);
+  hipLaunchKernelGGL(k_solve_batch, dim3(b->T * b->P), dim3(kPT), solve_shmem_bytes(), st,
+                     (const PSArgs*)b->dev, (const int*)b->dorder, n, b->P, b->T);
   prof_end(pf, SFFT_PROF_SOLVE, st);
   return hipGetLastError();
 }

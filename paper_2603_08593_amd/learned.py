@@ -1,9 +1,11 @@
 """Learned form: training of the coefficient network with the library's own
 forward, backward and Adam kernels, and gated inference with the chi2 judge.
 
-A pair is differenced with the predicted coefficients first; when the
-difference image's reduced chi2 exceeds the threshold (1.05), the full
-build + solve runs and the pair is differenced again with its own fit.
+A pair is differenced with the predicted kernel first (its background
+re-fitted exactly for that kernel, a 6-unknown least-squares problem from
+image moments); when the difference image's reduced chi2 exceeds the
+threshold (1.05), the full build + solve runs and the pair is differenced
+again with its own fit.
 Every step runs in the HIP library (argument marshalling only here).
 """
 from __future__ import annotations
@@ -13,8 +15,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import (SFFT_NET_BF16, SFFT_NET_FP32, Differencer, Handle, Surrogate, make_desc,
-               sfft_extract_stamps, sfft_surrogate_destandardize, SFFT_F32, SFFT_F64)
+from . import (SFFT_NET_BF16, Differencer, Surrogate, sfft_extract_stamps, sfft_surrogate_destandardize)
 
 N_STAMPS = 64
 STAMP = 32
@@ -86,7 +87,8 @@ class GatedDifferencer:
     the full fit when the chi2 judge rejects them."""
 
     def __init__(self, width, height, L, dk, db, params, std: Standardizer, *, threshold=1.05,
-                 precision=SFFT_NET_BF16, image_dtype="float32", n_stamps=N_STAMPS, device="cuda"):
+                 precision=SFFT_NET_BF16, image_dtype="float32", n_stamps=N_STAMPS, device="cuda",
+                 refit_background=True):
         import torch
         self.torch = torch
         self.diff = Differencer(width, height, L, dk, db, image_dtype=image_dtype, device=device)
@@ -94,6 +96,7 @@ class GatedDifferencer:
                              device=device)
         self.threshold = float(threshold)
         self.precision = precision
+        self.refit = bool(refit_background)
         self.n_stamps = n_stamps
         dev = torch.device(device)
         self.mean = torch.as_tensor(std.mean, dtype=torch.float64, device=dev)
@@ -103,18 +106,23 @@ class GatedDifferencer:
         self.pred = torch.empty((1, self.diff.N), dtype=torch.float32, device=dev)
         self.coef_pred = torch.empty((self.diff.N,), dtype=torch.float64, device=dev)
 
-    def predict(self, R, S, centers, stream=None):
-        """Network coefficients for the pair (device FP64 [N]); asynchronous."""
+    def predict(self, R, S, centers, refit_background=None, stream=None):
+        """Coefficients for the pair (device FP64 [N]); asynchronous. The
+        kernel part is the network's; the background part is the network's,
+        or (default) the least-squares background for that kernel: the
+        sky-subtracted stamps carry no information on the images' sky levels."""
         d = self.diff
         sfft_extract_stamps(d.handle, d.desc, R, S, centers, self.stamps, self.pos, stream)
         self.net.forward(self.stamps, self.pos, 1, precision=self.precision, out=self.pred, stream=stream)
         sfft_surrogate_destandardize(d.handle, self.pred, self.mean, self.scale, 1, d.N, self.coef_pred, stream)
+        if self.refit if refit_background is None else refit_background:
+            d.refit_background(R, S, coef=self.coef_pred, stream=stream)
         return self.coef_pred
 
     def run(self, R, S, centers, max_refine=1, stream=None):
         """Returns (accepted, chi2 of the prediction, final chi2)."""
         d = self.diff
-        self.predict(R, S, centers, stream)
+        self.predict(R, S, centers, stream=stream)
         d.subtract(R, S, coef=self.coef_pred, stream=stream)
         chi_pred = float(d.buf.chi2.item())          # the judge's decision needs the value on the host
         if chi_pred <= self.threshold:

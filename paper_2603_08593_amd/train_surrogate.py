@@ -58,12 +58,13 @@ def build_dataset(indices, diff, torch, log_every=200):
     return stamps.index_select(0, it), pos.index_select(0, it), thetas[idx], chi2[idx], np.asarray(indices)[idx]
 
 
-def evaluate(net_params, std, test_indices, torch, threshold=1.05, log=_log):
+def evaluate(net_params, std, test_indices, torch, threshold=1.05, log=_log, refit_background=True):
     """Gated vs plain vs trivial on held-out pairs; times exclude rendering."""
     import synth
     import synth.gpu as sg
     from .learned import GatedDifferencer
-    g = GatedDifferencer(2048, 4096, 11, 2, 2, net_params, std, threshold=threshold)
+    g = GatedDifferencer(2048, 4096, 11, 2, 2, net_params, std, threshold=threshold,
+                         refit_background=refit_background)
     d = g.diff
     trivial = torch.as_tensor(std.mean, dtype=torch.float64, device="cuda")
     acc_net = acc_triv = 0
@@ -89,6 +90,9 @@ def evaluate(net_params, std, test_indices, torch, threshold=1.05, log=_log):
         acc_net += ok
         chi_net.append(cp)
         chi_final.append(cf)
+        trivial.copy_(torch.as_tensor(std.mean, dtype=torch.float64, device="cuda"))
+        if refit_background:
+            d.refit_background(R, S, coef=trivial)   # the same background refit as the gated path
         d.subtract(R, S, coef=trivial)
         ct2 = float(d.buf.chi2.item())
         chi_triv.append(ct2)
@@ -112,11 +116,22 @@ def main(argv=None):
     ap.add_argument("--eval-pairs", type=int, default=200)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--out", default="surrogate.npz")
+    ap.add_argument("--eval-only", default=None, help="evaluate saved weights instead of training")
+    ap.add_argument("--eval-start", type=int, default=None, help="first held-out pair index")
+    ap.add_argument("--no-refit", action="store_true", help="use the network's background coefficients")
     a = ap.parse_args(argv)
     import torch
     import synth
     from . import Differencer, Surrogate
-    from .learned import Standardizer, save_weights, train
+    from .learned import Standardizer, load_weights, save_weights, train
+    if a.eval_only:
+        params, std, _ = load_weights(a.eval_only)
+        start = a.eval_start if a.eval_start is not None else int(0.85 * a.pairs)
+        res = evaluate(params, std, np.arange(start, start + a.eval_pairs), torch,
+                       refit_background=not a.no_refit)
+        res.update(weights=a.eval_only, refit_background=not a.no_refit)
+        print(json.dumps(res), flush=True)
+        return 0
     diff = Differencer(2048, 4096, 11, 2, 2, image_dtype="float32")
     n_tr, n_va = int(0.80 * a.pairs), int(0.05 * a.pairs)
     idx = np.arange(a.pairs)
@@ -158,7 +173,8 @@ def main(argv=None):
     save_weights(a.out, params, std, train_loss=[x[0] for x in hist], val_loss=[x[1] for x in hist],
                  pairs=a.pairs, epochs=a.epochs, batch=a.batch, lr=a.lr)
     _log(f"saved {a.out}; evaluating on {a.eval_pairs} held-out pairs")
-    res = evaluate(params, std, idx[n_tr + n_va:n_tr + n_va + a.eval_pairs], torch)
+    res = evaluate(params, std, idx[n_tr + n_va:n_tr + n_va + a.eval_pairs], torch,
+                   refit_background=not a.no_refit)
     res.update(train_seconds=train_s, final_train_loss=hist[-1][0], final_val_loss=hist[-1][1])
     print(json.dumps(res), flush=True)
     return 0

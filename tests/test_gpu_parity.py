@@ -233,3 +233,32 @@ def test_cfg2_full_size_sampled():
         worst = max(worst, v)
     _say(f"  orthogonality |a^T D|/(|a||D|) max {worst:.2e}")
     assert worst <= 1e-10
+
+
+def test_refit_background_matches_oracle():
+    """Least-squares background for a fixed (perturbed) kernel: GPU against
+    b = G_bb^-1 (h_b - G_kb^T a) from the oracle's normal equations; and for
+    the full fit's own kernel it returns the fit's background."""
+    torch, sf = _torch(), _sf()
+    p = synth.make_pair(256, 192, 7, 2, 2, seed=77, nstars=60, psf="moffat", fwhm=3.5,
+                       fwhm_end=4.5, flux=(1e2, 1e6), dtype=np.float32)
+    G, h = O.build_fft64(p.R, p.S, 7, 2, 2)
+    th, _ = O.solve_cholesky64(G, h)
+    nk = O.n_mono(2) * 49
+    rng = np.random.default_rng(1)
+    a = th[:nk] * (1 + 0.05 * rng.standard_normal(nk))
+    want = np.linalg.solve(G[nk:, nk:], h[nk:] - G[nk:, :nk] @ a)
+    d = sf.Differencer(256, 192, 7, 2, 2, image_dtype="float32")
+    R, S = torch.from_numpy(p.R).cuda(), torch.from_numpy(p.S).cuda()
+    coef = torch.from_numpy(np.concatenate([a, np.zeros(6)])).cuda()
+    d.refit_background(R, S, coef=coef)
+    torch.cuda.synchronize()
+    got = coef.cpu().numpy()
+    e = np.max(np.abs(got[nk:] - want)) / np.max(np.abs(want))
+    _say(f"  refit background rel err {e:.2e}")
+    assert e <= 1e-9
+    assert np.array_equal(got[:nk], a)
+    coef2 = torch.from_numpy(np.concatenate([th[:nk], np.zeros(6)])).cuda()
+    d.refit_background(R, S, coef=coef2)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(coef2.cpu().numpy()[nk:] - th[nk:])) <= 1e-8 * np.max(np.abs(th[nk:]))
