@@ -57,7 +57,9 @@ struct FftPlan {
   int radix[12];
 };
 
-template <typename T, int R, bool INV, int NQ>
+// POW2: N and Ns are powers of two, so the butterfly's position within its
+// group is a mask instead of a division
+template <typename T, int R, bool INV, int NQ, bool POW2>
 __device__ __forceinline__ void stockham_pass(cx<T>* buf, const cx<T>* tw, int N, int Ns) {
   constexpr int MAXB = (NQ * kRowThreads + R * kRowThreads - 1) / (R * kRowThreads);
   const int nb = N / R;
@@ -67,7 +69,7 @@ __device__ __forceinline__ void stockham_pass(cx<T>* buf, const cx<T>* tw, int N
   for (int t = 0; t < MAXB; ++t) {
     const int j = threadIdx.x + t * kRowThreads;
     if (j < nb) {
-      const int k = j % Ns;
+      const int k = POW2 ? (j & (Ns - 1)) : j % Ns;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[t][r] = buf[pad8(j + r * nb)];
       if (Ns > 1) {
@@ -86,7 +88,7 @@ __device__ __forceinline__ void stockham_pass(cx<T>* buf, const cx<T>* tw, int N
   for (int t = 0; t < MAXB; ++t) {
     const int j = threadIdx.x + t * kRowThreads;
     if (j < nb) {
-      const int k = j % Ns;
+      const int k = POW2 ? (j & (Ns - 1)) : j % Ns;
       const int base = (j - k) * R + k;
 #pragma unroll
       for (int r = 0; r < R; ++r) buf[pad8(base + r * Ns)] = v[t][r];
@@ -100,12 +102,12 @@ __device__ void fft_lds(cx<T>* buf, const cx<T>* tw, int N, const FftPlan& plan)
   int Ns = 1;
   for (int s = 0; s < plan.nstages; ++s) {
     const int R = plan.radix[s];
-    if (R == 8) stockham_pass<T, 8, INV, NQ>(buf, tw, N, Ns);
-    else if (R == 4) stockham_pass<T, 4, INV, NQ>(buf, tw, N, Ns);
-    else if (R == 2) stockham_pass<T, 2, INV, NQ>(buf, tw, N, Ns);
+    if (R == 8) stockham_pass<T, 8, INV, NQ, !MIXED>(buf, tw, N, Ns);
+    else if (R == 4) stockham_pass<T, 4, INV, NQ, !MIXED>(buf, tw, N, Ns);
+    else if (R == 2) stockham_pass<T, 2, INV, NQ, !MIXED>(buf, tw, N, Ns);
     else if constexpr (MIXED) {
-      if (R == 3) stockham_pass<T, 3, INV, NQ>(buf, tw, N, Ns);
-      else stockham_pass<T, 5, INV, NQ>(buf, tw, N, Ns);
+      if (R == 3) stockham_pass<T, 3, INV, NQ, false>(buf, tw, N, Ns);
+      else stockham_pass<T, 5, INV, NQ, false>(buf, tw, N, Ns);
     }
     Ns *= R;
   }
@@ -304,8 +306,11 @@ constexpr int col_spec_stride() {
 
 template <typename T, int NK>
 constexpr size_t col_pass_shmem() {
+  // spectra, twiddles, staged rows, then the row weight table:
+  // [window (U, V)][power 0..DK][row] of T
   return sizeof(cx<T>) * ((size_t)kColsPerWG * col_spec_stride<NK>() + kTP +
-                          (size_t)BaseCount<NK>::value * kTP * kColsPerWG);
+                          (size_t)BaseCount<NK>::value * kTP * kColsPerWG) +
+         sizeof(T) * 2 * (BaseCount<NK>::value - 1) * kTP;
 }
 
 template <typename T, int NK>
@@ -320,6 +325,8 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const VB vb) {
   cx<T>* spec = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* tw = spec + kColsPerWG * CS;
   cx<T>* raw = tw + kTP;                     // staged rows: [base][m][column]
+  constexpr int NPOW = NBASE - 1;            // powers yt^0 .. yt^DK
+  T* wtab = reinterpret_cast<T*>(raw + NBASE * kTP * kColsPerWG);
   const cx<T>* twg = static_cast<const cx<T>*>(a.tw128);
   const int tid = threadIdx.x;
   if (tid < kTP) tw[tid] = twg[tid];
@@ -365,15 +372,36 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const VB vb) {
     for (int u = 0; u < NBASE; ++u) raw[(u * kTP + fm) * kColsPerWG + fc] = pre[u];
   };
 
+  // weight of window row m for the block starting at yb: yt(y)^b inside the
+  // window (kernel side: the T rows of the block; science side: the block
+  // plus its h-row halo), 0 outside
+  auto fill_weights = [&](int yb) {
+    const int Tb = min(a.T, H - yb);
+    for (int m = tid; m < kTP; m += kColThreads) {
+      const int o = (m < kTP - h) ? m : m - kTP;
+      int y = yb + o;
+      y = (y < 0) ? y + H : ((y >= H) ? y - H : y);
+      const double yt = (double)y * a.sy - 1.0;
+      const bool inu = (o >= 0 && o < Tb), inv = (o >= -h && o < Tb + h);
+      double pw = 1.0;
+#pragma unroll
+      for (int b = 0; b < NPOW; ++b) {
+        wtab[b * kTP + m] = inu ? (T)pw : (T)0;
+        wtab[(NPOW + b) * kTP + m] = inv ? (T)pw : (T)0;
+        pw *= yt;
+      }
+    }
+  };
+
   cx<T> acc[NP];
 #pragma unroll
   for (int p = 0; p < NP; ++p) acc[p] = cx<T>{(T)0, (T)0};
   fetch(0);
   commit();
+  fill_weights(0);
   __syncthreads();
 
   for (int yb = 0; yb < H; yb += a.T) {
-    const int Tb = min(a.T, H - yb);
     // ---- stage 1: weighted rows j + 8q from the staging buffer, radix-16
     if (tid < kColsPerWG * NS * 8) {
       const int c = tid & 3;
@@ -386,20 +414,12 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const VB vb) {
       else if (s < 2 * NK) { int ea, eb; mono_ab(s - NK, ea, eb); base = ea; bpow = eb; is_u = false; }
       else { base = NBASE - 1; bpow = 0; is_u = false; }
       const cx<T>* src = raw + (base * kTP) * kColsPerWG + c;
+      const T* wrow = wtab + (is_u ? bpow : NPOW + bpow) * kTP;
       cx<T> v[16];
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int m = j + 8 * q;
-        const int o = (m < kTP - h) ? m : m - kTP;
-        const bool in = is_u ? (o >= 0 && o < Tb) : (o >= -h && o < Tb + h);
-        cx<T> val = src[m * kColsPerWG];
-        if (bpow > 0) {
-          int y = yb + o;
-          y = (y < 0) ? y + H : ((y >= H) ? y - H : y);
-          const double yt = (double)y * a.sy - 1.0;
-          val = cscale(val, (T)ipow(yt, bpow));
-        }
-        v[q] = in ? val : cx<T>{(T)0, (T)0};
+        v[q] = cscale(src[m * kColsPerWG], wrow[m]);
       }
       dft16<T, false>(v);
       cx<T>* dst = spec + c * CS + s * SPAD;
@@ -449,7 +469,10 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const VB vb) {
 #pragma unroll
       for (int i = 0; i < NK; ++i) cmac_conj(acc[NKK + i], U[i], V[NK]);
     }
-    if (more) commit();
+    if (more) {
+      commit();
+      fill_weights(yb + a.T);
+    }
     __syncthreads();
   }
 

@@ -71,7 +71,7 @@ struct Layout {
   // build
   size_t flags, F, MR, MS, ER, edge, strips, C, mom, build_end;
   // solve (overlaps the build region after `flags`)
-  size_t A, s, b, theta, x, rvec, rowabs, Ud, sync, solve_end;
+  size_t A, s, b, theta, x, rvec, rowabs, Ud, part, sync, solve_end;
   // subtract
   size_t partials, sub_end;
   size_t total;
@@ -121,6 +121,9 @@ inline Layout make_layout(const Geometry& g) {
   l.rvec = o; o = align256(o + sizeof(double) * Np);
   l.rowabs = o; o = align256(o + sizeof(double) * Np);
   l.Ud = o; o = align256(o + sizeof(double) * Np * kTile);
+  // partial sums of the transposed triangular product: (row chunks) x Np,
+  // at most max(Np, 64 workgroups x 8 waves x 64 columns)
+  l.part = o; o = align256(o + sizeof(double) * (Np > 32768 ? Np : 32768));
   l.sync = o; o = align256(o + sizeof(unsigned) * 128 + sizeof(unsigned long long) * 256);
   l.solve_end = o;
   // subtract region

@@ -45,6 +45,7 @@ struct PSArgs {
   double* r;        // Np
   double* rowabs;   // Np
   double* Ud;       // nt tiles of 64 x 64: U_k = L_kk^-T of each diagonal tile
+  double* part;     // partial sums of gemv_upper_t
   unsigned* sync;   // [0, P): arrival flags, [P]: release flag
   unsigned long long* stamps;   // optional: 100 MHz time stamp of each barrier
   int* flags;       // [0] nonfinite (build), [1] failed pivot + 1, [2] barrier timeout
@@ -181,86 +182,98 @@ __device__ __forceinline__ double rsqrt64(double d) {
   return y * fma(-0.5 * d * y, y, 1.5);
 }
 
-// Cholesky of the 64 x 64 SPD tile T (lower, in place) and U = L^-T into Ut:
-// the right-looking factorisation of the stacked [T; I] turns the identity
-// rows into L^-T (I = Y L^T). Thread (i, q) holds T[i][8q + m] and the
-// identity row's [i][8q + m], m = 0..7, so column j lives in wave j / 8,
-// register j % 8: with the inner 8 columns unrolled every register index is
-// a constant and every branch on the column is uniform. Column j of both
-// parts is published in colbuf (double-buffered); one barrier per column.
-// Returns the failing local pivot or -1. colbuf: 4 x 64 doubles.
-__device__ int tile_potrf_aug(double (*T)[kLD], double (*Ut)[kLD], double (*colbuf)[kTile]) {
-  const int i = threadIdx.x & 63;
-  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave index, uniform
-  double reg[8], aug[8];
-#pragma unroll
-  for (int m = 0; m < 8; ++m) {
-    reg[m] = T[i][8 * q + m];
-    aug[m] = (i == 8 * q + m) ? 1.0 : 0.0;
-  }
+// value of x in lane `lane` (uniform result)
+__device__ __forceinline__ double lane_value(double x, int lane) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// Cholesky of the 64 x 64 SPD tile T (lower, in place) and U = L^-T into Ut.
+// The right-looking factorisation of the stacked [T; I] turns the identity
+// rows into L^-T (I = Y L^T); Ut starts as the identity and holds Y. Blocked
+// by 8 columns, two workgroup barriers per block:
+//   panel: wave 0 (lane i = row i of T and of Y) keeps the block's 8 entries
+//   of both rows in registers and factors the 8 columns one by one; pivots
+//   and the entries of L that update the rest of the block come from other
+//   lanes by readlane, so the column chain never waits on LDS; column j of L
+//   is written to T and the block of Y to Ut;
+//   trailing update: every wave applies the block's rank-8 update to its
+//   share of the later columns (wave w: columns j0 + 8 + w, + 8, ...) for all
+//   64 rows of T and of Y, reading the block of L as broadcasts.
+// A pivot that is not positive and finite is recorded (the first one) and
+// the sweep goes on with a zero scale, so values stay finite; the caller
+// discards them. Returns the failing local pivot or -1.
+__device__ __forceinline__ int tile_potrf_aug(double (*T)[kLD], double (*Ut)[kLD]) {
+  constexpr int kB = 8;
   __shared__ int fail;
+  const int i = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (threadIdx.x == 0) fail = -1;
-  if (q == 0) { colbuf[0][i] = reg[0]; colbuf[2][i] = aug[0]; }
+  for (int idx = threadIdx.x; idx < kTile * kTile; idx += kPT)
+    Ut[idx >> 6][idx & 63] = ((idx >> 6) == (idx & 63)) ? 1.0 : 0.0;
   __syncthreads();
-  bool ok = true;
+  int f = -1;
 #pragma unroll 1
-  for (int qb = 0; qb < 8 && ok; ++qb) {
+  for (int jb = 0; jb < kTile / kB; ++jb) {
+    const int j0 = jb * kB;
+    if (w == 0) {
+      double rb[kB], yb[kB];
 #pragma unroll
-    for (int jj = 0; jj < 8; ++jj) {
-      const int j = 8 * qb + jj;
-      const int bsel = jj & 1;              // j & 1
-      const double* cT = colbuf[bsel];
-      const double d = cT[j];
-      const double ci = cT[i], ai = colbuf[2 + bsel][i];
-      double cl[8];
-#pragma unroll
-      for (int m = 0; m < 8; ++m) cl[m] = cT[8 * q + m];
-      if (!(d > 0.0) || !is_finite_d(d)) {   // uniform: every thread read the same pivot
-        if (threadIdx.x == 0) fail = j;
-        ok = false;
-        break;
+      for (int c = 0; c < kB; ++c) {
+        rb[c] = T[i][j0 + c];
+        yb[c] = Ut[i][j0 + c];
       }
-      const double rs = rsqrt64(d);
-      const double li = ci * rs, yi = ai * rs;
-      if (q > qb) {
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
-          const double lp = cl[m] * rs;
-          reg[m] = fma(-li, lp, reg[m]);
-          aug[m] = fma(-yi, lp, aug[m]);
-        }
-      } else if (q == qb) {
+      for (int c = 0; c < kB; ++c) {
+        const int j = j0 + c;
+        const double d = lane_value(rb[c], j);
+        const bool good = (d > 0.0) && is_finite_d(d);
+        f = (f < 0 && !good) ? j : f;
+        const double rs = good ? rsqrt64(d) : 0.0;
+        const double l = (i >= j) ? rb[c] * rs : 0.0;
+        const double y = yb[c] * rs;
+        rb[c] = l;
+        yb[c] = y;
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
-          if (m > jj) {
-            const double lp = cl[m] * rs;
-            reg[m] = fma(-li, lp, reg[m]);
-            aug[m] = fma(-yi, lp, aug[m]);
-          } else if (m == jj) {
-            reg[m] = (i >= j) ? li : 0.0;
-            aug[m] = yi;
-          }
+        for (int c2 = c + 1; c2 < kB; ++c2) {
+          const double lm = lane_value(l, j0 + c2);     // L[j0 + c2][j]
+          rb[c2] = fma(-l, lm, rb[c2]);
+          yb[c2] = fma(-y, lm, yb[c2]);
         }
       }
-      // the wave owning column j + 1 publishes both parts of it
-      if (jj < 7) {
-        if (q == qb) {
-          colbuf[bsel ^ 1][i] = reg[(jj + 1) & 7];
-          colbuf[2 + (bsel ^ 1)][i] = aug[(jj + 1) & 7];
+#pragma unroll
+      for (int c = 0; c < kB; ++c) {
+        T[i][j0 + c] = rb[c];
+        Ut[i][j0 + c] = yb[c];
+      }
+    }
+    __syncthreads();
+    if (j0 + kB < kTile) {
+      double li[kB], yi[kB];
+#pragma unroll
+      for (int c = 0; c < kB; ++c) {
+        li[c] = T[i][j0 + c];
+        yi[c] = Ut[i][j0 + c];
+      }
+      for (int m = j0 + kB + w; m < kTile; m += kPT / 64) {
+        double t = T[i][m], u = Ut[i][m];
+#pragma unroll
+        for (int c = 0; c < kB; ++c) {
+          const double lm = T[m][j0 + c];                 // broadcast
+          t = fma(-li[c], lm, t);
+          u = fma(-yi[c], lm, u);
         }
-      } else if (q == qb + 1) {
-        colbuf[bsel ^ 1][i] = reg[0];
-        colbuf[2 + (bsel ^ 1)][i] = aug[0];
+        T[i][m] = t;
+        Ut[i][m] = u;
       }
       __syncthreads();
     }
   }
-  __syncthreads();
-#pragma unroll
-  for (int m = 0; m < 8; ++m) {
-    const int l = 8 * q + m;
-    T[i][l] = (l <= i) ? reg[m] : 0.0;
-    Ut[i][l] = (l >= i) ? aug[m] : 0.0;
+  if (w == 0) {
+    for (int k = i + 1; k < kTile; ++k) T[i][k] = 0.0;
+    if (i == 0) fail = f;
   }
   __syncthreads();
   return fail;
@@ -310,23 +323,36 @@ __device__ void gemv_upper(const PSArgs& a, const double* in, double* out, int b
   }
 }
 
-// out_j = sum_i U[i][j] in_i (U^T = L^-1, lower): one column per thread
-__device__ void gemv_upper_t(const PSArgs& a, const double* in, double* out, int bid) {
+// out_j = sum_{i <= j} U[i][j] in_i (U^T = L^-1, lower). The rows are cut
+// into chunks; wave (column block cb, chunk ch) sums its chunk for the 64
+// columns of the block (one column per lane, coalesced row reads) into
+// part[ch][j]; after a barrier the chunks are added in order.
+__device__ void gemv_upper_t(const PSArgs& a, const double* in, double* out, int bid, Barrier& bar) {
   const double* U = a.A + ((int64_t)a.Np + kTile) * a.Np;
-  for (int j = bid * kPT + threadIdx.x; j < a.Np; j += a.P * kPT) {
+  const int lane = threadIdx.x & 63;
+  const int nw = kPT / 64;
+  const int ncb = a.Np / 64;
+  const int nwaves = a.P * nw;
+  const int nch = nwaves >= ncb ? nwaves / ncb : 1;
+  const int len = (a.Np + nch - 1) / nch;
+  for (int gw = bid * nw + (threadIdx.x >> 6); gw < ncb * nch; gw += nwaves) {
+    const int cb = gw % ncb, ch = gw / ncb;
+    const int j = cb * 64 + lane;
+    const int i0 = ch * len;
+    const int i1 = min(min(i0 + len, a.Np), cb * 64 + 64);
     double acc = 0.0;
-    const int iend = j + 1;
-    int i = 0;
-    for (; i + 4 <= iend; i += 4) {
-      const double u0 = U[(int64_t)i * a.Np + j], u1 = U[(int64_t)(i + 1) * a.Np + j];
-      const double u2 = U[(int64_t)(i + 2) * a.Np + j], u3 = U[(int64_t)(i + 3) * a.Np + j];
-      acc = fma(u0, in[i], acc);
-      acc = fma(u1, in[i + 1], acc);
-      acc = fma(u2, in[i + 2], acc);
-      acc = fma(u3, in[i + 3], acc);
+#pragma unroll 8
+    for (int i = i0; i < i1; ++i) {
+      const double u = U[(int64_t)i * a.Np + j];
+      acc = (i <= j) ? fma(u, in[i], acc) : acc;
     }
-    for (; i < iend; ++i) acc = fma(U[(int64_t)i * a.Np + j], in[i], acc);
-    out[j] = acc;
+    a.part[(int64_t)ch * a.Np + j] = acc;
+  }
+  bar.wait(a);
+  for (int j = bid * kPT + threadIdx.x; j < a.Np; j += a.P * kPT) {
+    double s = 0.0;
+    for (int ch = 0; ch < nch; ++ch) s += a.part[(int64_t)ch * a.Np + j];
+    out[j] = s;
   }
 }
 
@@ -352,7 +378,6 @@ __device__ __forceinline__ void solve_body(const PSArgs& a, const int bid) {
   double (*T0)[kLD] = reinterpret_cast<double (*)[kLD]>(smem);
   double (*T1)[kLD] = reinterpret_cast<double (*)[kLD]>(smem + kTile * kLD);
   double (*T2)[kLD] = reinterpret_cast<double (*)[kLD]>(smem + 2 * kTile * kLD);
-  double (*colbuf)[kTile] = reinterpret_cast<double (*)[kTile]>(smem + 3 * kTile * kLD);
   __shared__ double red[kPT / 64];
   Barrier bar;
   bar.bid = bid;
@@ -395,26 +420,65 @@ __device__ __forceinline__ void solve_body(const PSArgs& a, const int bid) {
   bar.wait(a);
 
   // ---- factorisation of [A; v^T; I]
-  // factor the tile held in T0 (diagonal tile k) and store it
-  // factor the tile held in T0 (diagonal tile k); store L_kk and U_k = L_kk^-T
-  auto factor_diag = [&](int k) {
-    const int f = tile_potrf_aug(T0, T2, colbuf);
-    if (f >= 0) {
-      if (threadIdx.x == 0) atomicCAS(&a.flags[1], 0, k * kTile + f + 1);
-    } else {
-      store_tile(T0, a.A, Np, k, k);
-      for (int idx = threadIdx.x; idx < kTile * kTile; idx += kPT)
-        a.Ud[(int64_t)k * kTile * kTile + idx] = T2[idx >> 6][idx & 63];
-    }
-    __syncthreads();
-  };
-  if (bid == 0) {
-    load_tile(T0, a.A, Np, 0, 0);
-    __syncthreads();
-    factor_diag(0);
-  }
-  bar.wait(a);
+  // Step k: workgroup 0 applies the last update to diagonal tile k (from the
+  // panel of step k - 1) and factors it, storing L_kk and U_k = L_kk^-T,
+  // while the others apply the remaining trailing updates of step k - 1
+  // (look-ahead); then every workgroup takes panel tiles of column tile k.
   for (int k = 0; k < nt; ++k) {
+    if (bid == 0) {
+      load_tile(T0, a.A, Np, k, k);
+      if (k > 0) load_tile(T1, a.A, Np, k, k - 1);
+      __syncthreads();
+      if (k > 0) tile_sub_abt(T0, T1, T1);
+      const int f = tile_potrf_aug(T0, T2);
+      if (f >= 0) {
+        if (threadIdx.x == 0) atomicCAS(&a.flags[1], 0, k * kTile + f + 1);
+      } else {
+        store_tile(T0, a.A, Np, k, k);
+        for (int idx = threadIdx.x; idx < kTile * kTile; idx += kPT)
+          a.Ud[(int64_t)k * kTile * kTile + idx] = T2[idx >> 6][idx & 63];
+      }
+      __syncthreads();
+    }
+    // trailing update of step kp = k - 1 on column tiles J in [k, nt): rows
+    // of the matrix (J <= I < nt), the v row and the identity rows i <= kp;
+    // item 0, tile (k, k), is workgroup 0's
+    if (k > 0 && (P == 1 || bid > 0)) {
+      const int kp = k - 1;
+      const int m = nt - k;
+      const int ntri = m * (m + 1) / 2;
+      const int nv = m;
+      const int naug = k * m;
+      const int ntot = ntri + nv + naug;
+      const int first = (P > 1) ? bid - 1 : 0;
+      const int stride = (P > 1) ? P - 1 : 1;
+      for (int t = 1 + first; t < ntot; t += stride) {
+        int rt, J;
+        if (t < ntri) {
+          int ti, tj;
+          tri_decode(t, ti, tj);
+          rt = k + ti;
+          J = k + tj;
+        } else if (t < ntri + nv) {
+          rt = nt;
+          J = k + (t - ntri);
+        } else {
+          const int u = t - ntri - nv;
+          rt = nt + 1 + u / m;
+          J = k + u % m;
+        }
+        const int rows = (rt == nt) ? 1 : kTile;
+        const int64_t r0 = row_off(rt, nt, Np);
+        load_tile_r(T0, a.A, Np, r0, J, rows);
+        load_tile_r(T1, a.A, Np, r0, kp, rows);
+        load_tile(T2, a.A, Np, J, kp);
+        __syncthreads();
+        tile_sub_abt(T0, T1, T2);
+        store_tile_r(T0, a.A, Np, r0, J, rows);
+        __syncthreads();
+      }
+    }
+    bar.wait(a);
     if (failed(a)) break;
     // panel: row tiles k+1 .. nt-1 (matrix), nt (v row), nt+1+i for i <= k
     // (identity rows with nonzero entries in column tile k)
@@ -442,52 +506,6 @@ __device__ __forceinline__ void solve_body(const PSArgs& a, const int bid) {
       }
     }
     bar.wait(a);
-    if (k + 1 >= nt) break;
-    // trailing update of column tiles J in (k, nt): rows of the matrix
-    // (J <= I < nt), the v row and the identity rows i <= k; workgroup 0
-    // takes (k+1, k+1) and factors it (look-ahead)
-    const int m = nt - k - 1;
-    const int ntri = m * (m + 1) / 2;
-    const int nv = m;
-    const int naug = (k + 1) * m;
-    const int ntot = ntri + nv + naug;
-    if (bid == 0) {
-      load_tile(T0, a.A, Np, k + 1, k + 1);
-      load_tile(T1, a.A, Np, k + 1, k);
-      __syncthreads();
-      tile_sub_abt(T0, T1, T1);
-      factor_diag(k + 1);
-    }
-    if (P == 1 || bid > 0) {
-      const int first = (P > 1) ? bid - 1 : 0;
-      const int stride = (P > 1) ? P - 1 : 1;
-      for (int t = 1 + first; t < ntot; t += stride) {
-        int rt, J;
-        if (t < ntri) {
-          int ti, tj;
-          tri_decode(t, ti, tj);
-          rt = k + 1 + ti;
-          J = k + 1 + tj;
-        } else if (t < ntri + nv) {
-          rt = nt;
-          J = k + 1 + (t - ntri);
-        } else {
-          const int u = t - ntri - nv;
-          rt = nt + 1 + u / m;
-          J = k + 1 + u % m;
-        }
-        const int rows = (rt == nt) ? 1 : kTile;
-        const int64_t r0 = row_off(rt, nt, Np);
-        load_tile_r(T0, a.A, Np, r0, J, rows);
-        load_tile_r(T1, a.A, Np, r0, k, rows);
-        load_tile(T2, a.A, Np, J, k);
-        __syncthreads();
-        tile_sub_abt(T0, T1, T2);
-        store_tile_r(T0, a.A, Np, r0, J, rows);
-        __syncthreads();
-      }
-    }
-    bar.wait(a);
   }
   const bool bad = failed(a);
   // ---- x = L^-T z, theta = D x, refinement
@@ -499,7 +517,7 @@ __device__ __forceinline__ void solve_body(const PSArgs& a, const int bid) {
     for (int it = 0; it < a.refine; ++it) {
       residual(a, bid);                  // r = D (h - G theta)
       bar.wait(a);
-      gemv_upper_t(a, a.r, a.x, bid);    // x = L^-1 r
+      gemv_upper_t(a, a.r, a.x, bid, bar);   // x = L^-1 r
       bar.wait(a);
       gemv_upper(a, a.x, a.r, bid);      // r = L^-T x
       bar.wait(a);
@@ -580,7 +598,7 @@ __global__ void k_solve_reset(unsigned* sync, int nsync, int* flags) {
 }
 
 size_t solve_shmem_bytes() {
-  return sizeof(double) * (3 * kTile * kLD + 4 * kTile);
+  return sizeof(double) * (3 * kTile * kLD);
 }
 
 int solve_workgroups(int nt) {
@@ -610,6 +628,7 @@ static PSArgs make_solve_args(const sfft_desc& d, const double* G, const double*
   a.r = reinterpret_cast<double*>(ws + l.rvec);
   a.rowabs = reinterpret_cast<double*>(ws + l.rowabs);
   a.Ud = reinterpret_cast<double*>(ws + l.Ud);
+  a.part = reinterpret_cast<double*>(ws + l.part);
   a.sync = reinterpret_cast<unsigned*>(ws + l.sync);
   a.stamps = reinterpret_cast<unsigned long long*>(ws + l.sync + 512);
   a.flags = reinterpret_cast<int*>(ws + l.flags);
