@@ -103,22 +103,52 @@ __device__ __forceinline__ bool failed(const PSArgs& a) {
 // tile helpers (512 threads)
 // ---------------------------------------------------------------------------
 
+constexpr int kPerThread = kTile * kTile / kPT;   // tile elements per thread
+
+// rows [r0, r0 + rows) x columns [c0, c0 + 64) of a row-major matrix with
+// leading dimension ld into an LDS tile (zeros below `rows`): every global
+// load of the thread is issued before the first LDS store, so one memory
+// latency is paid per tile instead of one per element
+__device__ __forceinline__ void tile_in(double (*T)[kLD], const double* A, int64_t ld, int64_t r0, int64_t c0,
+                                        int rows = kTile) {
+  double v[kPerThread];
+#pragma unroll
+  for (int t = 0; t < kPerThread; ++t) {
+    const int idx = threadIdx.x + t * kPT;
+    const int i = idx >> 6, j = idx & 63;
+    v[t] = (i < rows) ? A[(r0 + i) * ld + c0 + j] : 0.0;
+  }
+#pragma unroll
+  for (int t = 0; t < kPerThread; ++t) {
+    const int idx = threadIdx.x + t * kPT;
+    T[idx >> 6][idx & 63] = v[t];
+  }
+}
+
+__device__ __forceinline__ void tile_out(const double (*T)[kLD], double* A, int64_t ld, int64_t r0, int64_t c0,
+                                         int rows = kTile) {
+  double v[kPerThread];
+#pragma unroll
+  for (int t = 0; t < kPerThread; ++t) {
+    const int idx = threadIdx.x + t * kPT;
+    v[t] = T[idx >> 6][idx & 63];
+  }
+#pragma unroll
+  for (int t = 0; t < kPerThread; ++t) {
+    const int idx = threadIdx.x + t * kPT;
+    const int i = idx >> 6, j = idx & 63;
+    if (i < rows) A[(r0 + i) * ld + c0 + j] = v[t];
+  }
+}
+
 __device__ __forceinline__ void load_tile(double (*T)[kLD], const double* A, int Np, int ti, int tj,
                                           int rows = kTile) {
-  const int64_t o = (int64_t)ti * kTile * Np + (int64_t)tj * kTile;
-  for (int idx = threadIdx.x; idx < kTile * kTile; idx += kPT) {
-    const int i = idx >> 6, j = idx & 63;
-    T[i][j] = (i < rows) ? A[o + (int64_t)i * Np + j] : 0.0;
-  }
+  tile_in(T, A, Np, (int64_t)ti * kTile, (int64_t)tj * kTile, rows);
 }
 
 __device__ __forceinline__ void store_tile(const double (*T)[kLD], double* A, int Np, int ti, int tj,
                                            int rows = kTile) {
-  const int64_t o = (int64_t)ti * kTile * Np + (int64_t)tj * kTile;
-  for (int idx = threadIdx.x; idx < kTile * kTile; idx += kPT) {
-    const int i = idx >> 6, j = idx & 63;
-    if (i < rows) A[o + (int64_t)i * Np + j] = T[i][j];
-  }
+  tile_out(T, A, Np, (int64_t)ti * kTile, (int64_t)tj * kTile, rows);
 }
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
@@ -294,18 +324,11 @@ __device__ __forceinline__ int64_t row_off(int t, int nt, int Np) {
 
 __device__ __forceinline__ void load_tile_r(double (*T)[kLD], const double* A, int Np, int64_t r0, int tj,
                                             int rows = kTile) {
-  for (int idx = threadIdx.x; idx < kTile * kTile; idx += kPT) {
-    const int i = idx >> 6, j = idx & 63;
-    T[i][j] = (i < rows) ? A[(r0 + i) * Np + (int64_t)tj * kTile + j] : 0.0;
-  }
+  tile_in(T, A, Np, r0, (int64_t)tj * kTile, rows);
 }
-
 __device__ __forceinline__ void store_tile_r(const double (*T)[kLD], double* A, int Np, int64_t r0, int tj,
                                              int rows = kTile) {
-  for (int idx = threadIdx.x; idx < kTile * kTile; idx += kPT) {
-    const int i = idx >> 6, j = idx & 63;
-    if (i < rows) A[(r0 + i) * Np + (int64_t)tj * kTile + j] = T[i][j];
-  }
+  tile_out(T, A, Np, r0, (int64_t)tj * kTile, rows);
 }
 
 // out_i = sum_j U[i][j] in_j with U = L^-T stored in the identity rows
@@ -317,6 +340,7 @@ __device__ void gemv_upper(const PSArgs& a, const double* in, double* out, int b
   for (int i = bid * nw + wave; i < a.Np; i += a.P * nw) {
     const double* Ur = U + (int64_t)i * a.Np;
     double acc = 0.0;
+#pragma unroll 4
     for (int j = (i & ~63) + lane; j < a.Np; j += 64) acc = fma(Ur[j], in[j], acc);
     acc = wave_sum(acc);
     if (lane == 0) out[i] = acc;
@@ -367,6 +391,7 @@ __device__ void residual(const PSArgs& a, int bid) {
     }
     const double* Gr = a.G + (int64_t)i * a.N;
     double sacc = 0.0;
+#pragma unroll 4
     for (int j = lane; j < a.N; j += 64) sacc = fma(Gr[j], a.theta[j], sacc);
     sacc = wave_sum(sacc);
     if (lane == 0) a.r[i] = a.s[i] * (a.h[i] - sacc);
@@ -435,8 +460,7 @@ __device__ __forceinline__ void solve_body(const PSArgs& a, const int bid) {
         if (threadIdx.x == 0) atomicCAS(&a.flags[1], 0, k * kTile + f + 1);
       } else {
         store_tile(T0, a.A, Np, k, k);
-        for (int idx = threadIdx.x; idx < kTile * kTile; idx += kPT)
-          a.Ud[(int64_t)k * kTile * kTile + idx] = T2[idx >> 6][idx & 63];
+        tile_out(T2, a.Ud + (int64_t)k * kTile * kTile, kTile, 0, 0);
       }
       __syncthreads();
     }
@@ -494,8 +518,7 @@ __device__ __forceinline__ void solve_body(const PSArgs& a, const int bid) {
         const int rows = (rt == nt) ? 1 : kTile;
         const int64_t r0 = row_off(rt, nt, Np);
         if (!loaded) {
-          for (int idx = threadIdx.x; idx < kTile * kTile; idx += kPT)
-            T1[idx >> 6][idx & 63] = a.Ud[(int64_t)k * kTile * kTile + idx];
+          tile_in(T1, a.Ud + (int64_t)k * kTile * kTile, kTile, 0, 0);
           loaded = true;
         }
         load_tile_r(T0, a.A, Np, r0, k, rows);

@@ -48,6 +48,10 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
   __shared__ double K2[(2 * DK + 1) * (2 * DK + 1)];
   const int tid = threadIdx.x;
   const int W = a.W, H = a.H;
+  // the fitted coefficients are read-only for the whole launch: reading them
+  // through the constant address space lets uniform reads use scalar loads
+  const __attribute__((address_space(4))) double* coef =
+      (const __attribute__((address_space(4))) double*)a.coef;
   const int x0 = vb.x * TX, y0 = vb.y * TY;
   for (int i = tid; i < NK * L * L; i += 128) cs[i] = a.coef[i];
   __syncthreads();
@@ -111,22 +115,20 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
     uy = (uy >= H) ? uy - H : uy;
     uy = (uy >= H) ? uy - H : uy;
     const double yt = (double)uy * a.sy - 1.0;
-    double ypw[DK + 1];
-    ypw[0] = 1.0;
-#pragma unroll
-    for (int b = 1; b <= DK; ++b) ypw[b] = ypw[b - 1] * yt;
     double win[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) win[q] = Rt[lr][P * tx + q];
 #pragma unroll
     for (int dxi = 0; dxi < L; ++dxi) {
       const int tap = dyi * L + dxi;
+      // c_m = sum_b a_((m,b),d) yt^b by Horner in yt; the coefficients are
+      // uniform across the workgroup and come through the scalar cache
       double cm[DK + 1];
 #pragma unroll
       for (int m = 0; m <= DK; ++m) {
-        double s = 0.0;
+        double s = coef[mono_index(m, DK - m) * L * L + tap];
 #pragma unroll
-        for (int b = 0; b <= DK - m; ++b) s = fma(cs[mono_index(m, b) * L * L + tap], ypw[b], s);
+        for (int b = DK - m - 1; b >= 0; --b) s = fma(s, yt, coef[mono_index(m, b) * L * L + tap]);
         cm[m] = s;
       }
       // Horner in xt for all P pixels stage by stage: P independent chains
