@@ -156,70 +156,35 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const VB vb) {
   const int W = a.W;
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* tw = buf + (W + W / 8);
-  double* red = reinterpret_cast<double*>(tw + W);   // [kRowThreads/64][16]
   const cx<T>* twg = static_cast<const cx<T>*>(a.twW);
   for (int i = threadIdx.x; i < W; i += kRowThreads) tw[i] = twg[i];
   constexpr int MAXQ = NQ;
-  const int nm = a.DK + a.DB + 1;
   const int nsig = a.DK + 2;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   cx<T>* F = static_cast<cx<T>*>(a.F);
 
-  for (int y = vb.x; y < a.H; y += vb.nx) {
-    double rp[MAXQ], sp[MAXQ];
-    double mr[9], ms[5];
-#pragma unroll
-    for (int m = 0; m < 9; ++m) mr[m] = 0.0;
-#pragma unroll
-    for (int m = 0; m < 5; ++m) ms[m] = 0.0;
-    bool bad = false;
+  // pixels of the workgroup's next row, loaded while the current row is
+  // transformed (row moments, edge pixels and the input check are done by
+  // k_row_moments)
+  TIN rn[MAXQ], sn[MAXQ];
+  auto prefetch = [&](int yy) {
 #pragma unroll
     for (int q = 0; q < MAXQ; ++q) {
       const int x = threadIdx.x + q * kRowThreads;
-      rp[q] = 0.0;
-      sp[q] = 0.0;
-      if (x < W) {
-        const double rv = load_pix<TIN>(a.R, (int64_t)y * a.ld + x) - a.cR;
-        const double sv = load_pix<TIN>(a.S, (int64_t)y * a.ld + x) - a.cS;
-        bad |= !(is_finite_d(rv) && is_finite_d(sv));
-        rp[q] = rv;
-        sp[q] = sv;
-        const double xt = (double)x * a.sx - 1.0;
-        double pw = 1.0;
+      const bool in = x < W && yy < a.H;
+      rn[q] = in ? static_cast<const TIN*>(a.R)[(int64_t)yy * a.ld + x] : (TIN)0;
+      sn[q] = in ? static_cast<const TIN*>(a.S)[(int64_t)yy * a.ld + x] : (TIN)0;
+    }
+  };
+  prefetch(vb.x);
+
+  for (int y = vb.x; y < a.H; y += vb.nx) {
+    TIN rc[MAXQ], sc[MAXQ];
 #pragma unroll
-        for (int m = 0; m < 9; ++m) {
-          if (m < nm) mr[m] = fma(pw, rv, mr[m]);
-          if (m <= a.DB && m < 5) ms[m] = fma(pw, sv, ms[m]);
-          pw *= xt;
-        }
-        if (x < a.r) a.ER[(int64_t)y * 2 * a.r + x] = rv;
-        if (x >= W - a.r) a.ER[(int64_t)y * 2 * a.r + a.r + (x - (W - a.r))] = rv;
-      }
+    for (int q = 0; q < MAXQ; ++q) {
+      rc[q] = rn[q];
+      sc[q] = sn[q];
     }
-    if (bad) atomicOr(a.flags, 1);
-    // moments: wave sums, then one value per (wave, moment) in LDS
-#pragma unroll
-    for (int m = 0; m < 9; ++m) {
-      if (m < nm) {
-        double v = wave_sum(mr[m]);
-        if (lane == 0) red[wid * 16 + m] = v;
-      }
-    }
-#pragma unroll
-    for (int m = 0; m < 5; ++m) {
-      if (m <= a.DB) {
-        double v = wave_sum(ms[m]);
-        if (lane == 0) red[wid * 16 + 9 + m] = v;
-      }
-    }
-    __syncthreads();
-    if (threadIdx.x < 16) {
-      const int m = threadIdx.x;
-      double s = 0.0;
-      for (int w = 0; w < kRowThreads / 64; ++w) s += red[w * 16 + m];
-      if (m < nm) a.MR[(int64_t)m * a.H + y] = s;
-      else if (m >= 9 && m - 9 <= a.DB) a.MS[(int64_t)(m - 9) * a.H + y] = s;
-    }
+    prefetch(y + vb.nx);
     // transforms: real signals s_a = xt^a R' (a <= DK), s_{DK+1} = S',
     // packed two per complex transform
     for (int f = 0; 2 * f < nsig; ++f) {
@@ -229,9 +194,10 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const VB vb) {
         const int x = threadIdx.x + q * kRowThreads;
         if (x < W) {
           const double xt = (double)x * a.sx - 1.0;
-          const double v0 = (s0 <= a.DK) ? ipow(xt, s0) * rp[q] : sp[q];
+          const double rv = (double)rc[q] - a.cR, sv = (double)sc[q] - a.cS;
+          const double v0 = (s0 <= a.DK) ? ipow(xt, s0) * rv : sv;
           double v1 = 0.0;
-          if (s1 < nsig) v1 = (s1 <= a.DK) ? ipow(xt, s1) * rp[q] : sp[q];
+          if (s1 < nsig) v1 = (s1 <= a.DK) ? ipow(xt, s1) * rv : sv;
           buf[pad8(x)] = cx<T>{(T)v0, (T)v1};
         }
       }
@@ -870,56 +836,107 @@ __global__ __launch_bounds__(256) void k_gather_kk_batch(const GatherArgs* args,
 // polynomial moments; only the row moments are needed, not the spectra.
 // ---------------------------------------------------------------------------
 
+// Row moments MR[m][y] = sum_x xt^m R'(x, y) (m <= DK + DB) and
+// MS[m][y] = sum_x xt^m S'(x, y) (m <= DB), the r edge pixels of R' of every
+// row, and the non-finite input flag. A wave takes 2 rows; the 32 lanes of a
+// row read 4 consecutive pixels each per 128-pixel span (one 16-byte load
+// when the rows are 16-byte aligned), four spans in flight at a time, keep
+// partial sums in registers and add them over the 32 lanes at the end.
+constexpr int kMomRowsPerWave = 2;
+constexpr int kMomRowsPerWG = kMomRowsPerWave * (kRowThreads / 64);
+
 template <typename TIN>
-__global__ __launch_bounds__(kRowThreads) void k_row_moments(RowArgs a) {
-  __shared__ double red[kRowThreads / 64][16];
+__device__ __forceinline__ void row_moments_body(const RowArgs& a, const VB vb) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rr = lane >> 5, cc = lane & 31;
+  const int y = vb.x * kMomRowsPerWG + wave * kMomRowsPerWave + rr;
   const int W = a.W;
   const int nm = a.DK + a.DB + 1;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int y = blockIdx.x; y < a.H; y += gridDim.x) {
-    double mr[9], ms[5];
+  double mr[9], ms[5];
 #pragma unroll
-    for (int m = 0; m < 9; ++m) mr[m] = 0.0;
+  for (int m = 0; m < 9; ++m) mr[m] = 0.0;
 #pragma unroll
-    for (int m = 0; m < 5; ++m) ms[m] = 0.0;
-    bool bad = false;
-    for (int x = threadIdx.x; x < W; x += kRowThreads) {
-      const double rv = load_pix<TIN>(a.R, (int64_t)y * a.ld + x) - a.cR;
-      const double sv = load_pix<TIN>(a.S, (int64_t)y * a.ld + x) - a.cS;
-      bad |= !(is_finite_d(rv) && is_finite_d(sv));
-      const double xt = (double)x * a.sx - 1.0;
-      double pw = 1.0;
-#pragma unroll
-      for (int m = 0; m < 9; ++m) {
-        if (m < nm) mr[m] = fma(pw, rv, mr[m]);
-        if (m <= a.DB && m < 5) ms[m] = fma(pw, sv, ms[m]);
-        pw *= xt;
-      }
-      if (x < a.r) a.ER[(int64_t)y * 2 * a.r + x] = rv;
-      if (x >= W - a.r) a.ER[(int64_t)y * 2 * a.r + a.r + (x - (W - a.r))] = rv;
-    }
-    if (bad) atomicOr(a.flags, 1);
+  for (int m = 0; m < 5; ++m) ms[m] = 0.0;
+  bool bad = false;
+  auto accumulate = [&](int x, double rv, double sv) {
+    bad |= !(is_finite_d(rv) && is_finite_d(sv));
+    if (x < a.r) a.ER[(int64_t)y * 2 * a.r + x] = rv;
+    if (x >= W - a.r) a.ER[(int64_t)y * 2 * a.r + a.r + (x - (W - a.r))] = rv;
+    const double xt = (double)x * a.sx - 1.0;
+    double pw = 1.0;
 #pragma unroll
     for (int m = 0; m < 9; ++m) {
-      const double v = wave_sum(mr[m]);
-      if (lane == 0) red[wid][m] = v;
+      if (m < nm) mr[m] = fma(pw, rv, mr[m]);
+      if (m <= a.DB && m < 5) ms[m] = fma(pw, sv, ms[m]);
+      pw *= xt;
     }
+  };
+  if (y < a.H) {
+    const TIN* Rr = static_cast<const TIN*>(a.R) + (int64_t)y * a.ld;
+    const TIN* Sr = static_cast<const TIN*>(a.S) + (int64_t)y * a.ld;
+    const bool vec = sizeof(TIN) == 4 && ((reinterpret_cast<uintptr_t>(Rr) | reinterpret_cast<uintptr_t>(Sr)) & 15) == 0;
+    for (int x00 = 0; x00 < W; x00 += 4 * 128) {
+      TIN rv[4][4], sv[4][4];
 #pragma unroll
-    for (int m = 0; m < 5; ++m) {
-      const double v = wave_sum(ms[m]);
-      if (lane == 0) red[wid][9 + m] = v;
+      for (int u = 0; u < 4; ++u) {
+        const int x0 = x00 + u * 128 + cc * 4;
+        if (vec && x0 + 3 < W) {
+          const float4 r4 = *reinterpret_cast<const float4*>(Rr + x0);
+          const float4 s4 = *reinterpret_cast<const float4*>(Sr + x0);
+          rv[u][0] = r4.x; rv[u][1] = r4.y; rv[u][2] = r4.z; rv[u][3] = r4.w;
+          sv[u][0] = s4.x; sv[u][1] = s4.y; sv[u][2] = s4.z; sv[u][3] = s4.w;
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            rv[u][k] = (x0 + k < W) ? Rr[x0 + k] : (TIN)0;
+            sv[u][k] = (x0 + k < W) ? Sr[x0 + k] : (TIN)0;
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int x = x00 + u * 128 + cc * 4 + k;
+          if (x < W) accumulate(x, (double)rv[u][k] - a.cR, (double)sv[u][k] - a.cS);
+        }
     }
-    __syncthreads();
-    if (threadIdx.x < 16) {
-      const int m = threadIdx.x;
-      double sum = 0.0;
-      for (int w = 0; w < kRowThreads / 64; ++w) sum += red[w][m];
-      if (m < nm) a.MR[(int64_t)m * a.H + y] = sum;
-      else if (m >= 9 && m - 9 <= a.DB) a.MS[(int64_t)(m - 9) * a.H + y] = sum;
+  }
+  if (bad) atomicOr(a.flags, 1);
+  // sum over the 32 lanes of each row (fixed order: butterfly 16, 8, 4, 2, 1)
+#pragma unroll
+  for (int m = 0; m < 9; ++m) {
+    if (m < nm) {
+      double v = mr[m];
+#pragma unroll
+      for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 32);
+      if (cc == 0 && y < a.H) a.MR[(int64_t)m * a.H + y] = v;
     }
-    __syncthreads();
+  }
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    if (m <= a.DB) {
+      double v = ms[m];
+#pragma unroll
+      for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 32);
+      if (cc == 0 && y < a.H) a.MS[(int64_t)m * a.H + y] = v;
+    }
   }
 }
+
+template <typename TIN>
+__global__ __launch_bounds__(kRowThreads) void k_row_moments(RowArgs a) {
+  row_moments_body<TIN>(a, vb_grid());
+}
+
+__global__ __launch_bounds__(kRowThreads) void k_row_moments_batch(const RowArgs* args, const BatchTab* tab,
+                                                                  int n) {
+  int item;
+  VB vb;
+  if (batch_locate(tab, n, item, vb)) row_moments_body<float>(args[item], vb);
+}
+
+inline int row_moments_grid(int H) { return (H + kMomRowsPerWG - 1) / kMomRowsPerWG; }
 
 // b = G_bb^-1 (h_b - G_kb^T a): one workgroup; FP64 dot products in a fixed
 // order, Cholesky of the (at most 15 x 15) background block by one thread
@@ -1160,6 +1177,14 @@ hipError_t launch_build(const sfft_desc& d, const void* R, const void* S, double
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st,
                      reinterpret_cast<int*>(ws + l.flags), 64, 0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  {
+    const RowArgs ra = make_row_args(g, d, R, S, ws, l, p);
+    if (d.image_dtype == SFFT_F32)
+      hipLaunchKernelGGL(k_row_moments<float>, dim3(row_moments_grid(g.H)), dim3(kRowThreads), 0, st, ra);
+    else
+      hipLaunchKernelGGL(k_row_moments<double>, dim3(row_moments_grid(g.H)), dim3(kRowThreads), 0, st, ra);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   prof_begin(pf, SFFT_PROF_ROW_PASS, st);
   e = g.fp32 ? launch_row<float>(g, d, R, S, ws, l, p, st)
              : launch_row<double>(g, d, R, S, ws, l, p, st);
@@ -1210,8 +1235,8 @@ struct BuildBatchHost {
   std::vector<KbArgs> kb;
   std::vector<GatherArgs> gat;
   std::vector<int*> flags;
-  std::vector<BatchTab> trow, tcol, txinv, tmom, tkb, tgat;
-  int brow = 0, bcol = 0, bxinv = 0, bmom = 0, bkb = 0, bgat = 0;   // total blocks per phase
+  std::vector<BatchTab> trm, trow, tcol, txinv, tmom, tkb, tgat;
+  int brm = 0, brow = 0, bcol = 0, bxinv = 0, bmom = 0, bkb = 0, bgat = 0;   // total blocks per phase
   size_t row_shmem = 0;
 };
 
@@ -1223,7 +1248,7 @@ struct BuildBatchDev {
   KbArgs* kb;
   GatherArgs* gat;
   int* const* flags;
-  BatchTab *trow, *tcol, *txinv, *tmom, *tkb, *tgat;
+  BatchTab *trm, *trow, *tcol, *txinv, *tmom, *tkb, *tgat;
 };
 
 struct BuildBatch {
@@ -1255,6 +1280,7 @@ static hipError_t plan_build_batch(const BuildItem* items, int n, const BuildPla
     if (k > 0 && g.nK != h.nK) return hipErrorInvalidValue;
     h.nK = g.nK;
     h.row.push_back(make_row_args(g, it.d, it.R, it.S, it.ws, l, plans[k]));
+    tab_push(h.trm, h.brm, row_moments_grid(g.H), 1);
     const int rpb = rows_per_block > 0 ? rows_per_block : 4;
     tab_push(h.trow, h.brow, (g.H + rpb - 1) / rpb, 1);
     h.row_shmem = std::max(h.row_shmem, row_shmem<float>(g.W));
@@ -1283,6 +1309,8 @@ hipError_t build_batch_launch(const BuildBatch* b, const Prof* pf, hipStream_t s
   hipError_t e;
   prof_begin(pf, SFFT_PROF_BUILD, st);
   hipLaunchKernelGGL(k_fill_flags_batch, dim3(h.n), dim3(64), 0, st, d.flags, h.n);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_row_moments_batch, dim3(h.brm), dim3(kRowThreads), 0, st, d.row, d.trm, h.n);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   prof_begin(pf, SFFT_PROF_ROW_PASS, st);
   hipLaunchKernelGGL((k_row_pass_batch<float, float, 8, true>), dim3(h.brow), dim3(kRowThreads), h.row_shmem,
@@ -1316,11 +1344,10 @@ hipError_t launch_bg_refit(const sfft_desc& d, const void* R, const void* S, dou
   const Geometry g = make_geometry(d);
   const Layout l = make_layout(g);
   const RowArgs ra = make_row_args(g, d, R, S, ws, l, p);
-  const int grid = g.H < 4 * p.num_cus ? g.H : 4 * p.num_cus;
   if (d.image_dtype == SFFT_F32)
-    hipLaunchKernelGGL(k_row_moments<float>, dim3(grid), dim3(kRowThreads), 0, st, ra);
+    hipLaunchKernelGGL(k_row_moments<float>, dim3(row_moments_grid(g.H)), dim3(kRowThreads), 0, st, ra);
   else
-    hipLaunchKernelGGL(k_row_moments<double>, dim3(grid), dim3(kRowThreads), 0, st, ra);
+    hipLaunchKernelGGL(k_row_moments<double>, dim3(row_moments_grid(g.H)), dim3(kRowThreads), 0, st, ra);
   hipError_t e;
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const MomArgs ma = make_mom_args(g, ws, l);
@@ -1339,7 +1366,7 @@ static size_t dev_bytes(const BuildBatchHost& h) {
   auto add = [&](size_t b) { o = align256(o) + b; };
   add(n * sizeof(RowArgs)); add(n * sizeof(ColArgs)); add(n * sizeof(XinvArgs)); add(n * sizeof(MomArgs));
   add(n * sizeof(KbArgs)); add(n * sizeof(GatherArgs)); add(n * sizeof(int*));
-  for (int t = 0; t < 6; ++t) add(n * sizeof(BatchTab));
+  for (int t = 0; t < 7; ++t) add(n * sizeof(BatchTab));
   return align256(o);
 }
 
@@ -1361,6 +1388,7 @@ static hipError_t upload(const BuildBatchHost& h, unsigned char* dev, BuildBatch
   d.kb = reinterpret_cast<KbArgs*>(put(h.kb.data(), n * sizeof(KbArgs)));
   d.gat = reinterpret_cast<GatherArgs*>(put(h.gat.data(), n * sizeof(GatherArgs)));
   d.flags = reinterpret_cast<int* const*>(put(h.flags.data(), n * sizeof(int*)));
+  d.trm = reinterpret_cast<BatchTab*>(put(h.trm.data(), n * sizeof(BatchTab)));
   d.trow = reinterpret_cast<BatchTab*>(put(h.trow.data(), n * sizeof(BatchTab)));
   d.tcol = reinterpret_cast<BatchTab*>(put(h.tcol.data(), n * sizeof(BatchTab)));
   d.txinv = reinterpret_cast<BatchTab*>(put(h.txinv.data(), n * sizeof(BatchTab)));

@@ -344,6 +344,7 @@ __global__ __launch_bounds__(256) void k_pool_fwd(const T* h, const float* pos, 
   for (int o = threadIdx.x; o < kNetU; o += 256) {
     const int i = o / kNetH, c = o % kNetH;
     float s = 0.0f;
+#pragma unroll 8
     for (int t = 0; t < S; ++t) {
       const int n = b * S + t;
       float m[6];
@@ -438,6 +439,11 @@ static hipError_t set_fwd_attrs() {
   SFFT_SET((k_conv_fwd<SFFT_CONV_CFG2, 32, T>), (conv_fwd_lds<SFFT_CONV_CFG2, 32>()));
   SFFT_SET((k_conv_fwd<SFFT_CONV_CFG3, 64, T>), (conv_fwd_lds<SFFT_CONV_CFG3, 64>()));
   SFFT_SET((k_conv_fwd<SFFT_CONV_CFG4, 32, T>), (conv_fwd_lds<SFFT_CONV_CFG4, 32>()));
+  // narrow batches (inference on a few pairs): more workgroups per layer
+  SFFT_SET((k_conv_fwd<SFFT_CONV_CFG1, 8, T>), (conv_fwd_lds<SFFT_CONV_CFG1, 8>()));
+  SFFT_SET((k_conv_fwd<SFFT_CONV_CFG2, 8, T>), (conv_fwd_lds<SFFT_CONV_CFG2, 8>()));
+  SFFT_SET((k_conv_fwd<SFFT_CONV_CFG3, 32, T>), (conv_fwd_lds<SFFT_CONV_CFG3, 32>()));
+  SFFT_SET((k_conv_fwd<SFFT_CONV_CFG4, 16, T>), (conv_fwd_lds<SFFT_CONV_CFG4, 16>()));
   return hipSuccess;
 }
 
@@ -456,9 +462,37 @@ hipError_t prepare_surrogate_attributes() {
   return hipSuccess;
 }
 
+// C = A B^T (+ bias, ReLU) for few rows of A (inference): one wave per
+// output element, lanes over k (coalesced rows of A and of B), FP32
+// accumulation, butterfly sum over the wave
+template <typename T, typename TO>
+__global__ __launch_bounds__(256) void k_gemm_rows(const T* A, const T* B, TO* C, int M, int N, int K, int lda,
+                                                   int ldb, int ldc, const T* bias, int relu) {
+  const int64_t wv = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (wv >= (int64_t)M * N) return;            // whole waves only
+  const int i = (int)(wv / N), j = (int)(wv % N);
+  float acc = 0.0f;
+#pragma unroll 4
+  for (int k = lane; k < K; k += 64) acc = fmaf(ldv(A, (int64_t)i * lda + k), ldv(B, (int64_t)j * ldb + k), acc);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (lane == 0) {
+    float c = acc + (bias ? ldv(bias, j) : 0.0f);
+    if (relu) c = fmaxf(c, 0.0f);
+    stv(C, (int64_t)i * ldc + j, c);
+  }
+}
+
 template <bool TA, bool TB, typename T, typename TO>
 static void gemm(const T* A, const T* B, TO* C, int M, int N, int K, int lda, int ldb, int ldc, const T* bias,
                  int relu, const float* mask, hipStream_t st) {
+  if (!TA && TB && !mask && M <= 1024) {
+    const int64_t waves = (int64_t)M * N;
+    hipLaunchKernelGGL((k_gemm_rows<T, TO>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, A, B, C, M, N,
+                       K, lda, ldb, ldc, bias, relu);
+    return;
+  }
   const dim3 grid((N + 63) / 64, (M + 63) / 64);
   hipLaunchKernelGGL((k_gemm<TA, TB, T, TO>), grid, dim3(256), 0, st, A, B, C, M, N, K, lda, ldb, ldc, bias,
                      relu, mask);
@@ -490,14 +524,27 @@ static void forward_t(const T* P, const T* x, const float* pos, int n_pairs, int
   T* h = reinterpret_cast<T*>(ws + w.h);
   T* u = reinterpret_cast<T*>(ws + w.u);
   T* g = reinterpret_cast<T*>(ws + w.g);
-  hipLaunchKernelGGL((k_conv_fwd<SFFT_CONV_CFG1, 16, T>), dim3(ns, 1), dim3(256),
-                     (conv_fwd_lds<SFFT_CONV_CFG1, 16>()), st, x, P + L.cw[0], P + L.cb[0], a1);
-  hipLaunchKernelGGL((k_conv_fwd<SFFT_CONV_CFG2, 32, T>), dim3(ns, 1), dim3(256),
-                     (conv_fwd_lds<SFFT_CONV_CFG2, 32>()), st, a1, P + L.cw[1], P + L.cb[1], a2);
-  hipLaunchKernelGGL((k_conv_fwd<SFFT_CONV_CFG3, 64, T>), dim3(ns, 1), dim3(256),
-                     (conv_fwd_lds<SFFT_CONV_CFG3, 64>()), st, a2, P + L.cw[2], P + L.cb[2], a3);
-  hipLaunchKernelGGL((k_conv_fwd<SFFT_CONV_CFG4, 32, T>), dim3(ns, 2), dim3(256),
-                     (conv_fwd_lds<SFFT_CONV_CFG4, 32>()), st, a3, P + L.cw[3], P + L.cb[3], a4);
+  if (ns < 1024) {
+    // few stamps (inference on one or a few pairs): split the output channels
+    // over more workgroups so that the layers fill the GPU (same arithmetic)
+    hipLaunchKernelGGL((k_conv_fwd<SFFT_CONV_CFG1, 8, T>), dim3(ns, 2), dim3(256),
+                       (conv_fwd_lds<SFFT_CONV_CFG1, 8>()), st, x, P + L.cw[0], P + L.cb[0], a1);
+    hipLaunchKernelGGL((k_conv_fwd<SFFT_CONV_CFG2, 8, T>), dim3(ns, 4), dim3(256),
+                       (conv_fwd_lds<SFFT_CONV_CFG2, 8>()), st, a1, P + L.cw[1], P + L.cb[1], a2);
+    hipLaunchKernelGGL((k_conv_fwd<SFFT_CONV_CFG3, 32, T>), dim3(ns, 2), dim3(256),
+                       (conv_fwd_lds<SFFT_CONV_CFG3, 32>()), st, a2, P + L.cw[2], P + L.cb[2], a3);
+    hipLaunchKernelGGL((k_conv_fwd<SFFT_CONV_CFG4, 16, T>), dim3(ns, 4), dim3(256),
+                       (conv_fwd_lds<SFFT_CONV_CFG4, 16>()), st, a3, P + L.cw[3], P + L.cb[3], a4);
+  } else {
+    hipLaunchKernelGGL((k_conv_fwd<SFFT_CONV_CFG1, 16, T>), dim3(ns, 1), dim3(256),
+                       (conv_fwd_lds<SFFT_CONV_CFG1, 16>()), st, x, P + L.cw[0], P + L.cb[0], a1);
+    hipLaunchKernelGGL((k_conv_fwd<SFFT_CONV_CFG2, 32, T>), dim3(ns, 1), dim3(256),
+                       (conv_fwd_lds<SFFT_CONV_CFG2, 32>()), st, a1, P + L.cw[1], P + L.cb[1], a2);
+    hipLaunchKernelGGL((k_conv_fwd<SFFT_CONV_CFG3, 64, T>), dim3(ns, 1), dim3(256),
+                       (conv_fwd_lds<SFFT_CONV_CFG3, 64>()), st, a2, P + L.cw[2], P + L.cb[2], a3);
+    hipLaunchKernelGGL((k_conv_fwd<SFFT_CONV_CFG4, 32, T>), dim3(ns, 2), dim3(256),
+                       (conv_fwd_lds<SFFT_CONV_CFG4, 32>()), st, a3, P + L.cw[3], P + L.cb[3], a4);
+  }
   gemm<false, true, T, T>(a4, P + L.fc1w, h, ns, kNetH, kNetF, kNetF, kNetF, kNetH, P + L.fc1b, 1, nullptr, st);
   hipLaunchKernelGGL((k_pool_fwd<T>), dim3(n_pairs), dim3(256), 0, st, h, pos, u, n_stamps);
   gemm<false, true, T, T>(u, P + L.fc2w, g, n_pairs, kNetG, kNetU, kNetU, kNetU, kNetG, P + L.fc2b, 1, nullptr,

@@ -15,7 +15,8 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import (SFFT_NET_BF16, Differencer, Surrogate, sfft_extract_stamps, sfft_surrogate_destandardize)
+from . import (SFFT_NET_BF16, Differencer, Surrogate, sfft_extract_stamps, sfft_subtract,
+               sfft_surrogate_destandardize)
 
 N_STAMPS = 64
 STAMP = 32
@@ -88,12 +89,13 @@ class GatedDifferencer:
 
     def __init__(self, width, height, L, dk, db, params, std: Standardizer, *, threshold=1.05,
                  precision=SFFT_NET_BF16, image_dtype="float32", n_stamps=N_STAMPS, device="cuda",
-                 refit_background=True):
+                 refit_background=True, max_pairs=1):
         import torch
         self.torch = torch
         self.diff = Differencer(width, height, L, dk, db, image_dtype=image_dtype, device=device)
-        self.net = Surrogate(params, self.diff.N, n_stamps=n_stamps, max_pairs=1, handle=self.diff.handle,
-                             device=device)
+        self.max_pairs = int(max_pairs)
+        self.net = Surrogate(params, self.diff.N, n_stamps=n_stamps, max_pairs=self.max_pairs,
+                             handle=self.diff.handle, device=device)
         self.threshold = float(threshold)
         self.precision = precision
         self.refit = bool(refit_background)
@@ -101,10 +103,14 @@ class GatedDifferencer:
         dev = torch.device(device)
         self.mean = torch.as_tensor(std.mean, dtype=torch.float64, device=dev)
         self.scale = torch.as_tensor(std.scale, dtype=torch.float64, device=dev)
-        self.stamps = torch.empty((n_stamps, 2, STAMP, STAMP), dtype=torch.float32, device=dev)
-        self.pos = torch.empty((n_stamps, 2), dtype=torch.float32, device=dev)
-        self.pred = torch.empty((1, self.diff.N), dtype=torch.float32, device=dev)
-        self.coef_pred = torch.empty((self.diff.N,), dtype=torch.float64, device=dev)
+        B = self.max_pairs
+        self.stamps_all = torch.empty((B, n_stamps, 2, STAMP, STAMP), dtype=torch.float32, device=dev)
+        self.pos_all = torch.empty((B, n_stamps, 2), dtype=torch.float32, device=dev)
+        self.pred_all = torch.empty((B, self.diff.N), dtype=torch.float32, device=dev)
+        self.coef_all = torch.empty((B, self.diff.N), dtype=torch.float64, device=dev)
+        self.chi2_all = torch.empty((B,), dtype=torch.float64, device=dev)
+        self.stamps, self.pos = self.stamps_all[0], self.pos_all[0]
+        self.pred, self.coef_pred = self.pred_all[:1], self.coef_all[0]
 
     def predict(self, R, S, centers, refit_background=None, stream=None):
         """Coefficients for the pair (device FP64 [N]); asynchronous. The
@@ -129,3 +135,34 @@ class GatedDifferencer:
             return True, chi_pred, chi_pred
         d.run(R, S, max_refine=max_refine, stream=stream)
         return False, chi_pred, float(d.buf.chi2.item())
+
+    def run_batch(self, pairs, max_refine=1, stream=None):
+        """Gated differencing of up to max_pairs pairs [(R, S, centers), ...]
+        with one network launch for all of them and one host read of their
+        chi2 values; the rejected pairs are then fitted in full. Every pair's
+        difference image goes through the one output buffer (diff.buf.diff),
+        overwritten pair after pair. Returns (accepted, chi2 of the
+        predictions, final chi2) as lists."""
+        B = len(pairs)
+        if B > self.max_pairs:
+            raise ValueError(f"{B} pairs > max_pairs = {self.max_pairs}")
+        d = self.diff
+        for k, (R, S, C) in enumerate(pairs):
+            sfft_extract_stamps(d.handle, d.desc, R, S, C, self.stamps_all[k], self.pos_all[k], stream)
+        self.net.forward(self.stamps_all[:B], self.pos_all[:B], B, precision=self.precision,
+                         out=self.pred_all[:B], stream=stream)
+        sfft_surrogate_destandardize(d.handle, self.pred_all[:B], self.mean, self.scale, B, d.N,
+                                     self.coef_all[:B], stream)
+        for k, (R, S, C) in enumerate(pairs):
+            if self.refit:
+                d.refit_background(R, S, coef=self.coef_all[k], stream=stream)
+            sfft_subtract(d.handle, d.desc, R, S, self.coef_all[k], d.buf.diff, self.chi2_all[k:k + 1], d.buf.ws,
+                          stream)
+        chi_pred = self.chi2_all[:B].cpu().tolist()     # the judge's decisions need the values on the host
+        accepted = [c <= self.threshold for c in chi_pred]
+        final = list(chi_pred)
+        for k, (R, S, C) in enumerate(pairs):
+            if not accepted[k]:
+                d.run(R, S, max_refine=max_refine, stream=stream)
+                final[k] = float(d.buf.chi2.item())
+        return accepted, chi_pred, final
