@@ -703,10 +703,11 @@ struct KbArgs {
   double sx, sy;
 };
 
+// binomial coefficient (exact in integers for the small degrees used here)
 __device__ __forceinline__ double binom(int n, int k) {
-  double b = 1.0;
-  for (int t = 1; t <= k; ++t) b = b * (double)(n - k + t) / (double)t;
-  return b;
+  int b = 1;
+  for (int t = 1; t <= k; ++t) b = b * (n - k + t) / t;
+  return (double)b;
 }
 
 __device__ __forceinline__ void kb_assemble_body(const KbArgs& a, const VB vb) {
