@@ -73,7 +73,9 @@ class HipEvents:
 # ---------------------------------------------------------------------------
 # algorithmic work per launch at this workload
 # ---------------------------------------------------------------------------
-def algorithmic_work():
+def algorithmic_work(fp32=False):
+    """Algorithmic bytes and flops per launch; fp32: the precision form's
+    FP32 spectra (half the spectra bytes)."""
     npix = W * H
     nkx = W // 2 + 1
     nsig = DK + 2
@@ -83,9 +85,10 @@ def algorithmic_work():
     T = 128 - 2 * h
     nblocks = -(-H // T)
     cplx64 = 16
-    row_bytes = 2 * npix * 4 + nsig * H * nkx * cplx64
+    cspec = 8 if fp32 else 16
+    row_bytes = 2 * npix * 4 + nsig * H * nkx * cspec
     row_flops = H * (-(-nsig // 2)) * 5 * W * 11
-    col_bytes = nsig * H * nkx * cplx64 + npairs * (2 * h + 1) * nkx * cplx64
+    col_bytes = nsig * H * nkx * cspec + npairs * (2 * h + 1) * nkx * cplx64
     col_flops = nkx * (nblocks * ((2 * nk + 1) * 5 * 128 * 7 + npairs * 128 * 8) + npairs * 5 * 128 * 7)
     sub_bytes = 3 * npix * 4
     sub_flops = npix * 2 * (L * L * (DK + 1))
@@ -96,8 +99,8 @@ def algorithmic_work():
     }
 
 
-def roofline_entry(name, avg_s, traffic):
-    w = algorithmic_work()[name]
+def roofline_entry(name, avg_s, traffic, fp32=False):
+    w = algorithmic_work(fp32)[name]
     if w["bound"] == "hbm":
         ach = w["bytes"] / avg_s / 1e9
         return {"kernel": name, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
@@ -444,7 +447,9 @@ def main():
 
     kern = {k: avg[k] for k in ("row_pass", "col_pass", "subtract")}
     dominant = max(kern, key=kern.get)
-    roof_all = {k: roofline_entry(k, kern[k], load_traffic(k)) for k in kern}
+    fp32 = args.compute == "fp32"
+    # the committed counters were taken on the FP64 kernels only
+    roof_all = {k: roofline_entry(k, kern[k], None if fp32 else load_traffic(k), fp32) for k in kern}
     out = {
         "metric": METRIC,
         "value": round(value, 3),
