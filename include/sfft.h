@@ -199,6 +199,13 @@ sfft_status sfft_batch_run_graph(sfft_batch batch, void* stream);
  * times; results of the last run are valid), keeps the fastest. Either out
  * pointer may be NULL. */
 sfft_status sfft_batch_tune(sfft_batch batch, void* stream, int32_t* rows_per_block, int32_t* team);
+/* Sets the configuration without timing: row-pass rows per workgroup 1..64,
+ * solve team size 1..128 workgroups, or 0 for one team per item (CUs / n,
+ * at most 64).
+ * Out-of-range values: SFFT_ERR_INVALID_ARG, the batch unchanged. Blocking
+ * (re-uploads the tables; not inside a stream capture); a captured graph is
+ * discarded and captured again on the next sfft_batch_run_graph. */
+sfft_status sfft_batch_plan(sfft_batch batch, int32_t rows_per_block, int32_t team);
 sfft_status sfft_batch_destroy(sfft_batch batch);
 
 /* Precision form of the build: the same least-squares problem restricted to

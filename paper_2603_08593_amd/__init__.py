@@ -105,6 +105,7 @@ _SIGS = {
     "sfft_batch_run": (ctypes.c_int, [_P, _P]),
     "sfft_batch_run_graph": (ctypes.c_int, [_P, _P]),
     "sfft_batch_tune": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "sfft_batch_plan": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
     "sfft_batch_destroy": (ctypes.c_int, [_P]),
     "sfft_surrogate_num_params": (ctypes.c_int64, [ctypes.c_int32]),
     "sfft_surrogate_workspace_size": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -506,6 +507,10 @@ class Batch:
         _check(lib().sfft_batch_tune(self._b, _stream_ptr(stream), ctypes.byref(rpb), ctypes.byref(team)),
                "sfft_batch_tune")
         return int(rpb.value), int(team.value)
+
+    def plan(self, rows_per_block, team):
+        """Fixed configuration (team 0: one solve team per item)."""
+        _check(lib().sfft_batch_plan(self._b, int(rows_per_block), int(team)), "sfft_batch_plan")
 
     def info(self, k) -> SolveInfo:
         return read_info(self.bufs[k].info)

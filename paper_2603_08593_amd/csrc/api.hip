@@ -634,6 +634,14 @@ sfft_status sfft_batch_tune(sfft_batch b, void* stream, int32_t* rows_per_block,
   return SFFT_OK;
 }
 
+sfft_status sfft_batch_plan(sfft_batch b, int32_t rows_per_block, int32_t team) {
+  if (!b || rows_per_block < 1 || rows_per_block > 64 || team < 0 || team > kMaxTeam) return SFFT_ERR_INVALID_ARG;
+  sfft_status s;
+  if ((s = check_device(b->handle)) != SFFT_OK) return s;
+  if (hipDeviceSynchronize() != hipSuccess) return SFFT_ERR_HIP;   // tables in use by queued work
+  return batch_plan(b, rows_per_block, team);
+}
+
 sfft_status sfft_batch_destroy(sfft_batch b) {
   if (!b) return SFFT_ERR_INVALID_ARG;
   batch_release(b);

@@ -16,6 +16,11 @@ constexpr int kRowThreads = 256;
 constexpr int kTile = 64;       // Cholesky tile
 constexpr int kSubTX = 64, kSubTY = 16;   // subtract output tile
 constexpr int kMaxW = 4096;
+// solve synchronisation words: [0, 256) barrier flags, [256, 512) progress
+// flags, then 256 64-bit time stamps
+constexpr int kSyncWords = 512;
+constexpr int kMaxTeam = 128;   // workgroups of one solve
+constexpr int kSyncClear = kSyncWords + 2 * 256;
 
 struct Geometry {
   int W, H, L, r, h, DK, DB, nK, nB, N, NKK, NP, nkx, TP, T, nsig;
@@ -71,7 +76,7 @@ struct Layout {
   // build
   size_t flags, F, MR, MS, ER, edge, strips, C, mom, build_end;
   // solve (overlaps the build region after `flags`)
-  size_t A, s, b, theta, x, rvec, rowabs, Ud, part, sync, solve_end;
+  size_t A, Z, s, b, theta, x, rvec, rowabs, Ud, part, sync, solve_end;
   // subtract
   size_t partials, sub_end;
   size_t total;
@@ -114,6 +119,8 @@ inline Layout make_layout(const Geometry& g) {
   o = base;
   // matrix rows, the right-hand-side row (padded to a tile) and identity rows
   l.A = o; o = align256(o + sizeof(double) * (2 * Np + kTile) * Np);
+  // outputs of the augmented rows: z and L^-T
+  l.Z = o; o = align256(o + sizeof(double) * (Np + kTile) * Np);
   l.s = o; o = align256(o + sizeof(double) * Np);
   l.b = o; o = align256(o + sizeof(double) * Np);
   l.theta = o; o = align256(o + sizeof(double) * Np);
@@ -122,9 +129,10 @@ inline Layout make_layout(const Geometry& g) {
   l.rowabs = o; o = align256(o + sizeof(double) * Np);
   l.Ud = o; o = align256(o + sizeof(double) * Np * kTile);
   // partial sums of the transposed triangular product: (row chunks) x Np,
-  // at most max(Np, 64 workgroups x 8 waves x 64 columns)
-  l.part = o; o = align256(o + sizeof(double) * (Np > 32768 ? Np : 32768));
-  l.sync = o; o = align256(o + sizeof(unsigned) * 128 + sizeof(unsigned long long) * 256);
+  // at most max(Np, kMaxTeam workgroups x 8 waves x 64 columns)
+  const size_t npart = (size_t)kMaxTeam * 8 * 64;
+  l.part = o; o = align256(o + sizeof(double) * (Np > npart ? Np : npart));
+  l.sync = o; o = align256(o + sizeof(unsigned) * kSyncClear);
   l.solve_end = o;
   // subtract region
   o = base;

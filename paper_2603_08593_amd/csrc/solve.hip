@@ -7,17 +7,23 @@
 //   right-looking blocked Cholesky on 64 x 64 tiles of the matrix augmented
 //   below by the right-hand side row v^T and by the identity: factorising
 //   [A; v^T; I] turns those rows into z^T = (L^-1 v)^T and L^-T, so the
-//   forward substitution and the inverse factor come out of the same sweep
-//   with no extra synchronisation; look-ahead: the workgroup that owns the
-//   next diagonal tile updates and factors it first while the others apply
-//   the remaining trailing updates;
+//   forward substitution and the inverse factor come out of the same sweep;
+//   the factorisation is a dataflow between two roles. Workgroup 0 runs the
+//   diagonal chain: it factors diagonal tile k (L_kk and U_k = L_kk^-T in
+//   one sweep), computes the next panel tile L_(k+1),k = A_(k+1),k U_k and
+//   applies its update to diagonal tile k + 1, which it keeps in LDS, then
+//   factors that one. The other workgroups compute the remaining panel
+//   tiles of step k and apply its remaining trailing updates, one step
+//   behind the chain. The roles synchronise through per-workgroup progress
+//   flags, never through a barrier of the whole team, so the chain's
+//   critical path is factor -> one panel tile -> one update per step;
 //   x = L^-T z as one distributed matrix-vector product; up to `refine`
 //   steps of iterative refinement on r = h - G theta (FP64), each three
 //   matrix-vector products (G theta, L^-1 r = (L^-T)^T r, L^-T z);
 //   final backward error and pivot range.
-// Workgroups synchronise through a flag barrier (one arrival flag per
-// workgroup, one release flag) with bounded spins: a timeout is reported in
-// the status instead of hanging.
+// Workgroups synchronise through flags (release fence + relaxed store;
+// relaxed polling + one acquire fence) with bounded spins: a timeout is
+// reported in the status instead of hanging.
 #include <algorithm>
 #include <new>
 #include <vector>
@@ -29,6 +35,7 @@
 namespace sfft {
 
 constexpr int kPT = 512;                    // threads per solve workgroup
+constexpr int kPlainTeam = 128;             // team of the single-pair solve
 constexpr long kSpinLimit = 1L << 26;
 constexpr int kLD = kTile + 1;              // LDS row pitch of a tile
 
@@ -37,17 +44,22 @@ struct PSArgs {
   const double* h;
   double* coef;
   sfft_solve_info* info;
-  double* A;        // (2 Np + 64) x Np: rows [0, Np) matrix -> L; row Np: v -> z;
-                    // rows [Np + 64, 2 Np + 64): identity -> L^-T
+  double* A;        // (2 Np + 64) x Np working matrix: rows [0, Np) matrix,
+                    // its diagonal tiles -> L_kk; row Np: v; rows
+                    // [Np + 64, 2 Np + 64): identity
   double* s;        // Np
   double* x;        // Np
   double* theta;    // Np
   double* r;        // Np
   double* rowabs;   // Np
+  double* Z;        // (Np + 64) x Np: row 0: z = L^-1 v; rows [64, Np + 64): L^-T
   double* Ud;       // nt tiles of 64 x 64: U_k = L_kk^-T of each diagonal tile
   double* part;     // partial sums of gemv_upper_t
   unsigned* sync;   // [0, P): arrival flags, [P]: release flag
-  unsigned long long* stamps;   // optional: 100 MHz time stamp of each barrier
+  unsigned* prog;   // [0, P): factorisation progress of every workgroup
+  unsigned long long* stamps;   // optional 100 MHz time stamps: [0, 128) team
+                                // barriers, [128 + 2k] diagonal tile k factored,
+                                // [129 + 2k] the chain's step k done
   int* flags;       // [0] nonfinite (build), [1] failed pivot + 1, [2] barrier timeout
   int N, Np, nt, P, refine;
 };
@@ -90,13 +102,57 @@ struct Barrier {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
-    if (bid == 0 && threadIdx.x == 0 && a.stamps && gen < 256)
+    if (bid == 0 && threadIdx.x == 0 && a.stamps && gen < 128)
       a.stamps[gen] = __builtin_amdgcn_s_memrealtime();
   }
 };
 
 __device__ __forceinline__ bool failed(const PSArgs& a) {
   return __hip_atomic_load(&a.flags[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+// true when the factorisation stopped at diagonal tile k or earlier (the
+// failing pivot index + 1 is recorded in flags[1])
+__device__ __forceinline__ bool failed_by(const PSArgs& a, int k) {
+  const int f = __hip_atomic_load(&a.flags[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return f != 0 && (f - 1) / kTile <= k;
+}
+
+// Progress flags of the factorisation, one monotonic word per workgroup.
+// Workgroup 0 (diagonal chain): 2k + 1 once L_kk and U_k of step k are
+// stored, 2k + 2 once the panel tile L_(k+1),k is. Workgroups 1 .. P-1:
+// 2k + 1 after their panel tiles of step k, 2k + 2 after their trailing
+// updates of step k. All stores of the workgroup precede the flag (barrier,
+// then a release fence by the storing thread).
+__device__ __forceinline__ void publish(const PSArgs& a, int bid, unsigned val) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(&a.prog[bid], val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Waits until workgroup 0's flag is >= want0 and every other workgroup's
+// flag is >= want (thread b polls the flag of workgroup b with relaxed
+// loads; one acquire fence after its wait). Bounded: a timeout is recorded
+// in flags[2] and the caller goes on.
+__device__ __forceinline__ void wait_progress(const PSArgs& a, unsigned want0, unsigned want) {
+  const int t = threadIdx.x;
+  if (t < a.P) {
+    const unsigned w = (t == 0) ? want0 : want;
+    long spins = 0;
+    while (__hip_atomic_load(&a.prog[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < w) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > kSpinLimit) { atomicOr(&a.flags[2], 1); break; }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
+// time stamp of a diagonal-chain event (workgroup 0)
+__device__ __forceinline__ void stamp(const PSArgs& a, int slot) {
+  if (threadIdx.x == 0 && a.stamps && slot < 256) a.stamps[slot] = __builtin_amdgcn_s_memrealtime();
 }
 
 // ---------------------------------------------------------------------------
@@ -141,6 +197,26 @@ __device__ __forceinline__ void tile_out(const double (*T)[kLD], double* A, int6
   }
 }
 
+// the two halves of tile_in, for issuing the loads of several tiles before
+// the first LDS store
+__device__ __forceinline__ void tile_gather(double (&v)[kPerThread], const double* A, int64_t ld, int64_t r0,
+                                            int64_t c0, int rows = kTile) {
+#pragma unroll
+  for (int t = 0; t < kPerThread; ++t) {
+    const int idx = threadIdx.x + t * kPT;
+    const int i = idx >> 6, j = idx & 63;
+    v[t] = (i < rows) ? A[(r0 + i) * ld + c0 + j] : 0.0;
+  }
+}
+
+__device__ __forceinline__ void tile_scatter(double (*T)[kLD], const double (&v)[kPerThread]) {
+#pragma unroll
+  for (int t = 0; t < kPerThread; ++t) {
+    const int idx = threadIdx.x + t * kPT;
+    T[idx >> 6][idx & 63] = v[t];
+  }
+}
+
 __device__ __forceinline__ void load_tile(double (*T)[kLD], const double* A, int Np, int ti, int tj,
                                           int rows = kTile) {
   tile_in(T, A, Np, (int64_t)ti * kTile, (int64_t)tj * kTile, rows);
@@ -158,8 +234,11 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 // 32 (w >> 2) .. +32 of the result, as two 16 x 16 blocks. Operand lanes:
 // A[l % 16][l / 16], B[l / 16][l % 16]; result lane l, element q:
 // row l / 16 + 4 q, column l % 16.
-// TRANS_B = true: acc = X Y^T; false: acc = X Y.
-template <bool TRANS_B>
+// TRANS_B = true: acc = X Y^T; false: acc = X Y. UPPER_Y: Y is upper
+// triangular, so columns j0 .. j0 + 31 need rows k < j0 + 32 only (a wave
+// pair sharing a SIMD, w and w + 4, does 24 of the 32 k-steps of the full
+// product).
+template <bool TRANS_B, bool UPPER_Y = false>
 __device__ __forceinline__ void tile_mma(const double (*X)[kLD], const double (*Y)[kLD],
                                          double4_t acc[2]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -167,8 +246,9 @@ __device__ __forceinline__ void tile_mma(const double (*X)[kLD], const double (*
   const int lr = lane & 15, lk = lane >> 4;
   acc[0] = double4_t{0.0, 0.0, 0.0, 0.0};
   acc[1] = double4_t{0.0, 0.0, 0.0, 0.0};
+  const int kend = UPPER_Y ? j0 + 32 : kTile;
 #pragma unroll 4
-  for (int k = 0; k < kTile; k += 4) {
+  for (int k = 0; k < kend; k += 4) {
     const double av = X[i0 + lr][k + lk];
     const double b0 = TRANS_B ? Y[j0 + lr][k + lk] : Y[k + lk][j0 + lr];
     const double b1 = TRANS_B ? Y[j0 + 16 + lr][k + lk] : Y[k + lk][j0 + 16 + lr];
@@ -191,11 +271,11 @@ __device__ __forceinline__ void tile_sub_abt(double (*C)[kLD], const double (*X)
   __syncthreads();
 }
 
-// C = X U (U upper triangular; C may not alias X or U)
-__device__ __forceinline__ void tile_mul_ab(double (*C)[kLD], const double (*X)[kLD],
-                                            const double (*U)[kLD]) {
+// C = C U (U upper triangular, not aliasing C)
+__device__ __forceinline__ void tile_mul_inplace(double (*C)[kLD], const double (*U)[kLD]) {
   double4_t acc[2];
-  tile_mma<false>(X, U, acc);
+  tile_mma<false, true>(C, U, acc);
+  __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i0 = 16 * (w & 3) + (lane >> 4), j0 = 32 * (w >> 2) + (lane & 15);
 #pragma unroll
@@ -220,91 +300,136 @@ __device__ __forceinline__ double lane_value(double x, int lane) {
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 
+// Column phase of block jb (wave 0; lane i = row i of T and of Y): the
+// block's 8 entries of both rows stay in registers while its 8 columns are
+// factored one by one; pivots and the entries of L that update the rest of
+// the block come from other lanes by readlane, so the column chain never
+// waits on LDS; column j of L is written to T and the block of Y to Ut.
+__device__ __forceinline__ void potrf_columns(double (*T)[kLD], double (*Ut)[kLD], int jb, int& f) {
+  constexpr int kB = 8;
+  const int i = threadIdx.x & 63;
+  const int j0 = jb * kB;
+  double rb[kB], yb[kB];
+#pragma unroll
+  for (int c = 0; c < kB; ++c) {
+    rb[c] = T[i][j0 + c];
+    yb[c] = Ut[i][j0 + c];
+  }
+#pragma unroll
+  for (int c = 0; c < kB; ++c) {
+    const int j = j0 + c;
+    const double d = lane_value(rb[c], j);
+    const bool good = (d > 0.0) && is_finite_d(d);
+    f = (f < 0 && !good) ? j : f;
+    // branch-free: the estimate is always computed, then masked to 0
+    const long long keep = -(long long)good;
+    const double rs = __builtin_bit_cast(double, __builtin_bit_cast(long long, rsqrt64(d)) & keep);
+    const double l = (i >= j) ? rb[c] * rs : 0.0;
+    const double y = yb[c] * rs;
+    rb[c] = l;
+    yb[c] = y;
+#pragma unroll
+    for (int c2 = c + 1; c2 < kB; ++c2) {
+      const double lm = lane_value(l, j0 + c2);     // L[j0 + c2][j]
+      rb[c2] = fma(-l, lm, rb[c2]);
+      yb[c2] = fma(-y, lm, yb[c2]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < kB; ++c) {
+    T[i][j0 + c] = rb[c];
+    Ut[i][j0 + c] = yb[c];
+  }
+}
+
+// Rank-8 update of columns m = m0, m0 + step, ... < m1 of T and of Y with
+// block jb (all 64 rows; lane = row), two columns per iteration.
+__device__ __forceinline__ void potrf_update(double (*T)[kLD], double (*Ut)[kLD], int jb, int m0, int m1,
+                                             int step) {
+  constexpr int kB = 8;
+  const int i = threadIdx.x & 63;
+  const int j0 = jb * kB;
+  double li[kB], yi[kB];
+#pragma unroll
+  for (int c = 0; c < kB; ++c) {
+    li[c] = T[i][j0 + c];
+    yi[c] = Ut[i][j0 + c];
+  }
+  int m = m0;
+  for (; m + step < m1; m += 2 * step) {
+    const int m2 = m + step;
+    double t = T[i][m], u = Ut[i][m], t2 = T[i][m2], u2 = Ut[i][m2];
+#pragma unroll
+    for (int c = 0; c < kB; ++c) {
+      const double lm = T[m][j0 + c], lm2 = T[m2][j0 + c];     // broadcasts
+      t = fma(-li[c], lm, t);
+      u = fma(-yi[c], lm, u);
+      t2 = fma(-li[c], lm2, t2);
+      u2 = fma(-yi[c], lm2, u2);
+    }
+    T[i][m] = t;
+    Ut[i][m] = u;
+    T[i][m2] = t2;
+    Ut[i][m2] = u2;
+  }
+  if (m < m1) {
+    double t = T[i][m], u = Ut[i][m];
+#pragma unroll
+    for (int c = 0; c < kB; ++c) {
+      const double lm = T[m][j0 + c];
+      t = fma(-li[c], lm, t);
+      u = fma(-yi[c], lm, u);
+    }
+    T[i][m] = t;
+    Ut[i][m] = u;
+  }
+}
+
 // Cholesky of the 64 x 64 SPD tile T (lower, in place) and U = L^-T into Ut.
 // The right-looking factorisation of the stacked [T; I] turns the identity
 // rows into L^-T (I = Y L^T); Ut starts as the identity and holds Y. Blocked
-// by 8 columns, two workgroup barriers per block:
-//   panel: wave 0 (lane i = row i of T and of Y) keeps the block's 8 entries
-//   of both rows in registers and factors the 8 columns one by one; pivots
-//   and the entries of L that update the rest of the block come from other
-//   lanes by readlane, so the column chain never waits on LDS; column j of L
-//   is written to T and the block of Y to Ut;
-//   trailing update: every wave applies the block's rank-8 update to its
-//   share of the later columns (wave w: columns j0 + 8 + w, + 8, ...) for all
-//   64 rows of T and of Y, reading the block of L as broadcasts.
+// by 8 columns and software-pipelined over the 8 waves, two barriers per
+// block: while wave 0 runs the column phase of block jb (potrf_columns),
+// waves 1-7 apply block jb - 1's update to columns j0 + 8 .. 63; then all 8
+// waves apply block jb's update to the next block's 8 columns (one each),
+// which is all the next column phase waits for.
+// `mid()` runs (in every thread) before block kMidBlock: the caller's point
+// to start global loads that complete during the rest of the sweep.
 // A pivot that is not positive and finite is recorded (the first one) and
 // the sweep goes on with a zero scale, so values stay finite; the caller
 // discards them. Returns the failing local pivot or -1.
-__device__ __forceinline__ int tile_potrf_aug(double (*T)[kLD], double (*Ut)[kLD]) {
-  constexpr int kB = 8;
+constexpr int kMidBlock = 5;
+
+template <class Mid>
+__device__ __forceinline__ int tile_potrf_aug(double (*T)[kLD], double (*Ut)[kLD], Mid&& mid) {
+  constexpr int kB = 8, kNB = kTile / kB;
   __shared__ int fail;
-  const int i = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (threadIdx.x == 0) fail = -1;
   for (int idx = threadIdx.x; idx < kTile * kTile; idx += kPT)
     Ut[idx >> 6][idx & 63] = ((idx >> 6) == (idx & 63)) ? 1.0 : 0.0;
   __syncthreads();
   int f = -1;
-#pragma unroll 1
-  for (int jb = 0; jb < kTile / kB; ++jb) {
+  auto block = [&](int jb) {
     const int j0 = jb * kB;
-    if (w == 0) {
-      double rb[kB], yb[kB];
-#pragma unroll
-      for (int c = 0; c < kB; ++c) {
-        rb[c] = T[i][j0 + c];
-        yb[c] = Ut[i][j0 + c];
-      }
-#pragma unroll
-      for (int c = 0; c < kB; ++c) {
-        const int j = j0 + c;
-        const double d = lane_value(rb[c], j);
-        const bool good = (d > 0.0) && is_finite_d(d);
-        f = (f < 0 && !good) ? j : f;
-        const double rs = good ? rsqrt64(d) : 0.0;
-        const double l = (i >= j) ? rb[c] * rs : 0.0;
-        const double y = yb[c] * rs;
-        rb[c] = l;
-        yb[c] = y;
-#pragma unroll
-        for (int c2 = c + 1; c2 < kB; ++c2) {
-          const double lm = lane_value(l, j0 + c2);     // L[j0 + c2][j]
-          rb[c2] = fma(-l, lm, rb[c2]);
-          yb[c2] = fma(-y, lm, yb[c2]);
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < kB; ++c) {
-        T[i][j0 + c] = rb[c];
-        Ut[i][j0 + c] = yb[c];
-      }
-    }
+    if (w == 0) potrf_columns(T, Ut, jb, f);
+    else if (jb > 0) potrf_update(T, Ut, jb - 1, j0 + kB + (w - 1), kTile, kPT / 64 - 1);
     __syncthreads();
-    if (j0 + kB < kTile) {
-      double li[kB], yi[kB];
-#pragma unroll
-      for (int c = 0; c < kB; ++c) {
-        li[c] = T[i][j0 + c];
-        yi[c] = Ut[i][j0 + c];
-      }
-      for (int m = j0 + kB + w; m < kTile; m += kPT / 64) {
-        double t = T[i][m], u = Ut[i][m];
-#pragma unroll
-        for (int c = 0; c < kB; ++c) {
-          const double lm = T[m][j0 + c];                 // broadcast
-          t = fma(-li[c], lm, t);
-          u = fma(-yi[c], lm, u);
-        }
-        T[i][m] = t;
-        Ut[i][m] = u;
-      }
+    if (jb + 1 < kNB) {
+      potrf_update(T, Ut, jb, j0 + kB + w, j0 + kB + w + 1, 1);
       __syncthreads();
     }
-  }
-  if (w == 0) {
-    for (int k = i + 1; k < kTile; ++k) T[i][k] = 0.0;
-    if (i == 0) fail = f;
-  }
+  };
+  // two loops, so that registers loaded by mid() stay live across the second
+  // without loop-carried copies (which would wait for the loads)
+#pragma unroll 1
+  for (int jb = 0; jb < kMidBlock; ++jb) block(jb);
+  mid();
+#pragma unroll 1
+  for (int jb = kMidBlock; jb < kNB; ++jb) block(jb);
+  for (int idx = threadIdx.x; idx < kTile * kTile; idx += kPT)
+    if ((idx & 63) > (idx >> 6)) T[idx >> 6][idx & 63] = 0.0;
+  if (threadIdx.x == 0) fail = f;
   __syncthreads();
   return fail;
 }
@@ -331,28 +456,46 @@ __device__ __forceinline__ void store_tile_r(const double (*T)[kLD], double* A, 
   tile_out(T, A, Np, r0, (int64_t)tj * kTile, rows);
 }
 
-// out_i = sum_j U[i][j] in_j with U = L^-T stored in the identity rows
-// (upper triangular: j >= i); one row per wave.
-__device__ void gemv_upper(const PSArgs& a, const double* in, double* out, int bid) {
+// Sum over j = j0 + lane + 64 u < n of x[j] y[j] (per lane, ascending j):
+// the loads of 8 strides are issued together, one memory round trip per 512
+// elements.
+__device__ __forceinline__ double lane_dot(const double* x, const double* y, int j0, int n) {
+  const int lane = threadIdx.x & 63;
+  double acc = 0.0;
+  for (int jb = j0; jb < n; jb += 64 * 8) {
+    double xv[8], yv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = jb + 64 * u + lane;
+      xv[u] = j < n ? x[j] : 0.0;
+      yv[u] = j < n ? y[j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = fma(xv[u], yv[u], acc);
+  }
+  return acc;
+}
+
+// y_i = sum_j U[i][j] in_j with U = L^-T (upper triangular: j >= i); one
+// row per wave; theta_i = s_i y_i, or theta_i += s_i y_i when `accumulate`.
+__device__ void gemv_upper_theta(const PSArgs& a, const double* in, bool accumulate, int bid) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nw = kPT / 64;
-  const double* U = a.A + ((int64_t)a.Np + kTile) * a.Np;
+  const double* U = a.Z + (int64_t)kTile * a.Np;
   for (int i = bid * nw + wave; i < a.Np; i += a.P * nw) {
-    const double* Ur = U + (int64_t)i * a.Np;
-    double acc = 0.0;
-#pragma unroll 4
-    for (int j = (i & ~63) + lane; j < a.Np; j += 64) acc = fma(Ur[j], in[j], acc);
+    double acc = lane_dot(U + (int64_t)i * a.Np, in, i & ~63, a.Np);
     acc = wave_sum(acc);
-    if (lane == 0) out[i] = acc;
+    if (lane == 0) a.theta[i] = (accumulate ? a.theta[i] : 0.0) + a.s[i] * acc;
   }
 }
 
 // out_j = sum_{i <= j} U[i][j] in_i (U^T = L^-1, lower). The rows are cut
 // into chunks; wave (column block cb, chunk ch) sums its chunk for the 64
-// columns of the block (one column per lane, coalesced row reads) into
-// part[ch][j]; after a barrier the chunks are added in order.
+// columns of the block (one column per lane, coalesced row reads, 8 rows
+// per memory round trip) into part[ch][j]; after a barrier the chunks are
+// added in order.
 __device__ void gemv_upper_t(const PSArgs& a, const double* in, double* out, int bid, Barrier& bar) {
-  const double* U = a.A + ((int64_t)a.Np + kTile) * a.Np;
+  const double* U = a.Z + (int64_t)kTile * a.Np;
   const int lane = threadIdx.x & 63;
   const int nw = kPT / 64;
   const int ncb = a.Np / 64;
@@ -365,17 +508,32 @@ __device__ void gemv_upper_t(const PSArgs& a, const double* in, double* out, int
     const int i0 = ch * len;
     const int i1 = min(min(i0 + len, a.Np), cb * 64 + 64);
     double acc = 0.0;
-#pragma unroll 8
-    for (int i = i0; i < i1; ++i) {
-      const double u = U[(int64_t)i * a.Np + j];
-      acc = (i <= j) ? fma(u, in[i], acc) : acc;
+    for (int ib = i0; ib < i1; ib += 8) {
+      double uv[8], iv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = ib + u;
+        uv[u] = i < i1 ? U[(int64_t)i * a.Np + j] : 0.0;
+        iv[u] = i < i1 ? in[i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = ib + u;
+        acc = (i < i1 && i <= j) ? fma(uv[u], iv[u], acc) : acc;
+      }
     }
     a.part[(int64_t)ch * a.Np + j] = acc;
   }
   bar.wait(a);
   for (int j = bid * kPT + threadIdx.x; j < a.Np; j += a.P * kPT) {
     double s = 0.0;
-    for (int ch = 0; ch < nch; ++ch) s += a.part[(int64_t)ch * a.Np + j];
+    for (int cb = 0; cb < nch; cb += 8) {
+      double pv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) pv[u] = (cb + u < nch) ? a.part[(int64_t)(cb + u) * a.Np + j] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += pv[u];
+    }
     out[j] = s;
   }
 }
@@ -389,12 +547,84 @@ __device__ void residual(const PSArgs& a, int bid) {
       if (lane == 0) a.r[i] = 0.0;
       continue;
     }
-    const double* Gr = a.G + (int64_t)i * a.N;
-    double sacc = 0.0;
-#pragma unroll 4
-    for (int j = lane; j < a.N; j += 64) sacc = fma(Gr[j], a.theta[j], sacc);
+    double sacc = lane_dot(a.G + (int64_t)i * a.N, a.theta, 0, a.N);
     sacc = wave_sum(sacc);
     if (lane == 0) a.r[i] = a.s[i] * (a.h[i] - sacc);
+  }
+}
+
+// The bulk work of step k, shared by `nb` workgroups (this one: `q`).
+// Task (r, J) updates tile (r, J) with the panel tiles it needs, computed
+// on the spot: A_rJ -= X_rk X_Jk^T with X_rk = A_rk U_k (every input tile
+// has the updates of steps < k). Tasks, in row-major order: the matrix
+// tiles k + 1 <= J <= r < nt except the diagonal tile (k + 1, k + 1), which
+// the chain updates; the v row and the identity rows of blocks i <= k, for
+// J in [k + 1, nt). Each workgroup takes a contiguous range, so consecutive
+// tasks of one row share X_rk, computed once.
+// The v row's and the identity rows' panel tiles are final results: their
+// J = k + 1 task stores them in Z (at the last step, k = nt - 1, they are the
+// only tasks), never over the input tile, which the row's other tasks of the
+// step still read; the matrix panel tiles are not needed after the step.
+__device__ __forceinline__ void bulk_step(const PSArgs& a, int k, int q, int nb, double (*TU)[kLD],
+                                          double (*TX)[kLD], double (*TL)[kLD], double (*TC)[kLD]) {
+  const int nt = a.nt, Np = a.Np;
+  const int m = nt - k - 1;
+  const int ntri = m * (m + 1) / 2;
+  const int nrow = k + 2;                       // v row + identity rows 0..k
+  const int t0 = m > 0 ? 1 : 0;
+  const int ntot = m > 0 ? ntri + nrow * m : nrow;
+  const int tb = t0 + (int)((int64_t)(ntot - t0) * q / nb);
+  const int te = t0 + (int)((int64_t)(ntot - t0) * (q + 1) / nb);
+  bool have_u = false;
+  int xrow = -1;                                // row tile whose X_rk is in TX
+  for (int t = tb; t < te; ++t) {
+    int rt, J;
+    if (m == 0) {
+      rt = nt + t;                              // panel only
+      J = -1;
+    } else if (t < ntri) {
+      int ti, tj;
+      tri_decode(t, ti, tj);
+      rt = k + 1 + ti;
+      J = k + 1 + tj;
+    } else {
+      const int u = t - ntri;
+      rt = nt + u / m;
+      J = k + 1 + u % m;
+    }
+    const int rows = (rt == nt) ? 1 : kTile;
+    const int64_t r0 = row_off(rt, nt, Np);
+    const bool diag = (J == rt);
+    const bool new_x = (rt != xrow);
+    {
+      // one memory round trip for all the task's tiles
+      double vu[kPerThread], vx[kPerThread], vc[kPerThread], vl[kPerThread];
+      if (!have_u) tile_gather(vu, a.Ud + (int64_t)k * kTile * kTile, kTile, 0, 0);
+      if (new_x) tile_gather(vx, a.A, Np, r0, (int64_t)k * kTile, rows);
+      if (J >= 0) {
+        tile_gather(vc, a.A, Np, r0, (int64_t)J * kTile, rows);
+        if (!diag) tile_gather(vl, a.A, Np, (int64_t)J * kTile, (int64_t)k * kTile);
+      }
+      if (!have_u) tile_scatter(TU, vu);
+      if (new_x) tile_scatter(TX, vx);
+      if (J >= 0) {
+        tile_scatter(TC, vc);
+        if (!diag) tile_scatter(TL, vl);
+      }
+    }
+    have_u = true;
+    __syncthreads();
+    if (new_x) {
+      tile_mul_inplace(TX, TU);                 // X_rk
+      if (rt >= nt && J <= k + 1) tile_out(TX, a.Z, Np, r0 - Np, (int64_t)k * kTile, rows);
+      xrow = rt;
+    }
+    if (J >= 0) {
+      if (!diag) tile_mul_inplace(TL, TU);      // X_Jk
+      tile_sub_abt(TC, TX, diag ? TX : TL);
+      store_tile_r(TC, a.A, Np, r0, J, rows);
+    }
+    __syncthreads();
   }
 }
 
@@ -403,36 +633,52 @@ __device__ __forceinline__ void solve_body(const PSArgs& a, const int bid) {
   double (*T0)[kLD] = reinterpret_cast<double (*)[kLD]>(smem);
   double (*T1)[kLD] = reinterpret_cast<double (*)[kLD]>(smem + kTile * kLD);
   double (*T2)[kLD] = reinterpret_cast<double (*)[kLD]>(smem + 2 * kTile * kLD);
+  double (*T3)[kLD] = reinterpret_cast<double (*)[kLD]>(smem + 3 * kTile * kLD);
   __shared__ double red[kPT / 64];
   Barrier bar;
   bar.bid = bid;
   const int N = a.N, Np = a.Np, nt = a.nt, P = a.P;
-  double* v = a.A + (int64_t)Np * Np;                     // row Np: v, then z
-  double* U = a.A + ((int64_t)Np + kTile) * Np;           // identity rows, then L^-T
+  double* v = a.A + (int64_t)Np * Np;                     // row Np: v
+  double* U = a.A + ((int64_t)Np + kTile) * Np;           // identity rows
 
   // ---- equilibrate: A = D G D (identity padding), v = D h, rowabs, identity rows
   {
+    double* sv = smem;                                    // D, computed by every workgroup
+    for (int j = threadIdx.x; j < Np; j += kPT) {
+      double sj = 1.0;
+      if (j < N) {
+        const double gjj = a.G[(int64_t)j * N + j];
+        sj = (gjj > 0.0 && is_finite_d(gjj)) ? 1.0 / sqrt(gjj) : 0.0;
+      }
+      sv[j] = sj;
+    }
+    __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int i = bid * (kPT / 64) + wave; i < Np; i += P * (kPT / 64)) {
-      double si = 1.0;
-      if (i < N) {
-        const double gii = a.G[(int64_t)i * N + i];
-        si = (gii > 0.0 && is_finite_d(gii)) ? 1.0 / sqrt(gii) : 0.0;
-      }
+      const double si = sv[i];
       double ra = 0.0;
-      for (int j = lane; j < Np; j += 64) {
-        double val;
-        if (i < N && j < N) {
-          const double gjj = a.G[(int64_t)j * N + j];
-          const double sj = (gjj > 0.0 && is_finite_d(gjj)) ? 1.0 / sqrt(gjj) : 0.0;
-          const double g = a.G[(int64_t)i * N + j];
-          ra += fabs(g);
-          val = si * g * sj;
-        } else {
-          val = (i == j) ? 1.0 : 0.0;
+      for (int jb = 0; jb < Np; jb += 64 * 8) {
+        double gv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int j = jb + 64 * u + lane;
+          gv[u] = (i < N && j < N) ? a.G[(int64_t)i * N + j] : 0.0;
         }
-        a.A[(int64_t)i * Np + j] = val;
-        U[(int64_t)i * Np + j] = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int j = jb + 64 * u + lane;
+          if (j >= Np) continue;
+          double val;
+          if (i < N && j < N) {
+            ra += fabs(gv[u]);
+            val = si * gv[u] * sv[j];
+          } else {
+            val = (i == j) ? 1.0 : 0.0;
+          }
+          a.A[(int64_t)i * Np + j] = val;
+          // identity rows: only the tiles on and right of the diagonal are read
+          if (j >= (i & ~63)) U[(int64_t)i * Np + j] = (i == j) ? 1.0 : 0.0;
+        }
       }
       ra = wave_sum(ra);
       if (lane == 0) {
@@ -444,107 +690,84 @@ __device__ __forceinline__ void solve_body(const PSArgs& a, const int bid) {
   }
   bar.wait(a);
 
-  // ---- factorisation of [A; v^T; I]
-  // Step k: workgroup 0 applies the last update to diagonal tile k (from the
-  // panel of step k - 1) and factors it, storing L_kk and U_k = L_kk^-T,
-  // while the others apply the remaining trailing updates of step k - 1
-  // (look-ahead); then every workgroup takes panel tiles of column tile k.
+  // ---- factorisation of [A; v^T; I]: diagonal chain (workgroup 0) and the
+  // bulk work of the others one step behind; with P = 1 workgroup 0 takes
+  // both roles in turn.
+  const int q = (P > 1) ? bid - 1 : 0;        // index among the bulk workgroups
+  const int nb = (P > 1) ? P - 1 : 1;
+  if (bid == 0) {
+    load_tile(T0, a.A, Np, 0, 0);
+    __syncthreads();
+  }
   for (int k = 0; k < nt; ++k) {
     if (bid == 0) {
-      load_tile(T0, a.A, Np, k, k);
-      if (k > 0) load_tile(T1, a.A, Np, k, k - 1);
-      __syncthreads();
-      if (k > 0) tile_sub_abt(T0, T1, T1);
-      const int f = tile_potrf_aug(T0, T2);
+      // T0: diagonal tile k with every update of steps < k. Half-way through
+      // its factorisation, once the bulk work of step k - 1 is complete, the
+      // two tiles of row k + 1 that the chain needs next are loaded into
+      // registers (they arrive while the sweep goes on).
+      if (P == 1 && k > 0) {
+        load_tile(T0, a.A, Np, k, k);
+        __syncthreads();
+      }
+      const bool ahead = k + 1 < nt;
+      double xr[kPerThread], dr[kPerThread];
+      const int f = tile_potrf_aug(T0, T2, [&]() {
+        if (!ahead) return;
+        if (P > 1) wait_progress(a, 0, 2 * k);
+#pragma unroll
+        for (int t = 0; t < kPerThread; ++t) {
+          const int idx = threadIdx.x + t * kPT;
+          const int64_t row = (int64_t)(k + 1) * kTile + (idx >> 6);
+          xr[t] = a.A[row * Np + (int64_t)k * kTile + (idx & 63)];
+          dr[t] = a.A[row * Np + (int64_t)(k + 1) * kTile + (idx & 63)];
+        }
+      });
+      stamp(a, 128 + 2 * k);
       if (f >= 0) {
         if (threadIdx.x == 0) atomicCAS(&a.flags[1], 0, k * kTile + f + 1);
-      } else {
-        store_tile(T0, a.A, Np, k, k);
-        tile_out(T2, a.Ud + (int64_t)k * kTile * kTile, kTile, 0, 0);
+        publish(a, 0, 2 * k + 1);
+        break;
       }
-      __syncthreads();
-    }
-    // trailing update of step kp = k - 1 on column tiles J in [k, nt): rows
-    // of the matrix (J <= I < nt), the v row and the identity rows i <= kp;
-    // item 0, tile (k, k), is workgroup 0's
-    if (k > 0 && (P == 1 || bid > 0)) {
-      const int kp = k - 1;
-      const int m = nt - k;
-      const int ntri = m * (m + 1) / 2;
-      const int nv = m;
-      const int naug = k * m;
-      const int ntot = ntri + nv + naug;
-      const int first = (P > 1) ? bid - 1 : 0;
-      const int stride = (P > 1) ? P - 1 : 1;
-      for (int t = 1 + first; t < ntot; t += stride) {
-        int rt, J;
-        if (t < ntri) {
-          int ti, tj;
-          tri_decode(t, ti, tj);
-          rt = k + ti;
-          J = k + tj;
-        } else if (t < ntri + nv) {
-          rt = nt;
-          J = k + (t - ntri);
-        } else {
-          const int u = t - ntri - nv;
-          rt = nt + 1 + u / m;
-          J = k + u % m;
+      store_tile(T0, a.A, Np, k, k);
+      tile_out(T2, a.Ud + (int64_t)k * kTile * kTile, kTile, 0, 0);
+      publish(a, 0, 2 * k + 1);
+      if (ahead) {
+#pragma unroll
+        for (int t = 0; t < kPerThread; ++t) {
+          const int idx = threadIdx.x + t * kPT;
+          T1[idx >> 6][idx & 63] = xr[t];
+          T0[idx >> 6][idx & 63] = dr[t];
         }
-        const int rows = (rt == nt) ? 1 : kTile;
-        const int64_t r0 = row_off(rt, nt, Np);
-        load_tile_r(T0, a.A, Np, r0, J, rows);
-        load_tile_r(T1, a.A, Np, r0, kp, rows);
-        load_tile(T2, a.A, Np, J, kp);
         __syncthreads();
-        tile_sub_abt(T0, T1, T2);
-        store_tile_r(T0, a.A, Np, r0, J, rows);
-        __syncthreads();
-      }
-    }
-    bar.wait(a);
-    if (failed(a)) break;
-    // panel: row tiles k+1 .. nt-1 (matrix), nt (v row), nt+1+i for i <= k
-    // (identity rows with nonzero entries in column tile k)
-    {
-      const int nmat = nt - k - 1;
-      const int npanel = nmat + 1 + (k + 1);
-      bool loaded = false;
-      for (int t = bid; t < npanel; t += P) {
-        int rt;
-        if (t < nmat) rt = k + 1 + t;
-        else if (t == nmat) rt = nt;
-        else rt = nt + 1 + (t - nmat - 1);
-        const int rows = (rt == nt) ? 1 : kTile;
-        const int64_t r0 = row_off(rt, nt, Np);
-        if (!loaded) {
-          tile_in(T1, a.Ud + (int64_t)k * kTile * kTile, kTile, 0, 0);
-          loaded = true;
+        tile_mul_inplace(T1, T2);                 // L_(k+1),k = A_(k+1),k U_k
+        tile_sub_abt(T0, T1, T1);                 // diagonal tile k + 1, step k
+        if (P == 1) {
+          store_tile(T0, a.A, Np, k + 1, k + 1);
+          __syncthreads();
         }
-        load_tile_r(T0, a.A, Np, r0, k, rows);
-        __syncthreads();
-        tile_mul_ab(T2, T0, T1);          // X = A_rk L_kk^-T
-        store_tile_r(T2, a.A, Np, r0, k, rows);
-        __syncthreads();
       }
+      stamp(a, 129 + 2 * k);
     }
-    bar.wait(a);
+    if (P == 1 || bid > 0) {
+      // U_k stored; the bulk work of step k - 1 complete
+      if (P > 1) wait_progress(a, 2 * k + 1, 2 * k);
+      if (failed_by(a, k)) break;
+      bulk_step(a, k, q, nb, T0, T1, T2, T3);
+      if (P > 1) publish(a, bid, 2 * k + 2);
+    }
   }
+  bar.wait(a);
   const bool bad = failed(a);
-  // ---- x = L^-T z, theta = D x, refinement
+  // ---- theta = D L^-T z, refinement
   if (!bad) {
-    gemv_upper(a, v, a.x, bid);
-    bar.wait(a);
-    for (int i = bid * kPT + threadIdx.x; i < Np; i += P * kPT) a.theta[i] = a.s[i] * a.x[i];
+    gemv_upper_theta(a, a.Z, false, bid);
     bar.wait(a);
     for (int it = 0; it < a.refine; ++it) {
       residual(a, bid);                  // r = D (h - G theta)
       bar.wait(a);
       gemv_upper_t(a, a.r, a.x, bid, bar);   // x = L^-1 r
       bar.wait(a);
-      gemv_upper(a, a.x, a.r, bid);      // r = L^-T x
-      bar.wait(a);
-      for (int i = bid * kPT + threadIdx.x; i < Np; i += P * kPT) a.theta[i] += a.s[i] * a.r[i];
+      gemv_upper_theta(a, a.x, true, bid);   // theta += D L^-T x
       bar.wait(a);
     }
     residual(a, bid);
@@ -613,21 +836,24 @@ __global__ __launch_bounds__(kPT) void k_solve_batch(const PSArgs* args, const i
   for (int q = team; q < n; q += T) solve_body(args[order[q]], bid);
 }
 
-// clears the arrival / release flags and the barrier time stamps
+// clears the arrival / release / progress flags and the time stamps
 __global__ void k_solve_reset(unsigned* sync, int nsync, int* flags) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nsync) sync[i] = 0u;
-  if (i == 0) { flags[1] = 0; flags[2] = 0; }
+  for (int i = threadIdx.x; i < nsync; i += blockDim.x) sync[i] = 0u;
+  if (threadIdx.x == 0) { flags[1] = 0; flags[2] = 0; }
 }
 
 size_t solve_shmem_bytes() {
-  return sizeof(double) * (3 * kTile * kLD);
+  return sizeof(double) * (4 * kTile * kLD);
 }
 
 int solve_workgroups(int nt) {
-  // about one trailing-update tile per workgroup in the first steps, at most 64
-  const int widest = nt * (nt + 1) / 2 + nt;
-  return widest < 64 ? (widest > 1 ? widest : 1) : 64;
+  // one bulk task per workgroup in the widest step (step 0: the lower
+  // triangle of the trailing matrix less its first tile, the v row and one
+  // identity row), plus the chain's workgroup; at most kPlainTeam
+  const int m = nt - 1;
+  const int widest = m > 0 ? m * (m + 1) / 2 - 1 + 2 * m : 2;
+  const int p = widest + 1;
+  return p < kPlainTeam ? p : kPlainTeam;
 }
 
 hipError_t prepare_solve_attributes() {
@@ -650,10 +876,12 @@ static PSArgs make_solve_args(const sfft_desc& d, const double* G, const double*
   a.theta = reinterpret_cast<double*>(ws + l.theta);
   a.r = reinterpret_cast<double*>(ws + l.rvec);
   a.rowabs = reinterpret_cast<double*>(ws + l.rowabs);
+  a.Z = reinterpret_cast<double*>(ws + l.Z);
   a.Ud = reinterpret_cast<double*>(ws + l.Ud);
   a.part = reinterpret_cast<double*>(ws + l.part);
   a.sync = reinterpret_cast<unsigned*>(ws + l.sync);
-  a.stamps = reinterpret_cast<unsigned long long*>(ws + l.sync + 512);
+  a.prog = a.sync + kSyncWords / 2;
+  a.stamps = reinterpret_cast<unsigned long long*>(ws + l.sync + kSyncWords * sizeof(unsigned));
   a.flags = reinterpret_cast<int*>(ws + l.flags);
   a.N = g.N; a.nt = l.nt; a.Np = l.nt * kTile; a.refine = max_refine;
   a.P = P > 0 ? P : solve_workgroups(l.nt);
@@ -665,7 +893,7 @@ hipError_t launch_solve(const sfft_desc& d, const double* G, const double* h, do
                         const Prof* pf, hipStream_t st) {
   PSArgs a = make_solve_args(d, G, h, coef, max_refine, info, ws, 0);
   prof_begin(pf, SFFT_PROF_SOLVE, st);
-  hipLaunchKernelGGL(k_solve_reset, dim3(1), dim3(640), 0, st, a.sync, 640, a.flags);
+  hipLaunchKernelGGL(k_solve_reset, dim3(1), dim3(256), 0, st, a.sync, kSyncClear, a.flags);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   void* args[] = {&a};
@@ -679,7 +907,7 @@ hipError_t launch_solve(const sfft_desc& d, const double* G, const double* h, do
 
 __global__ void k_solve_reset_batch(const PSArgs* args) {
   const PSArgs& a = args[blockIdx.x];
-  for (int i = threadIdx.x; i < 640; i += blockDim.x) a.sync[i] = 0u;
+  for (int i = threadIdx.x; i < kSyncClear; i += blockDim.x) a.sync[i] = 0u;
   if (threadIdx.x == 0) { a.flags[1] = 0; a.flags[2] = 0; }
 }
 
@@ -698,7 +926,7 @@ SolveBatch* solve_batch_create(const SolveItem* items, int n, int max_refine, in
                                hipError_t* err) {
   const int cus = num_cus > 0 ? num_cus : 256;
   if (P <= 0) P = std::max(1, cus / n);
-  if (P > 64) P = 64;
+  if (P > kMaxTeam) P = kMaxTeam;
   if (P < 1 || P > cus) { *err = hipErrorInvalidValue; return nullptr; }
   SolveBatch* b = new (std::nothrow) SolveBatch();
   if (!b) { *err = hipErrorOutOfMemory; return nullptr; }

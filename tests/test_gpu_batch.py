@@ -91,6 +91,32 @@ def test_batch_matches_single_pairs_eager_graph_and_tuned():
     b.close()
 
 
+def test_batch_fixed_plans_small_solve_teams():
+    """Solve teams of 1, 2 and 3 workgroups: with one workgroup it runs the
+    diagonal chain and the panel / trailing work in turn, with two the bulk
+    role has a single workgroup; odd row-pass blockings."""
+    torch, sf = _torch(), _sf()
+    pairs = _pairs()
+    refs = [_single(p, torch, sf) for p in pairs]
+    b = sf.Batch(SHAPES, dk=2, db=2, max_refine=1)
+    for k, p in enumerate(pairs):
+        b.load(k, torch.from_numpy(p.R).cuda(), torch.from_numpy(p.S).cuda())
+    for rpb, team in [(1, 1), (3, 2), (16, 3), (4, 0)]:
+        b.plan(rpb, team)
+        for k in range(len(SHAPES)):
+            b.bufs[k].coef.zero_()
+        b.run()
+        torch.cuda.synchronize()
+        _check(b, refs, f"rows per workgroup {rpb}, team {team}")
+    with pytest.raises(sf.SfftError) as e:
+        b.plan(0, 1)
+    assert e.value.status == sf.SFFT_ERR_INVALID_ARG
+    with pytest.raises(sf.SfftError) as e:
+        b.plan(4, 129)
+    assert e.value.status == sf.SFFT_ERR_INVALID_ARG
+    b.close()
+
+
 def test_batch_rejects_unsupported():
     torch, sf = _torch(), _sf()
     with pytest.raises(sf.SfftError) as e:
