@@ -78,7 +78,7 @@ struct Layout {
   // solve (overlaps the build region after `flags`)
   size_t A, Z, s, b, theta, x, rvec, rowabs, Ud, part, sync, solve_end;
   // subtract
-  size_t partials, sub_end;
+  size_t partials, k2, sub_end;
   size_t total;
   int nmom;           // doubles in the moment block
   int nt;             // Cholesky tiles per side
@@ -138,6 +138,8 @@ inline Layout make_layout(const Geometry& g) {
   o = base;
   l.npartials = subtract_blocks(g);
   l.partials = o; o = align256(o + sizeof(double) * l.npartials);
+  // coefficients of the chi2 judge's kappa2 polynomial, (2 DK + 1)^2
+  l.k2 = o; o = align256(o + sizeof(double) * 81);
   l.sub_end = o;
   size_t t = l.build_end;
   if (l.solve_end > t) t = l.solve_end;

@@ -7,7 +7,9 @@
 // pixel u by Horner in xt, with c_m(d, u_y) = sum_b a_((m,b),d) yt(u_y)^b
 // formed once per (tap, input row) and shared by a thread's 8 pixels.
 // Output tiles of 64 x 16 pixels; the reference tile with an r-pixel halo is
-// staged in LDS in FP64; accumulation in FP64.
+// staged in LDS in FP64; accumulation in FP64. The chi2 judge's kappa2(x)
+// polynomial depends on the coefficients only: a one-workgroup kernel forms
+// it once per launch.
 #include <cstring>
 #include <new>
 #include <vector>
@@ -25,7 +27,8 @@ struct SubArgs {
   int64_t ld;
   const double* coef;
   double* partials;
-  int W, H, N, DB, want_chi2;
+  double* k2;         // kappa2 polynomial: K2[e][f], e, f <= 2 DK
+  int W, H, N, DB, want_chi2, L, DK;
   double cR, cS, sx, sy;
 };
 
@@ -33,6 +36,43 @@ __device__ __forceinline__ int mono_index(int a, int b) {
   const int d = a + b;
   return d * (d + 1) / 2 + b;
 }
+
+// a * b + c, rounded twice (never contracted into one fused operation)
+__device__ __forceinline__ double mul_add_nc(double a, double b, double c) {
+#pragma clang fp contract(off)
+  return a * b + c;
+}
+
+// kappa2(x) = sum_d (sum_i a_(i,d) p_i(x))^2 = sum_{e,f} K2[e][f] xt^e yt^f:
+// Q[i][j] = sum_d a_(i,d) a_(j,d), K2[ai+aj][bi+bj] += Q[i][j] (64 threads)
+__device__ __forceinline__ void kappa2_body(const SubArgs& a) {
+  __shared__ double Q[36];
+  const int DK = a.DK, NK = (DK + 1) * (DK + 2) / 2, LL = a.L * a.L, NE = 2 * DK + 1;
+  const int t = threadIdx.x;
+  if (t < NK * NK) {
+    const int i = t / NK, j = t % NK;
+    double sacc = 0.0;
+    for (int dd = 0; dd < LL; ++dd) sacc = fma(a.coef[i * LL + dd], a.coef[j * LL + dd], sacc);
+    Q[t] = sacc;
+  }
+  __syncthreads();
+  if (t < NE * NE) {
+    const int e = t / NE, f = t % NE;
+    double sacc = 0.0;
+    int i = 0;
+    for (int di = 0; di <= DK; ++di)
+      for (int bi = 0; bi <= di; ++bi, ++i) {
+        int j = 0;
+        for (int dj = 0; dj <= DK; ++dj)
+          for (int bj = 0; bj <= dj; ++bj, ++j)
+            if ((di - bi) + (dj - bj) == e && bi + bj == f) sacc += Q[i * NK + j];
+      }
+    a.k2[t] = sacc;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_kappa2(SubArgs a) { kappa2_body(a); }
+__global__ __launch_bounds__(64) void k_kappa2_batch(const SubArgs* args) { kappa2_body(args[blockIdx.x]); }
 
 template <int L, int DK, typename TIO>
 __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
@@ -44,8 +84,6 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
   __shared__ double Rt[RH][RW + 1];
   __shared__ double cs[NK * L * L];
   __shared__ double red[2];
-  __shared__ double Qk[NK * NK];
-  __shared__ double K2[(2 * DK + 1) * (2 * DK + 1)];
   const int tid = threadIdx.x;
   const int W = a.W, H = a.H;
   // the fitted coefficients are read-only for the whole launch: reading them
@@ -55,41 +93,26 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
   const int x0 = vb.x * TX, y0 = vb.y * TY;
   for (int i = tid; i < NK * L * L; i += 128) cs[i] = a.coef[i];
   __syncthreads();
-  if (a.want_chi2) {
-    // kappa2(x) = sum_d (sum_i a_(i,d) p_i(x))^2 = sum_{e,f} K2[e][f] xt^e yt^f,
-    // K2[ai+aj][bi+bj] += sum_d a_(i,d) a_(j,d)
-    if (tid < NK * NK) {
-      const int i = tid / NK, j = tid % NK;
-      double sacc = 0.0;
-      for (int dd = 0; dd < L * L; ++dd) sacc = fma(cs[i * L * L + dd], cs[j * L * L + dd], sacc);
-      Qk[tid] = sacc;
+  // tiles whose halo stays inside the image need no periodic wrap
+  const bool inner = x0 >= r && x0 + RW - r <= W && y0 >= r && y0 + RH - r <= H;
+  if (inner) {
+    const TIO* Rb = static_cast<const TIO*>(a.R) + (int64_t)(y0 - r) * a.ld + (x0 - r);
+    for (int i = tid; i < RH * RW; i += 128) {
+      const int ly = i / RW, lx = i - (i / RW) * RW;
+      Rt[ly][lx] = (double)Rb[(int64_t)ly * a.ld + lx] - a.cR;
     }
-    __syncthreads();
-    constexpr int NE = 2 * DK + 1;
-    if (tid < NE * NE) {
-      const int e = tid / NE, f = tid % NE;
-      double sacc = 0.0;
-      int i = 0;
-      for (int di = 0; di <= DK; ++di)
-        for (int bi = 0; bi <= di; ++bi, ++i) {
-          int j = 0;
-          for (int dj = 0; dj <= DK; ++dj)
-            for (int bj = 0; bj <= dj; ++bj, ++j)
-              if ((di - bi) + (dj - bj) == e && bi + bj == f) sacc += Qk[i * NK + j];
-        }
-      K2[tid] = sacc;
+  } else {
+    for (int i = tid; i < RH * RW; i += 128) {
+      const int ly = i / RW, lx = i - (i / RW) * RW;
+      int yy = y0 + ly - r, xx = x0 + lx - r;
+      yy = (yy < 0) ? yy + H : yy;
+      yy = (yy >= H) ? yy - H : yy;
+      yy = (yy >= H) ? yy - H : yy;
+      xx = (xx < 0) ? xx + W : xx;
+      xx = (xx >= W) ? xx - W : xx;
+      xx = (xx >= W) ? xx - W : xx;
+      Rt[ly][lx] = (double)static_cast<const TIO*>(a.R)[(int64_t)yy * a.ld + xx] - a.cR;
     }
-  }
-  for (int i = tid; i < RH * RW; i += 128) {
-    const int ly = i / RW, lx = i - (i / RW) * RW;
-    int yy = y0 + ly - r, xx = x0 + lx - r;
-    yy = (yy < 0) ? yy + H : yy;
-    yy = (yy >= H) ? yy - H : yy;
-    yy = (yy >= H) ? yy - H : yy;
-    xx = (xx < 0) ? xx + W : xx;
-    xx = (xx >= W) ? xx - W : xx;
-    xx = (xx >= W) ? xx - W : xx;
-    Rt[ly][lx] = (double)static_cast<const TIO*>(a.R)[(int64_t)yy * a.ld + xx] - a.cR;
   }
   __syncthreads();
   const int tx = tid & 7, ty = tid >> 3;
@@ -99,9 +122,11 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     int ux = xb + q - r;
-    ux = (ux < 0) ? ux + W : ux;
-    ux = (ux >= W) ? ux - W : ux;
-    ux = (ux >= W) ? ux - W : ux;
+    if (!inner) {
+      ux = (ux < 0) ? ux + W : ux;
+      ux = (ux >= W) ? ux - W : ux;
+      ux = (ux >= W) ? ux - W : ux;
+    }
     xq[q] = (double)ux * a.sx - 1.0;
   }
   double acc[P];
@@ -127,8 +152,13 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
 #pragma unroll
       for (int m = 0; m <= DK; ++m) {
         double s = coef[mono_index(m, DK - m) * L * L + tap];
+        if (DK - m - 1 >= 0) {
+          // first step as a separate multiply and add: a fused step would
+          // read two scalar operands, which one VALU instruction cannot
+          s = mul_add_nc(s, yt, coef[mono_index(m, DK - m - 1) * L * L + tap]);
 #pragma unroll
-        for (int b = DK - m - 1; b >= 0; --b) s = fma(s, yt, coef[mono_index(m, b) * L * L + tap]);
+          for (int b = DK - m - 2; b >= 0; --b) s = fma(s, yt, coef[mono_index(m, b) * L * L + tap]);
+        }
         cm[m] = s;
       }
       // Horner in xt for all P pixels stage by stage: P independent chains
@@ -162,9 +192,12 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
     }
     double kk[2 * DK + 1];
     if (a.want_chi2) {
+      const __attribute__((address_space(4))) double* K2 =
+          (const __attribute__((address_space(4))) double*)a.k2;
 #pragma unroll
       for (int e = 0; e <= 2 * DK; ++e) {
         double s = 0.0;
+#pragma unroll
         for (int f = 2 * DK; f >= 0; --f) s = fma(s, yto, K2[e * (2 * DK + 1) + f]);
         kk[e] = s;
       }
@@ -185,7 +218,11 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
           for (int e = 2 * DK; e >= 0; --e) k2v = fma(k2v, xt, kk[e]);
           const double rv = Rt[ty + r][P * tx + p + r] + a.cR;
           const double var = fmax(sv, 1.0) + k2v * fmax(rv, 1.0);
-          chi = fma(dv, dv / var, chi);
+          // 1 / var: hardware estimate and two Newton steps (var >= 1)
+          double iv = __builtin_amdgcn_rcp(var);
+          iv = fma(fma(-var, iv, 1.0), iv, iv);
+          iv = fma(fma(-var, iv, 1.0), iv, iv);
+          chi = fma(dv * dv, iv, chi);
         }
       }
     }
@@ -244,7 +281,8 @@ static SubArgs make_sub_args(const sfft_desc& d, const void* R, const void* S, c
   SubArgs a{};
   a.R = R; a.S = S; a.D = D; a.ld = d.ld; a.coef = coef;
   a.partials = reinterpret_cast<double*>(ws + l.partials);
-  a.W = g.W; a.H = g.H; a.N = g.N; a.DB = g.DB; a.want_chi2 = want_chi2;
+  a.k2 = reinterpret_cast<double*>(ws + l.k2);
+  a.W = g.W; a.H = g.H; a.N = g.N; a.DB = g.DB; a.want_chi2 = want_chi2; a.L = g.L; a.DK = g.DK;
   a.cR = d.ref_pedestal; a.cS = d.sci_pedestal;
   a.sx = g.W > 1 ? 2.0 / (double)(g.W - 1) : 0.0;
   a.sy = g.H > 1 ? 2.0 / (double)(g.H - 1) : 0.0;
@@ -266,6 +304,10 @@ hipError_t launch_subtract(const sfft_desc& d, const void* R, const void* S, con
   const dim3 grid((g.W + kSubTX - 1) / kSubTX, (g.H + kSubTY - 1) / kSubTY);
   const bool f32 = d.image_dtype == SFFT_F32;
   prof_begin(pf, SFFT_PROF_SUBTRACT, st);
+  if (chi2) {
+    hipLaunchKernelGGL(k_kappa2, dim3(1), dim3(64), 0, st, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   switch (g.L) {
     case 1: e = launch_sub_l<1>(a, g.DK, f32, grid, st); break;
     case 3: e = launch_sub_l<3>(a, g.DK, f32, grid, st); break;
@@ -412,6 +454,9 @@ static void sub_batch_l(const SubBatch* b, int q, hipStream_t st) {
 
 hipError_t sub_batch_launch(const SubBatch* b, const Prof* pf, hipStream_t st) {
   prof_begin(pf, SFFT_PROF_SUBTRACT, st);
+  for (size_t q = 0; q < b->Ls.size(); ++q)
+    hipLaunchKernelGGL(k_kappa2_batch, dim3((unsigned)b->args[q].size()), dim3(64), 0, st,
+                       (const SubArgs*)b->dargs[q]);
   for (size_t q = 0; q < b->Ls.size(); ++q) {
     switch (b->Ls[q]) {
       case 1: sub_batch_l<1>(b, (int)q, st); break;
