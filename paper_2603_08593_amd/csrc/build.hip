@@ -49,8 +49,15 @@ __device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
 // ---------------------------------------------------------------------------
 // Stockham FFT of length N = 2^a 3^b 5^c (<= 4096) in LDS, 256 threads,
 // stages of radix 8, 4, 2, 3, 5 (host-chosen plan). buf uses the padded index
-// pad8(i); tw[m] = exp(-2 pi i m / N). Output in natural order.
+// pad8(i). Twiddles exp(-2 pi i m / N) come from two small tables,
+// twl[m mod 64] * twh[m div 64] (one complex product), so the transform's LDS
+// footprint stays close to its data.
 // ---------------------------------------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ cx<T> twiddle(const cx<T>* twl, const cx<T>* twh, int m) {
+  return cmul(twl[m & 63], twh[m >> 6]);
+}
 
 struct FftPlan {
   int nstages;
@@ -60,7 +67,7 @@ struct FftPlan {
 // POW2: N and Ns are powers of two, so the butterfly's position within its
 // group is a mask instead of a division
 template <typename T, int R, bool INV, int NQ, bool POW2>
-__device__ __forceinline__ void stockham_pass(cx<T>* buf, const cx<T>* tw, int N, int Ns) {
+__device__ __forceinline__ void stockham_pass(cx<T>* buf, const cx<T>* twl, const cx<T>* twh, int N, int Ns) {
   constexpr int MAXB = (NQ * kRowThreads + R * kRowThreads - 1) / (R * kRowThreads);
   const int nb = N / R;
   const int tstride = N / (Ns * R);
@@ -75,7 +82,7 @@ __device__ __forceinline__ void stockham_pass(cx<T>* buf, const cx<T>* tw, int N
       if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          cx<T> w = tw[r * k * tstride];
+          cx<T> w = twiddle(twl, twh, r * k * tstride);
           if (INV) w.im = -w.im;
           v[t][r] = cmul(v[t][r], w);
         }
@@ -98,16 +105,16 @@ __device__ __forceinline__ void stockham_pass(cx<T>* buf, const cx<T>* tw, int N
 }
 
 template <typename T, bool INV, int NQ, bool MIXED>
-__device__ void fft_lds(cx<T>* buf, const cx<T>* tw, int N, const FftPlan& plan) {
+__device__ void fft_lds(cx<T>* buf, const cx<T>* twl, const cx<T>* twh, int N, const FftPlan& plan) {
   int Ns = 1;
   for (int s = 0; s < plan.nstages; ++s) {
     const int R = plan.radix[s];
-    if (R == 8) stockham_pass<T, 8, INV, NQ, !MIXED>(buf, tw, N, Ns);
-    else if (R == 4) stockham_pass<T, 4, INV, NQ, !MIXED>(buf, tw, N, Ns);
-    else if (R == 2) stockham_pass<T, 2, INV, NQ, !MIXED>(buf, tw, N, Ns);
+    if (R == 8) stockham_pass<T, 8, INV, NQ, !MIXED>(buf, twl, twh, N, Ns);
+    else if (R == 4) stockham_pass<T, 4, INV, NQ, !MIXED>(buf, twl, twh, N, Ns);
+    else if (R == 2) stockham_pass<T, 2, INV, NQ, !MIXED>(buf, twl, twh, N, Ns);
     else if constexpr (MIXED) {
-      if (R == 3) stockham_pass<T, 3, INV, NQ, false>(buf, tw, N, Ns);
-      else stockham_pass<T, 5, INV, NQ, false>(buf, tw, N, Ns);
+      if (R == 3) stockham_pass<T, 3, INV, NQ, false>(buf, twl, twh, N, Ns);
+      else stockham_pass<T, 5, INV, NQ, false>(buf, twl, twh, N, Ns);
     }
     Ns *= R;
   }
@@ -150,41 +157,60 @@ struct RowArgs {
 };
 
 // NQ: row elements per thread, max(1, ceil(W / 256)); MIXED: W has factors 3 or 5
-template <typename T, typename TIN, int NQ, bool MIXED>
+template <typename T, typename TIN, int NQ, bool MIXED, bool PF>
 __device__ __forceinline__ void row_pass_body(const RowArgs& a, const VB vb) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int W = a.W;
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* tw = buf + (W + W / 8);
+  cx<T>* twl = buf + (W + W / 8);
+  cx<T>* twh = twl + 64;
   const cx<T>* twg = static_cast<const cx<T>*>(a.twW);
-  for (int i = threadIdx.x; i < W; i += kRowThreads) tw[i] = twg[i];
+  for (int i = threadIdx.x; i < 64; i += kRowThreads) twl[i] = twg[i < W ? i : 0];
+  for (int i = threadIdx.x; 64 * i < W; i += kRowThreads) twh[i] = twg[64 * i];
   constexpr int MAXQ = NQ;
   const int nsig = a.DK + 2;
   cx<T>* F = static_cast<cx<T>*>(a.F);
 
-  // pixels of the workgroup's next row, loaded while the current row is
-  // transformed (row moments, edge pixels and the input check are done by
-  // k_row_moments)
+  // Row moments, edge pixels and the input check are done by k_row_moments.
+  // PF: the pixels of the workgroup's next row are loaded while the current
+  // row is transformed; without it the memory latency is left to the other
+  // workgroups on the CU (the variant with the smaller register budget).
+  const TIN* Rg = static_cast<const TIN*>(a.R);
+  const TIN* Sg = static_cast<const TIN*>(a.S);
   TIN rn[MAXQ], sn[MAXQ];
-  auto prefetch = [&](int yy) {
+  if constexpr (PF) {
 #pragma unroll
     for (int q = 0; q < MAXQ; ++q) {
       const int x = threadIdx.x + q * kRowThreads;
-      const bool in = x < W && yy < a.H;
-      rn[q] = in ? static_cast<const TIN*>(a.R)[(int64_t)yy * a.ld + x] : (TIN)0;
-      sn[q] = in ? static_cast<const TIN*>(a.S)[(int64_t)yy * a.ld + x] : (TIN)0;
+      const bool in = x < W && vb.x < a.H;
+      rn[q] = in ? Rg[(int64_t)vb.x * a.ld + x] : (TIN)0;
+      sn[q] = in ? Sg[(int64_t)vb.x * a.ld + x] : (TIN)0;
     }
-  };
-  prefetch(vb.x);
+  }
 
   for (int y = vb.x; y < a.H; y += vb.nx) {
     TIN rc[MAXQ], sc[MAXQ];
+    // PF: the current row was loaded one step ahead; the next one is loaded
+    // now. Otherwise the current row is loaded here.
+    const int yl = PF ? y + vb.nx : y;
 #pragma unroll
     for (int q = 0; q < MAXQ; ++q) {
-      rc[q] = rn[q];
-      sc[q] = sn[q];
+      if constexpr (PF) {
+        rc[q] = rn[q];
+        sc[q] = sn[q];
+      }
+      const int x = threadIdx.x + q * kRowThreads;
+      const bool in = x < W && yl < a.H;
+      const TIN rv = in ? Rg[(int64_t)yl * a.ld + x] : (TIN)0;
+      const TIN sv = in ? Sg[(int64_t)yl * a.ld + x] : (TIN)0;
+      if constexpr (PF) {
+        rn[q] = rv;
+        sn[q] = sv;
+      } else {
+        rc[q] = rv;
+        sc[q] = sv;
+      }
     }
-    prefetch(y + vb.nx);
     // transforms: real signals s_a = xt^a R' (a <= DK), s_{DK+1} = S',
     // packed two per complex transform
     for (int f = 0; 2 * f < nsig; ++f) {
@@ -202,7 +228,7 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const VB vb) {
         }
       }
       __syncthreads();
-      fft_lds<T, false, NQ, MIXED>(buf, tw, W, a.plan);
+      fft_lds<T, false, NQ, MIXED>(buf, twl, twh, W, a.plan);
       const int half = W / 2;
       for (int kx = threadIdx.x; kx <= half; kx += kRowThreads) {
         const cx<T> z1 = buf[pad8(kx)];
@@ -224,8 +250,8 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const VB vb) {
 }
 
 template <typename T, typename TIN, int NQ, bool MIXED>
-__global__ __launch_bounds__(kRowThreads, 2) void k_row_pass(RowArgs a) {
-  row_pass_body<T, TIN, NQ, MIXED>(a, vb_grid());
+__global__ __launch_bounds__(kRowThreads, NQ >= 16 ? 2 : 4) void k_row_pass(RowArgs a) {
+  row_pass_body<T, TIN, NQ, MIXED, NQ >= 16>(a, vb_grid());
 }
 
 template <typename T, typename TIN, int NQ, bool MIXED>
@@ -233,7 +259,7 @@ __global__ __launch_bounds__(kRowThreads, 2) void k_row_pass_batch(const RowArgs
                                                                   int n) {
   int item;
   VB vb;
-  if (batch_locate(tab, n, item, vb)) row_pass_body<T, TIN, NQ, MIXED>(args[item], vb);
+  if (batch_locate(tab, n, item, vb)) row_pass_body<T, TIN, NQ, MIXED, true>(args[item], vb);
 }
 
 // ---------------------------------------------------------------------------
@@ -1071,7 +1097,7 @@ static RowArgs make_row_args(const Geometry& g, const sfft_desc& d, const void* 
 
 template <typename T>
 static size_t row_shmem(int W) {
-  return sizeof(cx<T>) * (size_t)(W + W / 8 + W) + sizeof(double) * 64;
+  return sizeof(cx<T>) * (size_t)(W + W / 8 + 64 + (W + 63) / 64) + sizeof(double) * 64;
 }
 
 static ColArgs make_col_args(const Geometry& g, unsigned char* ws, const Layout& l, const BuildPlan& p) {
