@@ -603,13 +603,31 @@ __device__ __forceinline__ void strip_xinv_body(const XinvArgs& a, const VB vb) 
   double sdc = 0.0, snq = 0.0;
   const double* eu = a.edge + (int64_t)au * 2 * a.H;
   const double* ev = a.edge + (int64_t)av * 2 * a.H;
-  for (int y = threadIdx.x; y < a.H; y += blockDim.x) {
-    int y2 = y + dy;
-    y2 = (y2 < 0) ? y2 + a.H : (y2 >= a.H ? y2 - a.H : y2);
-    const double wu = ipow((double)y * a.sy - 1.0, bu);
-    const double wv = ipow((double)y2 * a.sy - 1.0, bv);
-    sdc = fma(wu * eu[y], wv * ev[y2], sdc);
-    snq = fma(wu * eu[a.H + y], wv * ev[a.H + y2], snq);
+  // 4 rows per thread per round, their loads issued together
+  constexpr int kU = 4;
+  for (int yb = threadIdx.x; yb < a.H; yb += kU * blockDim.x) {
+    double u0[kU], u1[kU], v0[kU], v1[kU];
+    int ys[kU], y2s[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int y = yb + u * blockDim.x;
+      const bool in = y < a.H;
+      int y2 = y + dy;
+      y2 = (y2 < 0) ? y2 + a.H : (y2 >= a.H ? y2 - a.H : y2);
+      ys[u] = y;
+      y2s[u] = y2;
+      u0[u] = in ? eu[y] : 0.0;
+      u1[u] = in ? eu[a.H + y] : 0.0;
+      v0[u] = in ? ev[y2] : 0.0;
+      v1[u] = in ? ev[a.H + y2] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const double wu = ipow((double)ys[u] * a.sy - 1.0, bu);
+      const double wv = ipow((double)y2s[u] * a.sy - 1.0, bv);
+      sdc = fma(wu * u0[u], wv * v0[u], sdc);
+      snq = fma(wu * u1[u], wv * v1[u], snq);
+    }
   }
   double acc[32];
 #pragma unroll
@@ -902,24 +920,37 @@ __device__ __forceinline__ void row_moments_body(const RowArgs& a, const VB vb) 
     const TIN* Rr = static_cast<const TIN*>(a.R) + (int64_t)y * a.ld;
     const TIN* Sr = static_cast<const TIN*>(a.S) + (int64_t)y * a.ld;
     const bool vec = sizeof(TIN) == 4 && ((reinterpret_cast<uintptr_t>(Rr) | reinterpret_cast<uintptr_t>(Sr)) & 15) == 0;
-    for (int x00 = 0; x00 < W; x00 += 4 * 128) {
-      TIN rv[4][4], sv[4][4];
+    // 4 spans of 128 pixels per round; the next round's loads are issued
+    // before this round's pixels are accumulated
+    TIN rv[4][4], sv[4][4], rn[4][4], sn[4][4];
+    auto load = [&](int x00, TIN (&rr)[4][4], TIN (&ss)[4][4]) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int x0 = x00 + u * 128 + cc * 4;
         if (vec && x0 + 3 < W) {
           const float4 r4 = *reinterpret_cast<const float4*>(Rr + x0);
           const float4 s4 = *reinterpret_cast<const float4*>(Sr + x0);
-          rv[u][0] = r4.x; rv[u][1] = r4.y; rv[u][2] = r4.z; rv[u][3] = r4.w;
-          sv[u][0] = s4.x; sv[u][1] = s4.y; sv[u][2] = s4.z; sv[u][3] = s4.w;
+          rr[u][0] = r4.x; rr[u][1] = r4.y; rr[u][2] = r4.z; rr[u][3] = r4.w;
+          ss[u][0] = s4.x; ss[u][1] = s4.y; ss[u][2] = s4.z; ss[u][3] = s4.w;
         } else {
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
-            rv[u][k] = (x0 + k < W) ? Rr[x0 + k] : (TIN)0;
-            sv[u][k] = (x0 + k < W) ? Sr[x0 + k] : (TIN)0;
+            rr[u][k] = (x0 + k < W) ? Rr[x0 + k] : (TIN)0;
+            ss[u][k] = (x0 + k < W) ? Sr[x0 + k] : (TIN)0;
           }
         }
       }
+    };
+    load(0, rn, sn);
+    for (int x00 = 0; x00 < W; x00 += 4 * 128) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          rv[u][k] = rn[u][k];
+          sv[u][k] = sn[u][k];
+        }
+      if (x00 + 4 * 128 < W) load(x00 + 4 * 128, rn, sn);
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
