@@ -703,18 +703,32 @@ __device__ __forceinline__ void moments_body(const MomArgs& a, const VB vb) {
   const int np = 2 * a.DB + 1;
   int id = vb.x;
   double s = 0.0;
+  // sum over y of yt^n src[y * stride]: 8 rows per thread per round, their
+  // loads issued together (rows ascending per thread)
+  auto ysum = [&](const double* src, int64_t stride, int n) {
+    for (int yb = threadIdx.x; yb < a.H; yb += 8 * blockDim.x) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int y = yb + u * blockDim.x;
+        v[u] = y < a.H ? src[(int64_t)y * stride] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int y = yb + u * blockDim.x;
+        if (y < a.H) s += ipow((double)y * a.sy - 1.0, n) * v[u];
+      }
+    }
+  };
   if (id < nM2) {
     const int m = id / nm, n = id % nm;
-    for (int y = threadIdx.x; y < a.H; y += blockDim.x)
-      s += ipow((double)y * a.sy - 1.0, n) * a.MR[(int64_t)m * a.H + y];
+    ysum(a.MR + (int64_t)m * a.H, 1, n);
   } else if ((id -= nM2) < nE) {
     const int e = id / nm, n = id % nm;
-    for (int y = threadIdx.x; y < a.H; y += blockDim.x)
-      s += ipow((double)y * a.sy - 1.0, n) * a.ER[(int64_t)y * 2 * a.r + e];
+    ysum(a.ER + e, 2 * a.r, n);
   } else if ((id -= nE) < nMS) {
     const int ac = id / (a.DB + 1), bc = id % (a.DB + 1);
-    for (int y = threadIdx.x; y < a.H; y += blockDim.x)
-      s += ipow((double)y * a.sy - 1.0, bc) * a.MS[(int64_t)ac * a.H + y];
+    ysum(a.MS + (int64_t)ac * a.H, 1, bc);
   } else if ((id -= nMS) < np) {
     for (int x = threadIdx.x; x < a.W; x += blockDim.x) s += ipow((double)x * a.sx - 1.0, id);
   } else {
@@ -758,66 +772,104 @@ __device__ __forceinline__ void kb_assemble_body(const KbArgs& a, const VB vb) {
   const int L2 = a.L * a.L;
   const int nKL = a.nK * L2;
   const int nm = a.DK + a.DB + 1;
-  const double* M2 = a.mom;
+  // the moment block and the seam rows (y < r, y >= H - r) of the per-row
+  // moments and edge pixels, staged in LDS: every entry reads them many times
+  constexpr int kMaxNm = 7, kMaxR2 = 14;
+  __shared__ double smom[kMaxNm * kMaxNm + kMaxR2 * kMaxNm + 25 + 18];
+  __shared__ double sMR[kMaxNm * kMaxR2];
+  __shared__ double sER[kMaxR2 * kMaxR2];
+  {
+    const int r2 = 2 * a.r;
+    const int nmomv = nm * nm + r2 * nm + (a.DB + 1) * (a.DB + 1) + 2 * (2 * a.DB + 1);
+    for (int i = threadIdx.x; i < nmomv; i += blockDim.x) smom[i] = a.mom[i];
+    for (int i = threadIdx.x; i < nm * r2; i += blockDim.x) {
+      const int m = i / r2, sj = i % r2;
+      const int uy = sj < a.r ? sj : a.H - a.r + (sj - a.r);
+      sMR[i] = a.MR[(int64_t)m * a.H + uy];
+    }
+    for (int i = threadIdx.x; i < r2 * r2; i += blockDim.x) {
+      const int sj = i / r2, e = i % r2;
+      const int uy = sj < a.r ? sj : a.H - a.r + (sj - a.r);
+      sER[i] = a.ER[(int64_t)uy * r2 + e];
+    }
+    __syncthreads();
+  }
+  auto yseam = [&](int uy) { return uy < a.r ? uy : a.r + (uy - (a.H - a.r)); };
+  const double* M2 = smom;
   const double* E = M2 + nm * nm;
   const double* MSy = E + 2 * a.r * nm;
   const double* Px = MSy + (a.DB + 1) * (a.DB + 1);
   const double* Py = Px + 2 * a.DB + 1;
-  const int tid = vb.x * blockDim.x + threadIdx.x;
+  // one wave per kernel-background entry: the entry is a sum of products
+  // (the moment terms and the x- and y-seam corrections); lane t takes terms
+  // t, t + 64, ... of the flattened list, then a fixed-order wave sum. The
+  // last wave forms the background block and the background RHS.
+  const int lane = threadIdx.x & 63;
+  const int entry = vb.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   const int nkb = nKL * a.nB;
-  if (tid < nkb) {
-    const int c = tid % a.nB;
-    const int row = tid / a.nB;
+  if (entry < nkb) {
+    const int c = entry % a.nB;
+    const int row = entry / a.nB;
     const int i = row / L2, d = row % L2;
     const int dy = d / a.L - a.r, dx = d % a.L - a.r;
     int ai, bi, ac, bc;
     mono_ab(i, ai, bi);
     mono_ab(c, ac, bc);
     const int W = a.W, H = a.H, r = a.r;
-    // x-seam columns of this dx: (ux, edge slot e)
-    int xs0 = 0, xs1 = 0;   // ux range [xs0, xs1)
+    // x-seam columns [xs0, xs1) of this dx and y-seam rows [ys0, ys1) of dy
+    int xs0 = 0, xs1 = 0;
     if (dx > 0) { xs0 = W - dx; xs1 = W; }
     else if (dx < 0) { xs0 = 0; xs1 = -dx; }
+    int ys0 = 0, ys1 = 0;
+    if (dy > 0) { ys0 = H - dy; ys1 = H; }
+    else if (dy < 0) { ys0 = 0; ys1 = -dy; }
+    const int nxs = xs1 - xs0, nys = ys1 - ys0;
     auto eslot = [&](int ux) { return ux < r ? ux : r + (ux - (W - r)); };
     auto dX = [&](int ux) {
       int w = ux + dx;
       w = (w < 0) ? w + W : (w >= W ? w - W : w);
       return ipow((double)w * a.sx - 1.0, ac) - ipow(-1.0 + a.sx * (double)(ux + dx), ac);
     };
-    double tot = 0.0;
-    for (int l = 0; l <= bc; ++l) {
-      const int n = bi + l;
-      double inner = 0.0;
-      for (int k = 0; k <= ac; ++k)
-        inner += binom(ac, k) * ipow(a.sx * dx, ac - k) * M2[(ai + k) * nm + n];
-      for (int ux = xs0; ux < xs1; ++ux)
-        inner += ipow((double)ux * a.sx - 1.0, ai) * dX(ux) * E[eslot(ux) * nm + n];
-      tot += binom(bc, l) * ipow(a.sy * dy, bc - l) * inner;
-    }
-    int ys0 = 0, ys1 = 0;
-    if (dy > 0) { ys0 = H - dy; ys1 = H; }
-    else if (dy < 0) { ys0 = 0; ys1 = -dy; }
-    for (int uy = ys0; uy < ys1; ++uy) {
+    auto yw = [&](int uy) {
       int w = uy + dy;
       w = (w < 0) ? w + H : (w >= H ? w - H : w);
       const double dY = ipow((double)w * a.sy - 1.0, bc) - ipow(-1.0 + a.sy * (double)(uy + dy), bc);
-      double I = 0.0;
-      for (int k = 0; k <= ac; ++k)
-        I += binom(ac, k) * ipow(a.sx * dx, ac - k) * a.MR[(int64_t)(ai + k) * H + uy];
-      for (int ux = xs0; ux < xs1; ++ux)
-        I += ipow((double)ux * a.sx - 1.0, ai) * dX(ux) * a.ER[(int64_t)uy * 2 * r + eslot(ux)];
-      tot += ipow((double)uy * a.sy - 1.0, bi) * dY * I;
+      return ipow((double)uy * a.sy - 1.0, bi) * dY;
+    };
+    // terms: (l, k) moments; (l, ux) x-seam; (uy, k) y-seam; (uy, ux) corner
+    const int nA = (bc + 1) * (ac + 1), nBx = (bc + 1) * nxs, nC = nys * (ac + 1), nD = nys * nxs;
+    double part = 0.0;
+    for (int t = lane; t < nA + nBx + nC + nD; t += 64) {
+      if (t < nA) {
+        const int l = t / (ac + 1), k = t % (ac + 1);
+        part += binom(bc, l) * ipow(a.sy * dy, bc - l) * binom(ac, k) * ipow(a.sx * dx, ac - k) *
+                M2[(ai + k) * nm + bi + l];
+      } else if (t < nA + nBx) {
+        const int u = t - nA, l = u / nxs, ux = xs0 + u % nxs;
+        part += binom(bc, l) * ipow(a.sy * dy, bc - l) * ipow((double)ux * a.sx - 1.0, ai) * dX(ux) *
+                E[eslot(ux) * nm + bi + l];
+      } else if (t < nA + nBx + nC) {
+        const int u = t - nA - nBx, uy = ys0 + u / (ac + 1), k = u % (ac + 1);
+        part += yw(uy) * binom(ac, k) * ipow(a.sx * dx, ac - k) * sMR[(ai + k) * 2 * r + yseam(uy)];
+      } else {
+        const int u = t - nA - nBx - nC, uy = ys0 + u / nxs, ux = xs0 + u % nxs;
+        part += yw(uy) * ipow((double)ux * a.sx - 1.0, ai) * dX(ux) * sER[yseam(uy) * 2 * r + eslot(ux)];
+      }
     }
-    a.G[(int64_t)row * a.N + nKL + c] = tot;
-    a.G[(int64_t)(nKL + c) * a.N + row] = tot;
-  } else if (tid < nkb + a.nB * a.nB) {
-    const int t = tid - nkb;
-    const int c = t / a.nB, c2 = t % a.nB;
-    int ac, bc, ac2, bc2;
-    mono_ab(c, ac, bc);
-    mono_ab(c2, ac2, bc2);
-    a.G[(int64_t)(nKL + c) * a.N + nKL + c2] = Px[ac + ac2] * Py[bc + bc2];
-    if (c2 == 0) a.hv[nKL + c] = MSy[ac * (a.DB + 1) + bc];
+    const double tot = wave_sum(part);
+    if (lane == 0) {
+      a.G[(int64_t)row * a.N + nKL + c] = tot;
+      a.G[(int64_t)(nKL + c) * a.N + row] = tot;
+    }
+  } else if (entry == nkb) {
+    for (int t = lane; t < a.nB * a.nB; t += 64) {
+      const int c = t / a.nB, c2 = t % a.nB;
+      int ac, bc, ac2, bc2;
+      mono_ab(c, ac, bc);
+      mono_ab(c2, ac2, bc2);
+      a.G[(int64_t)(nKL + c) * a.N + nKL + c2] = Px[ac + ac2] * Py[bc + bc2];
+      if (c2 == 0) a.hv[nKL + c] = MSy[ac * (a.DB + 1) + bc];
+    }
   }
 }
 
@@ -897,25 +949,34 @@ __device__ __forceinline__ void row_moments_body(const RowArgs& a, const VB vb) 
   const int y = vb.x * kMomRowsPerWG + wave * kMomRowsPerWave + rr;
   const int W = a.W;
   const int nm = a.DK + a.DB + 1;
-  double mr[9], ms[5];
+  // every power up to the largest supported degree (DK <= 2, DB <= 4) is
+  // accumulated without predicates; only the first nm / DB + 1 are stored
+  constexpr int kMR = 7, kMS = 5;
+  double mr[kMR], ms[kMS];
 #pragma unroll
-  for (int m = 0; m < 9; ++m) mr[m] = 0.0;
+  for (int m = 0; m < kMR; ++m) mr[m] = 0.0;
 #pragma unroll
-  for (int m = 0; m < 5; ++m) ms[m] = 0.0;
+  for (int m = 0; m < kMS; ++m) ms[m] = 0.0;
   bool bad = false;
   auto accumulate = [&](int x, double rv, double sv) {
     bad |= !(is_finite_d(rv) && is_finite_d(sv));
-    if (x < a.r) a.ER[(int64_t)y * 2 * a.r + x] = rv;
-    if (x >= W - a.r) a.ER[(int64_t)y * 2 * a.r + a.r + (x - (W - a.r))] = rv;
     const double xt = (double)x * a.sx - 1.0;
     double pw = 1.0;
 #pragma unroll
-    for (int m = 0; m < 9; ++m) {
-      if (m < nm) mr[m] = fma(pw, rv, mr[m]);
-      if (m <= a.DB && m < 5) ms[m] = fma(pw, sv, ms[m]);
+    for (int m = 0; m < kMR; ++m) {
+      mr[m] = fma(pw, rv, mr[m]);
+      if (m < kMS) ms[m] = fma(pw, sv, ms[m]);
       pw *= xt;
     }
   };
+  // edge pixels x < r and x >= W - r of the row, for the seam corrections
+  if (y < a.H) {
+    const TIN* Rr = static_cast<const TIN*>(a.R) + (int64_t)y * a.ld;
+    for (int e = cc; e < 2 * a.r; e += 32) {
+      const int x = e < a.r ? e : W - 2 * a.r + e;
+      a.ER[(int64_t)y * 2 * a.r + e] = (double)Rr[x] - a.cR;
+    }
+  }
   if (y < a.H) {
     const TIN* Rr = static_cast<const TIN*>(a.R) + (int64_t)y * a.ld;
     const TIN* Sr = static_cast<const TIN*>(a.S) + (int64_t)y * a.ld;
@@ -951,19 +1012,27 @@ __device__ __forceinline__ void row_moments_body(const RowArgs& a, const VB vb) 
           sv[u][k] = sn[u][k];
         }
       if (x00 + 4 * 128 < W) load(x00 + 4 * 128, rn, sn);
+      if (x00 + 4 * 128 <= W) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int x = x00 + u * 128 + cc * 4 + k;
-          if (x < W) accumulate(x, (double)rv[u][k] - a.cR, (double)sv[u][k] - a.cS);
-        }
+          for (int k = 0; k < 4; ++k)
+            accumulate(x00 + u * 128 + cc * 4 + k, (double)rv[u][k] - a.cR, (double)sv[u][k] - a.cS);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int x = x00 + u * 128 + cc * 4 + k;
+            if (x < W) accumulate(x, (double)rv[u][k] - a.cR, (double)sv[u][k] - a.cS);
+          }
+      }
     }
   }
   if (bad) atomicOr(a.flags, 1);
   // sum over the 32 lanes of each row (fixed order: butterfly 16, 8, 4, 2, 1)
 #pragma unroll
-  for (int m = 0; m < 9; ++m) {
+  for (int m = 0; m < kMR; ++m) {
     if (m < nm) {
       double v = mr[m];
 #pragma unroll
@@ -972,7 +1041,7 @@ __device__ __forceinline__ void row_moments_body(const RowArgs& a, const VB vb) 
     }
   }
 #pragma unroll
-  for (int m = 0; m < 5; ++m) {
+  for (int m = 0; m < kMS; ++m) {
     if (m <= a.DB) {
       double v = ms[m];
 #pragma unroll
@@ -1176,7 +1245,8 @@ static KbArgs make_kb_args(const Geometry& g, const MomArgs& ma, double* G, doub
   return ka;
 }
 
-static int kb_grid(const Geometry& g) { return (g.nK * g.L * g.L * g.nB + g.nB * g.nB + 255) / 256; }
+// one wave per kernel-background entry plus one for the background block
+static int kb_grid(const Geometry& g) { return (g.nK * g.L * g.L * g.nB + 1 + 3) / 4; }
 
 static GatherArgs make_gather_args(const Geometry& g, const XinvArgs& xa, double* G, double* hv) {
   GatherArgs ga{};

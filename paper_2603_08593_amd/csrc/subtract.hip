@@ -44,15 +44,33 @@ __device__ __forceinline__ double mul_add_nc(double a, double b, double c) {
 }
 
 // kappa2(x) = sum_d (sum_i a_(i,d) p_i(x))^2 = sum_{e,f} K2[e][f] xt^e yt^f:
-// Q[i][j] = sum_d a_(i,d) a_(j,d), K2[ai+aj][bi+bj] += Q[i][j] (64 threads)
+// Q[i][j] = sum_d a_(i,d) a_(j,d), K2[ai+aj][bi+bj] += Q[i][j]. One
+// workgroup of 256 threads: the kernel coefficients are staged in LDS, each
+// Q entry is summed as 7 fixed chunks (one thread each) added in order.
+constexpr int kK2Threads = 256;
+constexpr int kK2Chunks = 7;
+
 __device__ __forceinline__ void kappa2_body(const SubArgs& a) {
+  __shared__ double cf[6 * 225];
+  __shared__ double part[36 * kK2Chunks];
   __shared__ double Q[36];
   const int DK = a.DK, NK = (DK + 1) * (DK + 2) / 2, LL = a.L * a.L, NE = 2 * DK + 1;
   const int t = threadIdx.x;
-  if (t < NK * NK) {
-    const int i = t / NK, j = t % NK;
+  for (int i = t; i < NK * LL; i += kK2Threads) cf[i] = a.coef[i];
+  __syncthreads();
+  const int len = (LL + kK2Chunks - 1) / kK2Chunks;
+  if (t < NK * NK * kK2Chunks) {
+    const int q = t / kK2Chunks, ch = t % kK2Chunks;
+    const int i = q / NK, j = q % NK;
     double sacc = 0.0;
-    for (int dd = 0; dd < LL; ++dd) sacc = fma(a.coef[i * LL + dd], a.coef[j * LL + dd], sacc);
+    const int d1 = min(LL, (ch + 1) * len);
+    for (int dd = ch * len; dd < d1; ++dd) sacc = fma(cf[i * LL + dd], cf[j * LL + dd], sacc);
+    part[t] = sacc;
+  }
+  __syncthreads();
+  if (t < NK * NK) {
+    double sacc = 0.0;
+    for (int ch = 0; ch < kK2Chunks; ++ch) sacc += part[t * kK2Chunks + ch];
     Q[t] = sacc;
   }
   __syncthreads();
@@ -71,8 +89,8 @@ __device__ __forceinline__ void kappa2_body(const SubArgs& a) {
   }
 }
 
-__global__ __launch_bounds__(64) void k_kappa2(SubArgs a) { kappa2_body(a); }
-__global__ __launch_bounds__(64) void k_kappa2_batch(const SubArgs* args) { kappa2_body(args[blockIdx.x]); }
+__global__ __launch_bounds__(kK2Threads) void k_kappa2(SubArgs a) { kappa2_body(a); }
+__global__ __launch_bounds__(kK2Threads) void k_kappa2_batch(const SubArgs* args) { kappa2_body(args[blockIdx.x]); }
 
 template <int L, int DK, typename TIO>
 __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
@@ -305,7 +323,7 @@ hipError_t launch_subtract(const sfft_desc& d, const void* R, const void* S, con
   const bool f32 = d.image_dtype == SFFT_F32;
   prof_begin(pf, SFFT_PROF_SUBTRACT, st);
   if (chi2) {
-    hipLaunchKernelGGL(k_kappa2, dim3(1), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(k_kappa2, dim3(1), dim3(kK2Threads), 0, st, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   switch (g.L) {
@@ -455,7 +473,7 @@ static void sub_batch_l(const SubBatch* b, int q, hipStream_t st) {
 hipError_t sub_batch_launch(const SubBatch* b, const Prof* pf, hipStream_t st) {
   prof_begin(pf, SFFT_PROF_SUBTRACT, st);
   for (size_t q = 0; q < b->Ls.size(); ++q)
-    hipLaunchKernelGGL(k_kappa2_batch, dim3((unsigned)b->args[q].size()), dim3(64), 0, st,
+    hipLaunchKernelGGL(k_kappa2_batch, dim3((unsigned)b->args[q].size()), dim3(kK2Threads), 0, st,
                        (const SubArgs*)b->dargs[q]);
   for (size_t q = 0; q < b->Ls.size(); ++q) {
     switch (b->Ls[q]) {
