@@ -24,8 +24,8 @@ namespace sfft {
 hipError_t launch_build(const sfft_desc& d, const void* R, const void* S, double* G, double* hv,
                         unsigned char* ws, const BuildPlan& p, const Prof* pf, hipStream_t st);
 hipError_t launch_solve(const sfft_desc& d, const double* G, const double* h, double* coef,
-                        int max_refine, sfft_solve_info* info, unsigned char* ws, const Prof* pf,
-                        hipStream_t st);
+                        int max_refine, sfft_solve_info* info, unsigned char* ws, int num_cus,
+                        const Prof* pf, hipStream_t st);
 hipError_t launch_subtract(const sfft_desc& d, const void* R, const void* S, const double* coef,
                            void* D, double* chi2, unsigned char* ws, const Prof* pf,
                            hipStream_t st);
@@ -255,7 +255,7 @@ sfft_status sfft_solve(sfft_handle h, const sfft_desc* d, const double* G, const
   if ((s = check_ws(ws, ws_bytes, make_layout(make_geometry(*d)).solve_end)) != SFFT_OK) return s;
   if ((s = check_device(h)) != SFFT_OK) return s;
   const hipError_t e = launch_solve(*d, G, hv, coef, max_refine, info,
-                                    static_cast<unsigned char*>(ws), &h->prof,
+                                    static_cast<unsigned char*>(ws), h->num_cus, &h->prof,
                                     static_cast<hipStream_t>(stream));
   return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
 }

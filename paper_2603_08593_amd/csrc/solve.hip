@@ -2,7 +2,7 @@
 //
 // The SFFT fit ends in a dense symmetric positive-definite solve (the
 // least-squares normal equations of the delta-basis kernel, paper Sec. 1).
-// One persistent cooperative kernel with P co-resident workgroups does:
+// One persistent kernel with P co-resident workgroups (one per CU) does:
 //   equilibration  A = D G D, D = diag(G)^-1/2, v = D h;
 //   right-looking blocked Cholesky on 64 x 64 tiles of the matrix augmented
 //   below by the right-hand side row v^T and by the identity: factorising
@@ -889,16 +889,21 @@ static PSArgs make_solve_args(const sfft_desc& d, const double* G, const double*
 }
 
 hipError_t launch_solve(const sfft_desc& d, const double* G, const double* h, double* coef,
-                        int max_refine, sfft_solve_info* info, unsigned char* ws,
+                        int max_refine, sfft_solve_info* info, unsigned char* ws, int num_cus,
                         const Prof* pf, hipStream_t st) {
   PSArgs a = make_solve_args(d, G, h, coef, max_refine, info, ws, 0);
+  // a plain launch (no cooperative-launch overhead, capturable in a graph):
+  // the LDS footprint allows one solve workgroup per CU and P is at most half
+  // the CUs, so every workgroup becomes resident while the others wait; the
+  // waits are bounded anyway
+  const int cus = num_cus > 0 ? num_cus : 256;
+  if (a.P > cus / 2) a.P = cus / 2 > 0 ? cus / 2 : 1;
   prof_begin(pf, SFFT_PROF_SOLVE, st);
   hipLaunchKernelGGL(k_solve_reset, dim3(1), dim3(256), 0, st, a.sync, kSyncClear, a.flags);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  void* args[] = {&a};
-  e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_solve_persistent), dim3(a.P),
-                                 dim3(kPT), args, (unsigned)solve_shmem_bytes(), st);
+  hipLaunchKernelGGL(k_solve_persistent, dim3(a.P), dim3(kPT), solve_shmem_bytes(), st, a);
+  e = hipGetLastError();
   prof_end(pf, SFFT_PROF_SOLVE, st);
   return e;
 }
