@@ -112,6 +112,25 @@ def roofline_entry(name, avg_s, traffic, fp32=False):
             "avg_us": round(avg_s * 1e6, 2), "alg_bytes": w["bytes"], "alg_flops": w["flops"]}
 
 
+def build_roofline(build_s, fp32=False):
+    """The whole system build (sfft_build_system, every kernel from the row
+    moments to the gather) against the HBM roofline: algorithmic bytes =
+    images read once, row spectra written and read back, column strips
+    written and read back, normal matrix written."""
+    npix = W * H
+    nkx = W // 2 + 1
+    nsig = DK + 2
+    nk = (DK + 1) * (DK + 2) // 2
+    npairs = nk * (nk + 1) // 2 + nk
+    N = nk * L * L + (DB + 1) * (DB + 2) // 2
+    cspec = 8 if fp32 else 16
+    b = (2 * npix * 4 + 2 * nsig * H * nkx * cspec + 2 * npairs * (2 * (L - 1) + 1) * nkx * 16
+         + N * N * 8)
+    ach = b / build_s / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "alg_bytes": b, "build_us": round(build_s * 1e6, 2)}
+
+
 def load_traffic(kernel):
     """HBM bytes per launch from committed rocprofv3 counter summaries, or
     None when absent or taken on a different kernel source."""
@@ -483,6 +502,7 @@ def main():
         "phase_us": {k: round(v * 1e6, 2) for k, v in avg.items()},
         "roofline": {k: v for k, v in roof_all[dominant].items()},
         "roofline_kernels": roof_all,
+        "build_roofline": build_roofline(avg["build"], fp32),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pair)

@@ -157,7 +157,7 @@ struct RowArgs {
 };
 
 // NQ: row elements per thread, max(1, ceil(W / 256)); MIXED: W has factors 3 or 5
-template <typename T, typename TIN, int NQ, bool MIXED, bool PF>
+template <typename T, typename TIN, int NQ, bool MIXED>
 __device__ __forceinline__ void row_pass_body(const RowArgs& a, const VB vb) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int W = a.W;
@@ -172,44 +172,30 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const VB vb) {
   cx<T>* F = static_cast<cx<T>*>(a.F);
 
   // Row moments, edge pixels and the input check are done by k_row_moments.
-  // PF: the pixels of the workgroup's next row are loaded while the current
-  // row is transformed; without it the memory latency is left to the other
-  // workgroups on the CU (the variant with the smaller register budget).
+  // The pixels of the workgroup's next row are loaded while the current row
+  // is transformed.
   const TIN* Rg = static_cast<const TIN*>(a.R);
   const TIN* Sg = static_cast<const TIN*>(a.S);
   TIN rn[MAXQ], sn[MAXQ];
-  if constexpr (PF) {
 #pragma unroll
-    for (int q = 0; q < MAXQ; ++q) {
-      const int x = threadIdx.x + q * kRowThreads;
-      const bool in = x < W && vb.x < a.H;
-      rn[q] = in ? Rg[(int64_t)vb.x * a.ld + x] : (TIN)0;
-      sn[q] = in ? Sg[(int64_t)vb.x * a.ld + x] : (TIN)0;
-    }
+  for (int q = 0; q < MAXQ; ++q) {
+    const int x = threadIdx.x + q * kRowThreads;
+    const bool in = x < W && vb.x < a.H;
+    rn[q] = in ? Rg[(int64_t)vb.x * a.ld + x] : (TIN)0;
+    sn[q] = in ? Sg[(int64_t)vb.x * a.ld + x] : (TIN)0;
   }
 
   for (int y = vb.x; y < a.H; y += vb.nx) {
     TIN rc[MAXQ], sc[MAXQ];
-    // PF: the current row was loaded one step ahead; the next one is loaded
-    // now. Otherwise the current row is loaded here.
-    const int yl = PF ? y + vb.nx : y;
+    const int yl = y + vb.nx;
 #pragma unroll
     for (int q = 0; q < MAXQ; ++q) {
-      if constexpr (PF) {
-        rc[q] = rn[q];
-        sc[q] = sn[q];
-      }
+      rc[q] = rn[q];
+      sc[q] = sn[q];
       const int x = threadIdx.x + q * kRowThreads;
       const bool in = x < W && yl < a.H;
-      const TIN rv = in ? Rg[(int64_t)yl * a.ld + x] : (TIN)0;
-      const TIN sv = in ? Sg[(int64_t)yl * a.ld + x] : (TIN)0;
-      if constexpr (PF) {
-        rn[q] = rv;
-        sn[q] = sv;
-      } else {
-        rc[q] = rv;
-        sc[q] = sv;
-      }
+      rn[q] = in ? Rg[(int64_t)yl * a.ld + x] : (TIN)0;
+      sn[q] = in ? Sg[(int64_t)yl * a.ld + x] : (TIN)0;
     }
     // transforms: real signals s_a = xt^a R' (a <= DK), s_{DK+1} = S',
     // packed two per complex transform
@@ -250,8 +236,8 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const VB vb) {
 }
 
 template <typename T, typename TIN, int NQ, bool MIXED>
-__global__ __launch_bounds__(kRowThreads, NQ >= 16 ? 2 : 4) void k_row_pass(RowArgs a) {
-  row_pass_body<T, TIN, NQ, MIXED, NQ >= 16>(a, vb_grid());
+__global__ __launch_bounds__(kRowThreads, NQ >= 16 ? 2 : 3) void k_row_pass(RowArgs a) {
+  row_pass_body<T, TIN, NQ, MIXED>(a, vb_grid());
 }
 
 template <typename T, typename TIN, int NQ, bool MIXED>
@@ -259,7 +245,7 @@ __global__ __launch_bounds__(kRowThreads, 2) void k_row_pass_batch(const RowArgs
                                                                   int n) {
   int item;
   VB vb;
-  if (batch_locate(tab, n, item, vb)) row_pass_body<T, TIN, NQ, MIXED, true>(args[item], vb);
+  if (batch_locate(tab, n, item, vb)) row_pass_body<T, TIN, NQ, MIXED>(args[item], vb);
 }
 
 // ---------------------------------------------------------------------------
@@ -1261,7 +1247,9 @@ static hipError_t launch_row(const Geometry& g, const sfft_desc& d, const void* 
                              hipStream_t st) {
   const RowArgs a = make_row_args(g, d, R, S, ws, l, p);
   const size_t shmem = row_shmem<T>(g.W);
-  int grid = g.H < 4 * p.num_cus ? g.H : 4 * p.num_cus;
+  // one resident wave of workgroups (3 per CU for rows up to 2048 pixels)
+  const int per_cu = (g.W + kRowThreads - 1) / kRowThreads >= 16 ? 2 : 3;
+  int grid = g.H < per_cu * p.num_cus ? g.H : per_cu * p.num_cus;
   const bool f32 = d.image_dtype == SFFT_F32;
   const bool mixed = (g.W % 3 == 0) || (g.W % 5 == 0);
 #define SFFT_ROW(NQ)                                                                              \
