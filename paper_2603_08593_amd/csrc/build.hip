@@ -157,7 +157,7 @@ struct RowArgs {
 };
 
 // NQ: row elements per thread, max(1, ceil(W / 256)); MIXED: W has factors 3 or 5
-template <typename T, typename TIN, int NQ, bool MIXED>
+template <typename T, typename TIN, int NQ, bool MIXED, bool PF>
 __device__ __forceinline__ void row_pass_body(const RowArgs& a, const VB vb) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int W = a.W;
@@ -172,30 +172,44 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const VB vb) {
   cx<T>* F = static_cast<cx<T>*>(a.F);
 
   // Row moments, edge pixels and the input check are done by k_row_moments.
-  // The pixels of the workgroup's next row are loaded while the current row
-  // is transformed.
+  // PF: the pixels of the workgroup's next row are loaded while the current
+  // row is transformed; without it the memory latency is left to the other
+  // workgroups on the CU (both launches use PF = true).
   const TIN* Rg = static_cast<const TIN*>(a.R);
   const TIN* Sg = static_cast<const TIN*>(a.S);
   TIN rn[MAXQ], sn[MAXQ];
+  if constexpr (PF) {
 #pragma unroll
-  for (int q = 0; q < MAXQ; ++q) {
-    const int x = threadIdx.x + q * kRowThreads;
-    const bool in = x < W && vb.x < a.H;
-    rn[q] = in ? Rg[(int64_t)vb.x * a.ld + x] : (TIN)0;
-    sn[q] = in ? Sg[(int64_t)vb.x * a.ld + x] : (TIN)0;
+    for (int q = 0; q < MAXQ; ++q) {
+      const int x = threadIdx.x + q * kRowThreads;
+      const bool in = x < W && vb.x < a.H;
+      rn[q] = in ? Rg[(int64_t)vb.x * a.ld + x] : (TIN)0;
+      sn[q] = in ? Sg[(int64_t)vb.x * a.ld + x] : (TIN)0;
+    }
   }
 
   for (int y = vb.x; y < a.H; y += vb.nx) {
     TIN rc[MAXQ], sc[MAXQ];
-    const int yl = y + vb.nx;
+    // PF: the current row was loaded one step ahead; the next one is loaded
+    // now. Otherwise the current row is loaded here.
+    const int yl = PF ? y + vb.nx : y;
 #pragma unroll
     for (int q = 0; q < MAXQ; ++q) {
-      rc[q] = rn[q];
-      sc[q] = sn[q];
+      if constexpr (PF) {
+        rc[q] = rn[q];
+        sc[q] = sn[q];
+      }
       const int x = threadIdx.x + q * kRowThreads;
       const bool in = x < W && yl < a.H;
-      rn[q] = in ? Rg[(int64_t)yl * a.ld + x] : (TIN)0;
-      sn[q] = in ? Sg[(int64_t)yl * a.ld + x] : (TIN)0;
+      const TIN rv = in ? Rg[(int64_t)yl * a.ld + x] : (TIN)0;
+      const TIN sv = in ? Sg[(int64_t)yl * a.ld + x] : (TIN)0;
+      if constexpr (PF) {
+        rn[q] = rv;
+        sn[q] = sv;
+      } else {
+        rc[q] = rv;
+        sc[q] = sv;
+      }
     }
     // transforms: real signals s_a = xt^a R' (a <= DK), s_{DK+1} = S',
     // packed two per complex transform
@@ -237,7 +251,7 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const VB vb) {
 
 template <typename T, typename TIN, int NQ, bool MIXED>
 __global__ __launch_bounds__(kRowThreads, NQ >= 16 ? 2 : 3) void k_row_pass(RowArgs a) {
-  row_pass_body<T, TIN, NQ, MIXED>(a, vb_grid());
+  row_pass_body<T, TIN, NQ, MIXED, true>(a, vb_grid());
 }
 
 template <typename T, typename TIN, int NQ, bool MIXED>
@@ -245,7 +259,7 @@ __global__ __launch_bounds__(kRowThreads, 2) void k_row_pass_batch(const RowArgs
                                                                   int n) {
   int item;
   VB vb;
-  if (batch_locate(tab, n, item, vb)) row_pass_body<T, TIN, NQ, MIXED>(args[item], vb);
+  if (batch_locate(tab, n, item, vb)) row_pass_body<T, TIN, NQ, MIXED, true>(args[item], vb);
 }
 
 // ---------------------------------------------------------------------------
