@@ -285,6 +285,15 @@ __device__ __forceinline__ void tile_mul_inplace(double (*C)[kLD], const double 
   __syncthreads();
 }
 
+// Workgroup barrier that orders LDS accesses only: unlike __syncthreads it
+// does not wait for the thread's outstanding global loads, so loads issued
+// before it stay in flight across it (their consumers wait for them).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // 1 / sqrt(d): hardware estimate refined by one Newton step (relative error
 // far below what the iterative refinement corrects)
 __device__ __forceinline__ double rsqrt64(double d) {
@@ -343,7 +352,9 @@ __device__ __forceinline__ void potrf_columns(double (*T)[kLD], double (*Ut)[kLD
 }
 
 // Rank-8 update of columns m = m0, m0 + step, ... < m1 of T and of Y with
-// block jb (all 64 rows; lane = row), two columns per iteration.
+// block jb (all 64 rows; lane = row), two columns per iteration. The wave
+// holds the block's rows of L in registers, so the multipliers L[m][j] come
+// by readlane from lane m instead of LDS broadcasts (m is wave-uniform).
 __device__ __forceinline__ void potrf_update(double (*T)[kLD], double (*Ut)[kLD], int jb, int m0, int m1,
                                              int step) {
   constexpr int kB = 8;
@@ -361,7 +372,7 @@ __device__ __forceinline__ void potrf_update(double (*T)[kLD], double (*Ut)[kLD]
     double t = T[i][m], u = Ut[i][m], t2 = T[i][m2], u2 = Ut[i][m2];
 #pragma unroll
     for (int c = 0; c < kB; ++c) {
-      const double lm = T[m][j0 + c], lm2 = T[m2][j0 + c];     // broadcasts
+      const double lm = lane_value(li[c], m), lm2 = lane_value(li[c], m2);   // L[m][j], L[m2][j]
       t = fma(-li[c], lm, t);
       u = fma(-yi[c], lm, u);
       t2 = fma(-li[c], lm2, t2);
@@ -376,7 +387,7 @@ __device__ __forceinline__ void potrf_update(double (*T)[kLD], double (*Ut)[kLD]
     double t = T[i][m], u = Ut[i][m];
 #pragma unroll
     for (int c = 0; c < kB; ++c) {
-      const double lm = T[m][j0 + c];
+      const double lm = lane_value(li[c], m);
       t = fma(-li[c], lm, t);
       u = fma(-yi[c], lm, u);
     }
@@ -394,11 +405,12 @@ __device__ __forceinline__ void potrf_update(double (*T)[kLD], double (*Ut)[kLD]
 // waves apply block jb's update to the next block's 8 columns (one each),
 // which is all the next column phase waits for.
 // `mid()` runs (in every thread) before block kMidBlock: the caller's point
-// to start global loads that complete during the rest of the sweep.
+// to start global loads that complete during the rest of the sweep (the
+// sweep's barriers order LDS only, so they do not wait for those loads).
 // A pivot that is not positive and finite is recorded (the first one) and
 // the sweep goes on with a zero scale, so values stay finite; the caller
 // discards them. Returns the failing local pivot or -1.
-constexpr int kMidBlock = 5;
+constexpr int kMidBlock = 7;
 
 template <class Mid>
 __device__ __forceinline__ int tile_potrf_aug(double (*T)[kLD], double (*Ut)[kLD], Mid&& mid) {
@@ -414,10 +426,10 @@ __device__ __forceinline__ int tile_potrf_aug(double (*T)[kLD], double (*Ut)[kLD
     const int j0 = jb * kB;
     if (w == 0) potrf_columns(T, Ut, jb, f);
     else if (jb > 0) potrf_update(T, Ut, jb - 1, j0 + kB + (w - 1), kTile, kPT / 64 - 1);
-    __syncthreads();
+    lds_barrier();
     if (jb + 1 < kNB) {
       potrf_update(T, Ut, jb, j0 + kB + w, j0 + kB + w + 1, 1);
-      __syncthreads();
+      lds_barrier();
     }
   };
   // two loops, so that registers loaded by mid() stay live across the second
@@ -701,8 +713,9 @@ __device__ __forceinline__ void solve_body(const PSArgs& a, const int bid) {
   }
   for (int k = 0; k < nt; ++k) {
     if (bid == 0) {
-      // T0: diagonal tile k with every update of steps < k. Half-way through
-      // its factorisation, once the bulk work of step k - 1 is complete, the
+      // T0: diagonal tile k with every update of steps < k. Before the last
+      // block of its factorisation, once the bulk work of step k - 1 is
+      // complete (late, so that the bulk rarely holds the chain up), the
       // two tiles of row k + 1 that the chain needs next are loaded into
       // registers (they arrive while the sweep goes on).
       if (P == 1 && k > 0) {
