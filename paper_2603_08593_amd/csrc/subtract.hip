@@ -100,7 +100,6 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
   constexpr int RW = TX + 2 * r, RH = TY + 2 * r;
   constexpr int NQ = P + 2 * r;
   __shared__ double Rt[RH][RW + 1];
-  __shared__ double cs[NK * L * L];
   __shared__ double red[2];
   const int tid = threadIdx.x;
   const int W = a.W, H = a.H;
@@ -109,8 +108,6 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
   const __attribute__((address_space(4))) double* coef =
       (const __attribute__((address_space(4))) double*)a.coef;
   const int x0 = vb.x * TX, y0 = vb.y * TY;
-  for (int i = tid; i < NK * L * L; i += 128) cs[i] = a.coef[i];
-  __syncthreads();
   // tiles whose halo stays inside the image need no periodic wrap
   const bool inner = x0 >= r && x0 + RW - r <= W && y0 >= r && y0 + RH - r <= H;
   if (inner) {
@@ -191,12 +188,18 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
       for (int p = 0; p < P; ++p) acc[p] = fma(w[p], win[p + (L - 1 - dxi)], acc[p]);
     }
   }
-  // background, difference, chi2
-  const double yto = (double)y * a.sy - 1.0;
+  // background, difference, chi2. The thread's indices are formed again
+  // here, behind an empty asm statement, so that the compiler does not keep
+  // per-pixel column indices live (spilled) across the tap loop.
+  int tid_e = tid;
+  asm volatile("" : "+v"(tid_e));
+  const int te_x = tid_e & 7, te_y = tid_e >> 3;
+  const int ye = y0 + te_y, xbe = x0 + P * te_x;
+  const double yto = (double)ye * a.sy - 1.0;
   const double* bg = a.coef + NK * L * L;
   const int DB = a.DB;
   double chi = 0.0;
-  if (y < H) {
+  if (ye < H) {
     // per-row background polynomial in xt: coefficients e_k(yt)
     double ek[5] = {0, 0, 0, 0, 0};
     {
@@ -222,19 +225,19 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
     }
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-      const int x = xb + p;
+      const int x = xbe + p;
       if (x < W) {
         const double xt = (double)x * a.sx - 1.0;
         double bgv = 0.0;
         for (int k = DB; k >= 0; --k) bgv = fma(bgv, xt, ek[k]);
-        const double sv = (double)static_cast<const TIO*>(a.S)[(int64_t)y * a.ld + x];
+        const double sv = (double)static_cast<const TIO*>(a.S)[(int64_t)ye * a.ld + x];
         const double dv = (sv - a.cS) - acc[p] - bgv;
-        static_cast<TIO*>(a.D)[(int64_t)y * a.ld + x] = (TIO)dv;
-        if (a.want_chi2 && x >= r && x < W - r && y >= r && y < H - r) {
+        static_cast<TIO*>(a.D)[(int64_t)ye * a.ld + x] = (TIO)dv;
+        if (a.want_chi2 && x >= r && x < W - r && ye >= r && ye < H - r) {
           double k2v = 0.0;
 #pragma unroll
           for (int e = 2 * DK; e >= 0; --e) k2v = fma(k2v, xt, kk[e]);
-          const double rv = Rt[ty + r][P * tx + p + r] + a.cR;
+          const double rv = Rt[te_y + r][P * te_x + p + r] + a.cR;
           const double var = fmax(sv, 1.0) + k2v * fmax(rv, 1.0);
           // 1 / var: hardware estimate and two Newton steps (var >= 1)
           double iv = __builtin_amdgcn_rcp(var);
@@ -253,8 +256,14 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
   }
 }
 
+// Four waves per SIMD (at most 128 registers) for the shapes whose kernel
+// fits in them without spilling (checked on the compiler's output: DK = 0,
+// and DK = 2 with 7 <= L <= 11); otherwise the compiler's choice
+template <int L, int DK>
+constexpr int subtract_waves() { return (DK == 0 || (DK == 2 && L >= 7 && L <= 11)) ? 4 : 1; }
+
 template <int L, int DK, typename TIO>
-__global__ __launch_bounds__(128) void k_subtract(SubArgs a) {
+__global__ __launch_bounds__(128, (subtract_waves<L, DK>())) void k_subtract(SubArgs a) {
   subtract_body<L, DK, TIO>(a, vb_grid());
 }
 
