@@ -256,9 +256,10 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
   }
 }
 
-// Four waves per SIMD (at most 128 registers) for the shapes whose kernel
-// fits in them without spilling (checked on the compiler's output: DK = 0,
-// and DK = 2 with 7 <= L <= 11); otherwise the compiler's choice
+// Four waves per SIMD (at most 128 registers) for the shapes whose kernels
+// (single-pair and batched) fit in them without spilling (checked on the
+// compiler's output: DK = 0, and DK = 2 with 7 <= L <= 11); otherwise the
+// compiler's choice
 template <int L, int DK>
 constexpr int subtract_waves() { return (DK == 0 || (DK == 2 && L >= 7 && L <= 11)) ? 4 : 1; }
 
@@ -268,7 +269,7 @@ __global__ __launch_bounds__(128, (subtract_waves<L, DK>())) void k_subtract(Sub
 }
 
 template <int L, int DK, typename TIO>
-__global__ __launch_bounds__(128) void k_subtract_batch(const SubArgs* args, const BatchTab* tab, int n) {
+__global__ __launch_bounds__(128, (subtract_waves<L, DK>())) void k_subtract_batch(const SubArgs* args, const BatchTab* tab, int n) {
   int item;
   VB vb;
   if (batch_locate(tab, n, item, vb)) subtract_body<L, DK, TIO>(args[item], vb);
