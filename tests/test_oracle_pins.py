@@ -197,3 +197,46 @@ def test_workload_cfg1_shape_and_kernel():
     assert (p.L, p.DK, p.DB) == (7, 0, 1)
     assert abs(p.a.sum() - 0.9) < 1e-12
     assert 900 < np.median(p.R) < 1100
+
+
+# 10. the single-output checkers used at full size: model_at against the
+#     tap-by-tap model image, normal_entry against the explicit design matrix,
+#     and the convolution form of the model against the same model image
+@pytest.mark.parametrize("L,DK,DB,ped", [(5, 2, 2, 0.0), (3, 1, 0, 7.5), (7, 0, 1, -2.0)])
+def test_model_at_matches_model_image(L, DK, DB, ped):
+    W, H = 36, 28
+    rng = np.random.default_rng(L + DK)
+    R = rng.normal(100, 20, (H, W))
+    th = rng.normal(0, 0.3, O.n_unknowns(L, DK, DB))
+    M = O.model_image(R, th, L, DK, DB, ref_pedestal=ped)
+    ys = np.array([0, H - 1, 0, H - 1, 3, 17, 2])
+    xs = np.array([0, W - 1, W - 1, 0, 1, 20, 34])
+    got = O.model_at(R, th, L, DK, DB, ys, xs, ref_pedestal=ped)
+    assert np.max(np.abs(got - M[ys, xs])) <= 1e-10 * np.max(np.abs(M))
+    Mc = O.model_image_conv(R, th, L, DK, DB, ref_pedestal=ped)
+    assert np.max(np.abs(Mc - M)) <= 1e-11 * np.max(np.abs(M))
+    S = rng.normal(90, 20, (H, W))
+    Dc = O.subtract_conv64(R, S, th, L, DK, DB, ped, 1.25)
+    assert np.max(np.abs(Dc - O.subtract64(R, S, th, L, DK, DB, ped, 1.25))) <= 1e-11 * np.max(np.abs(M))
+
+
+def test_model_conv_one_hot_shift():
+    """A one-hot kernel at delta = (dy, dx) moves the reference by +delta."""
+    W, H, L = 20, 16, 5
+    R = np.random.default_rng(3).normal(0, 1, (H, W))
+    th = np.zeros(O.n_unknowns(L, 0, 0))
+    th[(1 + 2) * L + (-2 + 2)] = 1.0          # dy = 1, dx = -2
+    M = O.model_image_conv(R, th, L, 0, 0)
+    assert np.array_equal(M, np.roll(R, shift=(1, -2), axis=(0, 1)))
+
+
+def test_normal_entry_matches_design_matrix():
+    W, H, L, DK = 30, 26, 5, 2
+    rng = np.random.default_rng(12)
+    R = rng.normal(50, 10, (H, W))
+    A = O.design_matrix(R, L, DK, 0, ref_pedestal=4.0)
+    G = A.T @ A
+    nk = O.n_mono(DK) * L * L
+    for row, col in [(0, 0), (nk - 1, 0), (12, 31), (60, 74), (nk - 1, nk - 1), (26, 51)]:
+        e = O.normal_entry(R, L, DK, row, col, ref_pedestal=4.0)
+        assert abs(e - G[row, col]) <= 1e-12 * np.max(np.abs(G))

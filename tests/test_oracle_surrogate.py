@@ -116,3 +116,13 @@ def test_extract_stamps_constructed():
     assert abs(out[0, 0, 4, 4] - 1.0) < 1e-15 and abs(out[0, 0].sum() - 1.0) < 1e-13
     assert abs(out[0, 1, 4, 4] - 0.5) < 1e-15
     assert np.count_nonzero(out[0, 0]) == 1
+
+
+def test_mse_loss_hand_values():
+    """Mean over every output of every pair: pred - target = [[1, -2, 0],
+    [3, 0, 2]] gives (1 + 4 + 0 + 9 + 0 + 4) / 6 = 3, gradient 2 d / 6."""
+    pred = np.array([[1.0, 0.0, 5.0], [4.0, 1.0, 2.0]])
+    target = np.array([[0.0, 2.0, 5.0], [1.0, 1.0, 0.0]])
+    loss, g = NN.mse_loss(pred, target)
+    assert loss == 3.0
+    assert np.array_equal(g, np.array([[2.0, -4.0, 0.0], [6.0, 0.0, 4.0]]) / 6.0)
