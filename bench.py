@@ -2,9 +2,14 @@
 
 A step is one pass of the whole path over one synthetic DECam-CCD-shaped
 pair (2048 x 4096 FP32 images, L = 11, DK = 2, DB = 2, N = 732 unknowns):
-sfft_build_system + sfft_solve (FP64, 2 refinement steps) + sfft_subtract
+sfft_build_system + sfft_solve (FP64, 1 refinement step) + sfft_subtract
 with the chi2 judge. Inputs are resident in HBM before the timed region.
-Prints one JSON line.
+
+The default run prints one JSON line for the plain form and adds, measured in
+the same process, the precision form (FP32 spectra), the batched form (one
+exposure of 60 CCD pairs and 40 cutouts from one HIP graph), the stamp form
+and the learned form (gated network inference with the chi2 fallback), each
+counted only when every pair it differenced ends at chi2 <= 1.05.
 """
 from __future__ import annotations
 
@@ -73,6 +78,10 @@ class HipEvents:
 # ---------------------------------------------------------------------------
 # algorithmic work per launch at this workload
 # ---------------------------------------------------------------------------
+def n_unknowns():
+    return (DK + 1) * (DK + 2) // 2 * L * L + (DB + 1) * (DB + 2) // 2
+
+
 def algorithmic_work(fp32=False):
     """Algorithmic bytes and flops per launch; fp32: the precision form's
     FP32 spectra (half the spectra bytes)."""
@@ -86,30 +95,43 @@ def algorithmic_work(fp32=False):
     nblocks = -(-H // T)
     cplx64 = 16
     cspec = 8 if fp32 else 16
+    N = n_unknowns()
     row_bytes = 2 * npix * 4 + nsig * H * nkx * cspec
     row_flops = H * (-(-nsig // 2)) * 5 * W * 11
     col_bytes = nsig * H * nkx * cspec + npairs * (2 * h + 1) * nkx * cplx64
     col_flops = nkx * (nblocks * ((2 * nk + 1) * 5 * 128 * 7 + npairs * 128 * 8) + npairs * 5 * 128 * 7)
     sub_bytes = 3 * npix * 4
     sub_flops = npix * 2 * (L * L * (DK + 1))
+    # Cholesky N^3/3, two triangular solves and one refinement step
+    # (residual product + two triangular solves): N^3/3 + 6 N^2 flops; reads G
+    solve_flops = N ** 3 // 3 + 6 * N * N
+    solve_bytes = N * N * 8 + 3 * N * 8
     return {
         "row_pass": dict(bytes=row_bytes, flops=row_flops, bound="hbm"),
         "col_pass": dict(bytes=col_bytes, flops=col_flops, bound="alu"),
+        "solve": dict(bytes=solve_bytes, flops=solve_flops, bound="mfma"),
         "subtract": dict(bytes=sub_bytes, flops=sub_flops, bound="alu"),
     }
 
 
 def roofline_entry(name, avg_s, traffic, fp32=False):
     w = algorithmic_work(fp32)[name]
+    base = {"kernel": name, "traffic": traffic, "avg_us": round(avg_s * 1e6, 2), "alg_bytes": w["bytes"],
+            "alg_flops": w["flops"]}
     if w["bound"] == "hbm":
         ach = w["bytes"] / avg_s / 1e9
-        return {"kernel": name, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "avg_us": round(avg_s * 1e6, 2), "alg_bytes": w["bytes"], "alg_flops": w["flops"]}
+        return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), **base}
     ach = w["flops"] / avg_s / 1e12
-    return {"kernel": name, "bound": "alu", "achieved": round(ach, 2), "peak": FP64_VALU_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(ach / FP64_VALU_TFLOPS, 4), "traffic": traffic,
-            "avg_us": round(avg_s * 1e6, 2), "alg_bytes": w["bytes"], "alg_flops": w["flops"]}
+    out = {"bound": w["bound"], "achieved": round(ach, 3), "peak": FP64_VALU_TFLOPS, "unit": "TFLOP/s",
+           "frac": round(ach / FP64_VALU_TFLOPS, 5), **base}
+    if name == "solve":
+        # FP64 tile products on the matrix cores (their FP64 peak equals the
+        # vector one); the kernel is bound by its chain of N dependent pivots
+        out["note"] = (f"latency-bound: {n_unknowns()} dependent pivot steps; HBM floor "
+                       f"{w['bytes'] / HBM_PEAK_GBS / 1e3:.2f} us, FP64 floor "
+                       f"{w['flops'] / FP64_VALU_TFLOPS / 1e6:.2f} us")
+    return out
 
 
 def build_roofline(build_s, fp32=False):
@@ -122,7 +144,7 @@ def build_roofline(build_s, fp32=False):
     nsig = DK + 2
     nk = (DK + 1) * (DK + 2) // 2
     npairs = nk * (nk + 1) // 2 + nk
-    N = nk * L * L + (DB + 1) * (DB + 2) // 2
+    N = n_unknowns()
     cspec = 8 if fp32 else 16
     b = (2 * npix * 4 + 2 * nsig * H * nkx * cspec + 2 * npairs * (2 * (L - 1) + 1) * nkx * 16
          + N * N * 8)
@@ -150,36 +172,116 @@ def load_traffic(kernel):
 # ---------------------------------------------------------------------------
 # CPU baseline: the FP64 oracle on a bounded sample of the same workload
 # ---------------------------------------------------------------------------
-def cpu_baseline(pair):
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return {i.get("internal_api", "?"): i.get("num_threads") for i in threadpool_info()}
+    except Exception:
+        return None
+
+
+def cpu_baseline(pair, reps=3):
+    """Median of `reps` runs of each oracle step: FFT normal equations and
+    Cholesky on the full pair, direct subtraction on a 2048 x 256 crop scaled
+    to the full height."""
+    import statistics
     import numpy as np
     import oracle as O
-    reps = 2
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        G, h = O.build_fft64(pair.R, pair.S, L, DK, DB)
-    t1 = time.perf_counter()
-    theta, _ = O.solve_cholesky64(G, h)
-    t2 = time.perf_counter()
-    rows = 1024
+    rows = 256
     Rc = np.ascontiguousarray(pair.R[:rows])
     Sc = np.ascontiguousarray(pair.S[:rows])
-    t3 = time.perf_counter()
-    O.subtract64(Rc, Sc, theta, L, DK, DB)
-    t4 = time.perf_counter()
-    build_s = (t1 - t0) / reps
-    per_pair = build_s + (t2 - t1) + (t4 - t3) * (H / rows)
-    return {"value": round(1.0 / per_pair, 5), "unit": "CCD pairs/s", "cores": len(os.sched_getaffinity(0)),
+    tb, ts, tsub = [], [], []
+    t_start = time.perf_counter()
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        G, h = O.build_fft64(pair.R, pair.S, L, DK, DB)
+        t1 = time.perf_counter()
+        theta, _ = O.solve_cholesky64(G, h, refine=1)
+        t2 = time.perf_counter()
+        O.subtract64(Rc, Sc, theta, L, DK, DB)
+        t3 = time.perf_counter()
+        tb.append(t1 - t0)
+        ts.append(t2 - t1)
+        tsub.append(t3 - t2)
+    b, s, u = statistics.median(tb), statistics.median(ts), statistics.median(tsub)
+    per_pair = b + s + u * (H / rows)
+    aff = len(os.sched_getaffinity(0))
+    return {"value": round(1.0 / per_pair, 5), "unit": "CCD pairs/s", "cores": aff,
             "kind": "oracle",
-            "sample": (f"FP64 oracle on pair 0: FFT normal equations {build_s:.2f} s (mean of {reps}) + Cholesky "
-                       f"{t2 - t1:.2f} s on the full 2048x4096 pair, direct subtraction timed on a "
-                       f"2048x{rows} crop ({t4 - t3:.2f} s) and scaled x{H // rows}"),
-            "seconds_measured": round(t4 - t0, 2)}
+            "sample": (f"FP64 oracle on the 2048x4096 pair, median of {reps}: FFT normal equations {b:.2f} s "
+                       f"and Cholesky + 1 refinement step {s:.2f} s on the full pair, direct 121-tap "
+                       f"subtraction on a 2048x{rows} crop {u:.2f} s scaled x{H // rows}"),
+            "cpu_model": _cpu_model(), "os_cpu_count": os.cpu_count(), "affinity_cpus": aff,
+            "fft_workers": os.cpu_count(), "blas_threads": _blas_threads(),
+            "seconds_measured": round(time.perf_counter() - t_start, 2)}
 
 
-def bench_batch(args):
+def _ok(info_status, chis):
+    return info_status == 0 and all(c <= 1.05 for c in chis)
+
+
+# ---------------------------------------------------------------------------
+# forms
+# ---------------------------------------------------------------------------
+def run_plain(R, S, pair, steps, warmup, compute="fp64"):
+    """Plain (FP64 build and solve) or precision (compute="fp32": FP32
+    spectra with the FP64 image means as pedestals) form on one pair."""
+    import numpy as np
+    import torch
+    import paper_2603_08593_amd as sf
+    peds = (0.0, 0.0)
+    if compute == "fp32":
+        peds = (float(np.mean(pair.R, dtype=np.float64)), float(np.mean(pair.S, dtype=np.float64)))
+    d = sf.Differencer(W, H, L, DK, DB, image_dtype="float32", compute=compute,
+                       ref_pedestal=peds[0], sci_pedestal=peds[1])
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        d.run(R, S, max_refine=1, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        d.run(R, S, max_refine=1, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    # per-kernel durations: the same steps again with the library recording
+    # HIP events around each kernel on the launch stream
+    ev = HipEvents()
+    slots = {"row_pass": 1, "col_pass": 2, "xinv": 3, "subtract": 4, "solve": 5, "build": 6}
+    evs = {k: [(ev.create(), ev.create()) for _ in range(steps)] for k in slots}
+    lib = sf.lib()
+    for k in range(steps):
+        for name, slot in slots.items():
+            a, b = evs[name][k]
+            lib.sfft_profile_events(d.handle.ptr, slot, a, b)
+        d.run(R, S, max_refine=1, stream=stream)
+    torch.cuda.synchronize()
+    for slot in slots.values():
+        lib.sfft_profile_events(d.handle.ptr, slot, None, None)
+    avg = {name: sum(ev.elapsed_ms(a, b) for a, b in evs[name]) / steps / 1e3 for name in slots}
+    ev.close()
+    info = d.info()
+    chi2 = float(d.buf.chi2.item())
+    d.close()
+    ok = _ok(info.status, [chi2])
+    return dict(value=(steps / (t1 - t0)) if ok else 0.0, ms=(t1 - t0) * 1e3 / steps, avg=avg, chi2=chi2,
+                info=info, peds=peds)
+
+
+def run_batch(steps, warmup):
     """Batched form: one exposure of 60 CCD pairs (2048x4096) and 40 uneven
-    cutouts, L in {11, 15}, FP32 spectra, every phase one launch, replayed
-    from one HIP graph; tunables from the autotuner."""
+    cutouts, L in {11, 15}, FP32 spectra with per-item FP64-mean pedestals,
+    every phase one launch, replayed from one HIP graph; tunables from the
+    autotuner."""
     import numpy as np
     import torch
     import synth.gpu as sg
@@ -195,7 +297,7 @@ def bench_batch(args):
     rpb, team = b.tune()
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             b.run_graph(stream)
     stream.synchronize()
     # phase timings on one eager run (events around each batched launch)
@@ -214,50 +316,33 @@ def bench_batch(args):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     with torch.cuda.stream(stream):
-        for _ in range(args.steps):
+        for _ in range(steps):
             b.run_graph(stream)
     stream.synchronize()
     t1 = time.perf_counter()
     chis = np.array([float(x.chi2.item()) for x in b.bufs])
     stat = [int(b.info(k).status) for k in range(len(shapes))]
+    b.close()
     ok = all(s == 0 for s in stat) and bool(np.all(chis <= 1.05))
-    t_step = (t1 - t0) / args.steps
-    out = {
-        "metric": METRIC,
-        "value": round(ccd_equiv / t_step, 3) if ok else 0.0,
-        "unit": "CCD pairs/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(t_step * 1e3, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "batched SFFT: one exposure of 60 CCD pairs 2048x4096 + 40 cutouts "
-                               "({2,3,5}-smooth 512..1536 x 512..2048), L in {11,15}, DK=2 DB=2, FP32 "
-                               "spectra, FP64 solve, one launch per phase, HIP graph",
-                   "form": "batched", "parallelism": "single GPU",
-                   "items": len(shapes), "ccd_equivalents": round(ccd_equiv, 2),
-                   "tuned_rows_per_workgroup": rpb, "tuned_solve_team": team},
-        "items_per_s": round(len(shapes) / t_step, 2),
-        "max_chi2_nu": round(float(chis.max()), 5),
-        "phase_us_eager": {k: round(v, 1) for k, v in phase.items()},
-    }
-    print(json.dumps(out), flush=True)
+    t_step = (t1 - t0) / steps
+    return dict(value=round(ccd_equiv / t_step, 3) if ok else 0.0, ms=t_step * 1e3, items=len(shapes),
+                ccd_equiv=ccd_equiv, items_per_s=len(shapes) / t_step, max_chi2=float(chis.max()),
+                rpb=rpb, team=team, phase=phase, steps=steps)
 
 
-def bench_stamps(args):
+def run_stamps(pair, R, S, steps, warmup):
     """Precision form: stamp-restricted build (64 stamps of 41 x 41, bf16 x 3
-    split products on the matrix cores) + FP64 solve + full-image subtract
-    and chi2 on the 2048x4096 pair."""
+    split products on the matrix cores, FP64 image means as pedestals) +
+    FP64 solve + full-image subtract and chi2 on the 2048x4096 pair."""
     import numpy as np
     import torch
     import synth
     import paper_2603_08593_amd as sf
-    pair = synth.make_cfg2(0)
     c = synth.pick_stamps(pair, 64, 41)
-    dev = torch.device("cuda:0")
-    R = torch.from_numpy(pair.R).to(dev)
-    S = torch.from_numpy(pair.S).to(dev)
-    C = torch.from_numpy(c).to(dev)
-    d = sf.Differencer(W, H, L, DK, DB, image_dtype="float32", stamps=(len(c), 41))
+    C = torch.from_numpy(c).to(R.device)
+    peds = (float(np.mean(pair.R, dtype=np.float64)), float(np.mean(pair.S, dtype=np.float64)))
+    d = sf.Differencer(W, H, L, DK, DB, image_dtype="float32", stamps=(len(c), 41),
+                       ref_pedestal=peds[0], sci_pedestal=peds[1])
     stream = torch.cuda.current_stream()
 
     def step():
@@ -265,129 +350,172 @@ def bench_stamps(args):
         d.solve(max_refine=1, stream=stream)
         d.subtract(R, S, stream=stream)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for _ in range(steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    # per-kernel durations: the same steps again with HIP events per kernel
     ev = HipEvents()
     slots = {"stamp_gram": 7, "solve": 5, "subtract": 4}
-    evs = {k: [(ev.create(), ev.create()) for _ in range(args.steps)] for k in slots}
+    evs = {k: [(ev.create(), ev.create()) for _ in range(steps)] for k in slots}
     lib = sf.lib()
-    for k in range(args.steps):
+    for k in range(steps):
         for name, slot in slots.items():
             lib.sfft_profile_events(d.handle.ptr, slot, evs[name][k][0], evs[name][k][1])
         step()
     torch.cuda.synchronize()
     for slot in slots.values():
         lib.sfft_profile_events(d.handle.ptr, slot, None, None)
-    avg = {n: sum(ev.elapsed_ms(a, b) for a, b in evs[n]) / args.steps / 1e3 for n in slots}
+    avg = {n: sum(ev.elapsed_ms(a, b) for a, b in evs[n]) / steps / 1e3 for n in slots}
     ev.close()
     info = d.info()
     chi2 = float(d.buf.chi2.item())
-    ok = info.status == 0 and chi2 <= 1.05
+    d.close()
+    ok = _ok(info.status, [chi2])
     K = len(c) * 41 * 41
-    N = (DK + 1) * (DK + 2) // 2 * L * L + (DB + 1) * (DB + 2) // 2
+    N = n_unknowns()
     flops = 3.0 * K * (N + 1) * (N + 2)          # upper triangle of the augmented Gram, 3 split products
     ach = flops / avg["stamp_gram"] / 1e12
-    out = {
-        "metric": METRIC,
-        "value": round(args.steps / (t1 - t0), 3) if ok else 0.0,
-        "unit": "CCD pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round((t1 - t0) * 1e3 / args.steps, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16x3", "data": "synthetic",
-        "config": {"workload": "precision form: 2048x4096 FP32 pair, 64 stamps of 41x41, L=11 DK=2 DB=2, "
-                               "bf16x3 split-product Gram on matrix cores, FP64 solve, FP64 subtract",
-                   "form": "stamps", "parallelism": "single GPU"},
-        "chi2_nu": round(chi2, 5),
-        "phase_us": {k: round(v * 1e6, 2) for k, v in avg.items()},
-        "roofline": {"kernel": "stamp_gram", "bound": "mfma", "achieved": round(ach, 2), "peak": 2500.0,
-                     "unit": "TFLOP/s", "frac": round(ach / 2500.0, 4), "traffic": None,
-                     "avg_us": round(avg["stamp_gram"] * 1e6, 2), "alg_flops": flops},
-    }
-    print(json.dumps(out), flush=True)
+    roof = {"kernel": "stamp_gram", "bound": "mfma", "achieved": round(ach, 2), "peak": 2500.0,
+            "unit": "TFLOP/s", "frac": round(ach / 2500.0, 4), "traffic": None,
+            "avg_us": round(avg["stamp_gram"] * 1e6, 2), "alg_flops": flops}
+    return dict(value=steps / (t1 - t0) if ok else 0.0, ms=(t1 - t0) * 1e3 / steps, chi2=chi2, avg=avg,
+                roofline=roof, steps=steps)
 
 
-def bench_learned(args):
+def run_learned(n_pairs, warmup, batch):
     """Learned form (gated inference) against the plain path on held-out
     pairs of the learned-form workload (seeds never used in training). Each
     pair: stamps -> bf16 network -> background refit -> subtract + chi2
-    judge (host read of chi2), full build + solve + subtract when the judge
-    rejects; the plain path runs build + solve + subtract on the same pairs.
-    The pairs are rendered into HBM before the timed loops."""
-    import numpy as np
+    judge, full build + solve + subtract when the judge rejects; the network
+    runs on `batch` pairs per launch with one host read of their chi2 values.
+    The plain path runs build + solve + subtract on the same pairs. The pairs
+    are rendered into HBM before the timed loops."""
     import torch
     import synth
     import synth.gpu as sg
-    import paper_2603_08593_amd as sf
     from paper_2603_08593_amd.learned import GatedDifferencer, load_weights
     path = os.path.join(ROOT, "paper_2603_08593_amd", "weights", "surrogate_L11_DK2_DB2.npz")
     params, std, _ = load_weights(path)
-    B = args.learned_batch
-    g = GatedDifferencer(W, H, L, DK, DB, params, std, max_pairs=B)
+    g = GatedDifferencer(W, H, L, DK, DB, params, std, max_pairs=batch)
     d = g.diff
     pairs = []
     k = 8500
-    while len(pairs) < args.steps + args.warmup:
+    while len(pairs) < n_pairs + warmup:
         pr = sg.make_learned_pair(k)
         c = synth.pick_centers(pr["xs"], pr["ys"], pr["flux"], W, H, 64, 32, 5)
         k += 1
         if len(c) < 64:
             continue
         pairs.append((pr["R"], pr["S"], torch.from_numpy(c).cuda()))
-    warm, timed = pairs[:args.warmup], pairs[args.warmup:]
+    warm, timed = pairs[:warmup], pairs[warmup:]
     for R, S, C in warm:
         g.run(R, S, C)
         d.run(R, S, max_refine=1)
-    g.run_batch(warm[:B])
+    g.run_batch(warm[:batch])
     torch.cuda.synchronize()
-    # gated, the network run on B pairs at a time (one chi2 read per batch)
     t0 = time.perf_counter()
     acc, finals = 0, []
-    for i in range(0, len(timed), B):
-        ok, _, cf = g.run_batch(timed[i:i + B])
+    for i in range(0, len(timed), batch):
+        ok, _, cf = g.run_batch(timed[i:i + batch])
         acc += sum(ok)
         finals += cf
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    plain_chi = []
     for R, S, C in timed:
         d.run(R, S, max_refine=1)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    # gated, one pair at a time (one chi2 read per pair)
-    for R, S, C in timed:
-        g.run(R, S, C)
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
+    plain_chi = []
     for R, S, C in timed:                      # chi2 of the plain path (outside the timing)
         d.run(R, S, max_refine=1)
         plain_chi.append(float(d.buf.chi2.item()))
+    d.close()
     n = len(timed)
     ok_all = max(finals) <= 1.05 and max(plain_chi) <= 1.05
     gated = n / (t1 - t0)
     plain = n / (t2 - t1)
-    out = {
-        "metric": METRIC, "value": round(gated, 3) if ok_all else 0.0, "unit": "CCD pairs/s", "n_gpus": 1,
-        "steps": n, "warmup": args.warmup, "ms_per_step": round((t1 - t0) * 1e3 / n, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f64",
-        "data": "synthetic",
+    return dict(value=gated if ok_all else 0.0, ms=(t1 - t0) * 1e3 / n, n=n, accept=acc / n,
+                max_final=max(finals), plain=plain if ok_all else 0.0, gain=gated / plain if ok_all else 0.0,
+                max_plain=max(plain_chi), batch=batch)
+
+
+# ---------------------------------------------------------------------------
+# JSON lines
+# ---------------------------------------------------------------------------
+BASE_KEYS = dict(unit="CCD pairs/s", n_gpus=1, higher_is_better=True, scaling="weak", vs_baseline=None,
+                 data="synthetic")
+
+
+def plain_line(args, res, compute, traffic_ok=True):
+    fp32 = compute == "fp32"
+    kern = {k: res["avg"][k] for k in ("row_pass", "col_pass", "solve", "subtract")}
+    dominant = max(kern, key=kern.get)
+    # the committed counters were taken on the FP64 kernels only
+    roof_all = {k: roofline_entry(k, kern[k], load_traffic(k) if (traffic_ok and not fp32) else None, fp32)
+                for k in kern}
+    info = res["info"]
+    label = ("plain SFFT, one DECam CCD pair 2048x4096 FP32, Moffat PSF, L=11 DK=2 DB=2 (N=732), FP64 "
+             "build+solve (1 refinement step), FP64-accumulated subtract") if not fp32 else \
+        ("precision form, one DECam CCD pair 2048x4096 FP32, Moffat PSF, L=11 DK=2 DB=2 (N=732), FP32 "
+         "spectra and products with FP32 accumulation, FP64 image-mean pedestals, FP64 solve "
+         "(1 refinement step), FP64-accumulated subtract")
+    return {
+        "metric": METRIC, "value": round(res["value"], 3), **BASE_KEYS, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(res["ms"], 4),
+        "dtype": "f64" if not fp32 else "f32",
+        "config": {"workload": label, "form": "plain" if not fp32 else "precision-fp32",
+                   "parallelism": "single GPU"},
+        "chi2_nu": round(res["chi2"], 5), "solve_status": int(info.status), "backward_err": info.backward_err,
+        "phase_us": {k: round(v * 1e6, 2) for k, v in res["avg"].items()},
+        "roofline": dict(roof_all[dominant]),
+        "roofline_kernels": roof_all,
+        "build_roofline": build_roofline(res["avg"]["build"], fp32),
+    }
+
+
+def batch_line(args, r):
+    return {
+        "metric": METRIC, "value": r["value"], **BASE_KEYS, "steps": r["steps"], "warmup": args.warmup,
+        "ms_per_step": round(r["ms"], 4), "dtype": "f32",
+        "config": {"workload": "batched SFFT: one exposure of 60 CCD pairs 2048x4096 + 40 cutouts "
+                               "({2,3,5}-smooth 512..1536 x 512..2048), L in {11,15}, DK=2 DB=2, FP32 "
+                               "spectra with FP64-mean pedestals, FP64 solve, one launch per phase, HIP graph",
+                   "form": "batched", "parallelism": "single GPU", "items": r["items"],
+                   "ccd_equivalents": round(r["ccd_equiv"], 2), "tuned_rows_per_workgroup": r["rpb"],
+                   "tuned_solve_team": r["team"]},
+        "items_per_s": round(r["items_per_s"], 2), "max_chi2_nu": round(r["max_chi2"], 5),
+        "phase_us_eager": {k: round(v, 1) for k, v in r["phase"].items()},
+    }
+
+
+def stamps_line(args, r):
+    return {
+        "metric": METRIC, "value": round(r["value"], 3), **BASE_KEYS, "steps": r["steps"], "warmup": args.warmup,
+        "ms_per_step": round(r["ms"], 4), "dtype": "bf16x3",
+        "config": {"workload": "precision form: 2048x4096 FP32 pair, 64 stamps of 41x41, L=11 DK=2 DB=2, "
+                               "bf16x3 split-product Gram on matrix cores with FP64-mean pedestals, FP64 solve, "
+                               "FP64 subtract", "form": "stamps", "parallelism": "single GPU"},
+        "chi2_nu": round(r["chi2"], 5), "phase_us": {k: round(v * 1e6, 2) for k, v in r["avg"].items()},
+        "roofline": r["roofline"],
+    }
+
+
+def learned_line(args, r):
+    return {
+        "metric": METRIC, "value": round(r["value"], 3), **BASE_KEYS, "steps": r["n"], "warmup": args.warmup,
+        "ms_per_step": round(r["ms"], 4), "dtype": "bf16+f64",
         "config": {"workload": "learned form: held-out 2048x4096 FP32 pairs with random PSF FWHM 2.5-6 px and "
                                "gradients, 64 star-stamp pairs of 32x32, bf16 network on batches of pairs + "
                                "background refit, chi2 judge at 1.05 with fallback to the FP64 build + solve, "
-                               "L=11 DK=2 DB=2",
-                   "form": "learned", "parallelism": "single GPU"},
-        "accept_rate": round(acc / n, 4), "max_final_chi2_nu": round(max(finals), 5),
-        "plain_pairs_per_s": round(plain, 3), "gain_vs_plain": round(gated / plain, 4),
-        "max_plain_chi2_nu": round(max(plain_chi), 5), "network_batch_pairs": B,
-        "unbatched_gated_pairs_per_s": round(n / (t3 - t2), 3),
+                               "L=11 DK=2 DB=2", "form": "learned", "parallelism": "single GPU"},
+        "accept_rate": round(r["accept"], 4), "max_final_chi2_nu": round(r["max_final"], 5),
+        "plain_pairs_per_s": round(r["plain"], 3), "gain_vs_plain": round(r["gain"], 4),
+        "max_plain_chi2_nu": round(r["max_plain"], 5), "network_batch_pairs": r["batch"],
     }
-    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -396,114 +524,72 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="plain form only (no precision/batched/learned keys)")
     ap.add_argument("--compute", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
     ap.add_argument("--form", choices=["plain", "batch", "stamps", "learned"], default="plain")
     ap.add_argument("--learned-batch", type=int, default=10, help="pairs per network launch (learned form)")
+    ap.add_argument("--learned-pairs", type=int, default=60, help="held-out pairs timed (learned form)")
+    ap.add_argument("--batch-steps", type=int, default=10, help="graph replays timed (batched form)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the path shards by CCD pair with no exchange between GPUs)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     import synth
-    import paper_2603_08593_amd as sf
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.form == "batch":
-        bench_batch(args)
+        print(json.dumps(batch_line(args, run_batch(args.steps, args.warmup))), flush=True)
         return
     if args.form == "learned":
-        return bench_learned(args)
-    if args.form == "stamps":
-        bench_stamps(args)
+        print(json.dumps(learned_line(args, run_learned(args.steps, args.warmup, args.learned_batch))), flush=True)
         return
     pair = synth.make_cfg2(0)
     dev = torch.device("cuda:0")
     R = torch.from_numpy(pair.R).to(dev)
     S = torch.from_numpy(pair.S).to(dev)
-    peds = (0.0, 0.0)
-    if args.compute == "fp32":
-        peds = (float(np.mean(pair.R, dtype=np.float64)), float(np.mean(pair.S, dtype=np.float64)))
-    d = sf.Differencer(W, H, L, DK, DB, image_dtype="float32", compute=args.compute,
-                       ref_pedestal=peds[0], sci_pedestal=peds[1])
-    stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        d.run(R, S, max_refine=1, stream=stream)
-    torch.cuda.synchronize()
-
-    # timed region: K steps, nothing else on the stream
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        d.run(R, S, max_refine=1, stream=stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-
-    # per-kernel durations: the same K steps again with the library recording
-    # HIP events around each kernel on the launch stream
-    ev = HipEvents()
-    slots = {"row_pass": 1, "col_pass": 2, "xinv": 3, "subtract": 4, "solve": 5, "build": 6}
-    evs = {k: [(ev.create(), ev.create()) for _ in range(args.steps)] for k in slots}
-    lib = sf.lib()
-    lib.sfft_profile_events.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
-    for k in range(args.steps):
-        for name, slot in slots.items():
-            a, b = evs[name][k]
-            lib.sfft_profile_events(d.handle.ptr, slot, a, b)
-        d.run(R, S, max_refine=1, stream=stream)
-    torch.cuda.synchronize()
-    for slot in slots.values():
-        lib.sfft_profile_events(d.handle.ptr, slot, None, None)
-    avg = {name: sum(ev.elapsed_ms(a, b) for a, b in evs[name]) / args.steps / 1e3 for name in slots}
-    ev.close()
-
-    info = d.info()
-    chi2 = float(d.buf.chi2.item())
-    ok = info.status == 0 and chi2 <= 1.05
-    ms = (t1 - t0) * 1e3 / args.steps
-    value = (args.steps / (t1 - t0)) if ok else 0.0
-
+    if args.form == "stamps":
+        print(json.dumps(stamps_line(args, run_stamps(pair, R, S, args.steps, args.warmup))), flush=True)
+        return
+    res = run_plain(R, S, pair, args.steps, args.warmup, args.compute)
     if args.copy_calib_mib:
         n = args.copy_calib_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-
-    kern = {k: avg[k] for k in ("row_pass", "col_pass", "subtract")}
-    dominant = max(kern, key=kern.get)
-    fp32 = args.compute == "fp32"
-    # the committed counters were taken on the FP64 kernels only
-    roof_all = {k: roofline_entry(k, kern[k], None if fp32 else load_traffic(k), fp32) for k in kern}
-    out = {
-        "metric": METRIC,
-        "value": round(value, 3),
-        "unit": "CCD pairs/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if args.compute == "fp64" else "f32",
-        "data": "synthetic",
-        "config": {"workload": "plain SFFT, one DECam CCD pair 2048x4096 FP32, Moffat PSF, "
-                               "L=11 DK=2 DB=2 (N=732), FP64 build+solve, FP64-accumulated subtract",
-                   "form": "plain" if args.compute == "fp64" else "precision-fp32",
-                   "parallelism": "single GPU"},
-        "chi2_nu": round(chi2, 5),
-        "solve_status": int(info.status),
-        "backward_err": info.backward_err,
-        "phase_us": {k: round(v * 1e6, 2) for k, v in avg.items()},
-        "roofline": {k: v for k, v in roof_all[dominant].items()},
-        "roofline_kernels": roof_all,
-        "build_roofline": build_roofline(avg["build"], fp32),
-    }
+        del src, dst
+    out = plain_line(args, res, args.compute)
+    if not args.no_forms and args.compute == "fp64":
+        ksteps = min(args.steps, 20)
+        p32 = run_plain(R, S, pair, ksteps, args.warmup, "fp32")
+        st = run_stamps(pair, R, S, ksteps, args.warmup)
+        del R, S
+        torch.cuda.empty_cache()
+        bt = run_batch(args.batch_steps, 2)
+        torch.cuda.empty_cache()
+        ln = run_learned(args.learned_pairs, 3, args.learned_batch)
+        torch.cuda.empty_cache()
+        out["precision_fp32_pairs_per_s"] = round(p32["value"], 3)
+        out["batched_ccd_equiv_per_s"] = bt["value"]
+        out["batched_items_per_s"] = round(bt["items_per_s"], 2) if bt["value"] else 0.0
+        out["stamps_pairs_per_s"] = round(st["value"], 3)
+        out["learned_pairs_per_s"] = round(ln["value"], 3)
+        out["learned_accept_rate"] = round(ln["accept"], 4)
+        out["learned_gain_vs_plain"] = round(ln["gain"], 4)
+        out["forms"] = {
+            "precision_fp32": plain_line(args, p32, "fp32"),
+            "batched": batch_line(args, bt),
+            "stamps": stamps_line(args, st),
+            "learned": learned_line(args, ln),
+        }
+        for v in out["forms"].values():
+            for k in ("metric", "unit", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data"):
+                v.pop(k, None)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pair)
     print(json.dumps(out), flush=True)

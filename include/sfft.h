@@ -206,6 +206,15 @@ sfft_status sfft_batch_tune(sfft_batch batch, void* stream, int32_t* rows_per_bl
  * (re-uploads the tables; not inside a stream capture); a captured graph is
  * discarded and captured again on the next sfft_batch_run_graph. */
 sfft_status sfft_batch_plan(sfft_batch batch, int32_t rows_per_block, int32_t team);
+/* Replaces every item's pedestals (ref_pedestals[k], sci_pedestals[k]: host
+ * arrays of the batch's item count, finite). The precision form of the
+ * build runs its FP32 spectra on R - c_R and S - c_S with c the FP64 image
+ * means (the pedestals leave the difference image unchanged up to the
+ * periodic seam rows, and keep the sky level out of the FP32 sums).
+ * Blocking (re-uploads the tables; not inside a stream capture); a captured
+ * graph is discarded. SFFT_ERR_INVALID_ARG for null or non-finite values. */
+sfft_status sfft_batch_set_pedestals(sfft_batch batch, const double* ref_pedestals,
+                                     const double* sci_pedestals);
 sfft_status sfft_batch_destroy(sfft_batch batch);
 
 /* Precision form of the build: the same least-squares problem restricted to

@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 from dataclasses import dataclass
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -106,6 +107,8 @@ _SIGS = {
     "sfft_batch_run_graph": (ctypes.c_int, [_P, _P]),
     "sfft_batch_tune": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "sfft_batch_plan": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
+    "sfft_batch_set_pedestals": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
+                                                ctypes.POINTER(ctypes.c_double)]),
     "sfft_batch_destroy": (ctypes.c_int, [_P]),
     "sfft_surrogate_num_params": (ctypes.c_int64, [ctypes.c_int32]),
     "sfft_surrogate_workspace_size": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -186,11 +189,17 @@ class Handle:
         return self._h
 
     def close(self):
+        """Release the handle's device tables now (idempotent)."""
         if self._h:
             lib().sfft_destroy(self._h)
             self._h = _P()
 
     def __del__(self):
+        # During interpreter shutdown the HIP runtime and torch's allocator may
+        # already be finalising: leave the tables to process exit rather than
+        # call into HIP from a finaliser. Explicit close() is the normal path.
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -347,6 +356,10 @@ class Differencer:
     def info(self) -> SolveInfo:
         return read_info(self.buf.info)
 
+    def close(self):
+        """Release the handle now; the torch buffers go with the object."""
+        self.handle.close()
+
 
 # ---------------------------------------------------------------------------
 # learned form
@@ -459,9 +472,12 @@ class Batch:
     def __init__(self, shapes, dk=2, db=2, max_refine=1, handle=None, device="cuda"):
         import torch
         self.torch = torch
+        self._own_handle = handle is None
         self.handle = handle or Handle()
         dev = torch.device(device)
         self.items = []
+        self.peds = [(0.0, 0.0)] * len(shapes)
+        self._peds_dirty = False
         self.bufs = []
         arr = (BatchItem * len(shapes))()
         for k, (W, H, L) in enumerate(shapes):
@@ -491,18 +507,47 @@ class Batch:
                "sfft_batch_create")
         self._b = ptr
 
-    def load(self, k, ref, sci):
-        """Copy pair k's images into the batch's resident input buffers."""
+    def load(self, k, ref, sci, pedestals=True):
+        """Copy pair k's images into the batch's resident input buffers. With
+        pedestals, the item's pedestals become the FP64 means of its two
+        images (the precision form's reading; applied before the next run)."""
         self.bufs[k].ref.copy_(ref)
         self.bufs[k].sci.copy_(sci)
+        if pedestals:
+            import math
+            t = self.torch
+            pr = float(self.bufs[k].ref.to(t.float64).mean())
+            ps = float(self.bufs[k].sci.to(t.float64).mean())
+            # a non-finite pixel makes the mean non-finite: keep 0 and let the
+            # build flag the pixel (the item then reports SFFT_ERR_NONFINITE)
+            self.peds[k] = (pr if math.isfinite(pr) else 0.0, ps if math.isfinite(ps) else 0.0)
+            self._peds_dirty = True
+
+    def set_pedestals(self, peds):
+        """peds: one (ref, sci) pair per item (sfft_batch_set_pedestals)."""
+        self.peds = [(float(a), float(b)) for a, b in peds]
+        n = len(self.peds)
+        ra = (ctypes.c_double * n)(*[p[0] for p in self.peds])
+        sa = (ctypes.c_double * n)(*[p[1] for p in self.peds])
+        _check(lib().sfft_batch_set_pedestals(self._b, ra, sa), "sfft_batch_set_pedestals")
+        for b, (pr, ps) in zip(self.bufs, self.peds):
+            b.desc.ref_pedestal, b.desc.sci_pedestal = pr, ps
+        self._peds_dirty = False
+
+    def _sync(self):
+        if self._peds_dirty:
+            self.set_pedestals(self.peds)
 
     def run(self, stream=None):
+        self._sync()
         _check(lib().sfft_batch_run(self._b, _stream_ptr(stream)), "sfft_batch_run")
 
     def run_graph(self, stream=None):
+        self._sync()
         _check(lib().sfft_batch_run_graph(self._b, _stream_ptr(stream)), "sfft_batch_run_graph")
 
     def tune(self, stream=None):
+        self._sync()
         rpb, team = ctypes.c_int32(), ctypes.c_int32()
         _check(lib().sfft_batch_tune(self._b, _stream_ptr(stream), ctypes.byref(rpb), ctypes.byref(team)),
                "sfft_batch_tune")
@@ -516,11 +561,16 @@ class Batch:
         return read_info(self.bufs[k].info)
 
     def close(self):
+        """Destroy the batch (tables, captured graph) and its handle if owned."""
         if getattr(self, "_b", None):
             lib().sfft_batch_destroy(self._b)
             self._b = None
+        if getattr(self, "_own_handle", False):
+            self.handle.close()
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

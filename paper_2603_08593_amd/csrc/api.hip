@@ -642,6 +642,21 @@ sfft_status sfft_batch_plan(sfft_batch b, int32_t rows_per_block, int32_t team) 
   return batch_plan(b, rows_per_block, team);
 }
 
+sfft_status sfft_batch_set_pedestals(sfft_batch b, const double* ref_pedestals, const double* sci_pedestals) {
+  if (!b || !ref_pedestals || !sci_pedestals) return SFFT_ERR_INVALID_ARG;
+  const int n = (int)b->items.size();
+  for (int k = 0; k < n; ++k)
+    if (!std::isfinite(ref_pedestals[k]) || !std::isfinite(sci_pedestals[k])) return SFFT_ERR_INVALID_ARG;
+  sfft_status s;
+  if ((s = check_device(b->handle)) != SFFT_OK) return s;
+  if (hipDeviceSynchronize() != hipSuccess) return SFFT_ERR_HIP;   // tables in use by queued work
+  for (int k = 0; k < n; ++k) {
+    b->items[k].desc.ref_pedestal = ref_pedestals[k];
+    b->items[k].desc.sci_pedestal = sci_pedestals[k];
+  }
+  return batch_plan(b, b->rows_per_block, b->team);
+}
+
 sfft_status sfft_batch_destroy(sfft_batch b) {
   if (!b) return SFFT_ERR_INVALID_ARG;
   batch_release(b);

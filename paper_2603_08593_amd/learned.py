@@ -52,6 +52,30 @@ def load_weights(path):
     return z["params"], Standardizer(z["mean"], z["scale"]), meta
 
 
+def save_checkpoint(path, net: Surrogate, std: Standardizer | None = None, **meta):
+    """Training state for resuming: parameters, both Adam moment vectors and
+    the step count (copied from the device after a synchronisation)."""
+    net.torch.cuda.synchronize()
+    extra = {} if std is None else dict(mean=std.mean, scale=std.scale)
+    np.savez(path, params=net.params.cpu().numpy(), adam_m=net.m.cpu().numpy(), adam_v=net.v.cpu().numpy(),
+             step=np.int64(net.step), **extra, **{k: np.asarray(v) for k, v in meta.items()})
+
+
+def load_checkpoint(path, net: Surrogate):
+    """Restores the state written by save_checkpoint into `net` (same n_out);
+    returns the Standardizer when the checkpoint holds one."""
+    z = np.load(path, allow_pickle=False)
+    t = net.torch
+    for name in ("params", "adam_m", "adam_v"):
+        if z[name].shape != (net.params.numel(),):
+            raise ValueError(f"checkpoint {name} has {z[name].shape}, network needs {net.params.numel()}")
+    net.params.copy_(t.from_numpy(z["params"]).to(net.params.device))
+    net.m.copy_(t.from_numpy(z["adam_m"]).to(net.m.device))
+    net.v.copy_(t.from_numpy(z["adam_v"]).to(net.v.device))
+    net.step = int(z["step"])
+    return Standardizer(z["mean"], z["scale"]) if "mean" in z.files else None
+
+
 def train(net: Surrogate, stamps, pos, targets, *, epochs: int, batch: int, lr: float, seed: int = 0,
           lr_final: float | None = None, log=None):
     """Adam on mini-batches of pairs. stamps (N, S, 2, 32, 32), pos (N, S, 2),

@@ -1,7 +1,8 @@
 """GPU parity of the batched form: a batch of unequal pairs (different
 sizes, {2,3,5}-smooth widths, L = 11 and 15) run in one launch per phase
 must give the same results as each pair run alone through the single-pair
-calls with the same precision (FP32 spectra, FP64 solve), and the same
+calls with the same precision (FP32 spectra, FP64 solve) and pedestals (each
+item's FP64 image means), and the same
 again when replayed from a captured HIP graph (several replays, with eager
 work and synchronisations between them) and after autotuning.
 
@@ -39,9 +40,10 @@ def _pairs():
     return out
 
 
-def _single(p, torch, sf):
+def _single(p, torch, sf, peds):
     H, W = p.R.shape
-    d = sf.Differencer(W, H, p.L, 2, 2, image_dtype="float32", compute="fp32")
+    d = sf.Differencer(W, H, p.L, 2, 2, image_dtype="float32", compute="fp32",
+                       ref_pedestal=peds[0], sci_pedestal=peds[1])
     d.run(torch.from_numpy(p.R).cuda(), torch.from_numpy(p.S).cuda(), max_refine=1)
     torch.cuda.synchronize()
     return d.buf.coef.cpu().numpy(), float(d.buf.chi2.item()), d.buf.diff.cpu().numpy()
@@ -63,10 +65,10 @@ def _check(b, refs, tag):
 def test_batch_matches_single_pairs_eager_graph_and_tuned():
     torch, sf = _torch(), _sf()
     pairs = _pairs()
-    refs = [_single(p, torch, sf) for p in pairs]
     b = sf.Batch(SHAPES, dk=2, db=2, max_refine=1)
     for k, p in enumerate(pairs):
         b.load(k, torch.from_numpy(p.R).cuda(), torch.from_numpy(p.S).cuda())
+    refs = [_single(p, torch, sf, b.peds[k]) for k, p in enumerate(pairs)]
     b.run()
     torch.cuda.synchronize()
     _check(b, refs, "eager")
@@ -97,10 +99,10 @@ def test_batch_fixed_plans_small_solve_teams():
     role has a single workgroup; odd row-pass blockings."""
     torch, sf = _torch(), _sf()
     pairs = _pairs()
-    refs = [_single(p, torch, sf) for p in pairs]
     b = sf.Batch(SHAPES, dk=2, db=2, max_refine=1)
     for k, p in enumerate(pairs):
         b.load(k, torch.from_numpy(p.R).cuda(), torch.from_numpy(p.S).cuda())
+    refs = [_single(p, torch, sf, b.peds[k]) for k, p in enumerate(pairs)]
     for rpb, team in [(1, 1), (3, 2), (16, 3), (4, 0)]:
         b.plan(rpb, team)
         for k in range(len(SHAPES)):
@@ -122,3 +124,33 @@ def test_batch_rejects_unsupported():
     with pytest.raises(sf.SfftError) as e:
         sf.Batch([(4096, 64, 5)], dk=2, db=2)          # width > 2048
     assert e.value.status == sf.SFFT_ERR_UNSUPPORTED
+
+
+def test_bad_items_do_not_poison_the_batch():
+    """An item with a NaN pixel reports SFFT_ERR_NONFINITE and an item whose
+    reference is constant (zero after its pedestal) reports SFFT_ERR_NOT_SPD;
+    the other items of the same launches give the results they give alone."""
+    torch, sf = _torch(), _sf()
+    pairs = _pairs()
+    bad_nan = pairs[1].R.copy()
+    bad_nan[17, 33] = np.nan
+    bad_const = np.full_like(pairs[3].R, 1234.0)
+    b = sf.Batch(SHAPES, dk=2, db=2, max_refine=1)
+    for k, p in enumerate(pairs):
+        R = bad_nan if k == 1 else (bad_const if k == 3 else p.R)
+        b.load(k, torch.from_numpy(np.ascontiguousarray(R)).cuda(), torch.from_numpy(p.S).cuda())
+    good = [0, 2, 4]
+    refs = {k: _single(pairs[k], torch, sf, b.peds[k]) for k in good}
+    b.run()
+    torch.cuda.synchronize()
+    assert b.info(1).status == sf.SFFT_ERR_NONFINITE
+    assert b.info(3).status == sf.SFFT_ERR_NOT_SPD and b.info(3).failed_pivot >= 0
+    assert np.all(np.isnan(b.bufs[3].coef.cpu().numpy()))
+    for k in good:
+        coef, chi2, D = refs[k]
+        assert b.info(k).status == 0
+        got = b.bufs[k].coef.cpu().numpy()
+        print(f"  good item {k}: bitwise {np.array_equal(got, coef)}", flush=True)
+        assert np.linalg.norm(got - coef) <= 1e-12 * np.linalg.norm(coef)
+        assert abs(float(b.bufs[k].chi2.item()) - chi2) <= 1e-12 * chi2
+    b.close()

@@ -57,3 +57,72 @@ def test_trained_network_gain_over_trivial_predictor():
     assert res["accept_net"] >= 0.6
     assert res["accept_net"] > res["accept_trivial"]
     assert res["median_chi2_net"] < res["median_chi2_trivial"]
+
+
+def _tiny_batch(torch, B=4, n_out=732, seed=5):
+    rng = np.random.default_rng(seed)
+    X = torch.from_numpy(rng.normal(0, 1, (B, 64, 2, 32, 32)).astype(np.float32)).cuda()
+    P = torch.from_numpy(rng.uniform(-1, 1, (B, 64, 2)).astype(np.float32)).cuda()
+    T = torch.from_numpy(rng.normal(0, 1, (B, n_out)).astype(np.float32)).cuda()
+    return X, P, T
+
+
+def test_checkpoint_resume_is_bitwise(tmp_path):
+    """Training 6 steps straight equals 3 steps, a checkpoint (parameters,
+    Adam moments, step), a fresh network restored from it, and 3 more steps."""
+    import torch
+    import paper_2603_08593_amd as sf
+    from paper_2603_08593_amd.learned import load_checkpoint, save_checkpoint
+    X, P, T = _tiny_batch(torch)
+    init = synth.surrogate_init(732, 11)
+    a = sf.Surrogate(init, 732, n_stamps=64, max_pairs=4)
+    for _ in range(6):
+        a.train_step(X, P, T, 4, 1e-3)
+    b = sf.Surrogate(init, 732, n_stamps=64, max_pairs=4)
+    for _ in range(3):
+        b.train_step(X, P, T, 4, 1e-3)
+    path = str(tmp_path / "ckpt.npz")
+    save_checkpoint(path, b)
+    c = sf.Surrogate(np.zeros_like(init), 732, n_stamps=64, max_pairs=4)
+    load_checkpoint(path, c)
+    assert c.step == 3
+    for _ in range(3):
+        c.train_step(X, P, T, 4, 1e-3)
+    torch.cuda.synchronize()
+    assert torch.equal(a.params, c.params) and torch.equal(a.m, c.m) and torch.equal(a.v, c.v)
+    assert c.step == a.step == 6
+
+
+def _gated_pair(torch):
+    import synth.gpu as sg
+    pr = sg.make_learned_pair(9100)
+    cen = synth.pick_centers(pr["xs"], pr["ys"], pr["flux"], 2048, 4096, 64, 32, 5)
+    assert len(cen) == 64
+    return pr["R"], pr["S"], torch.from_numpy(cen).cuda()
+
+
+def test_gated_fallback_threshold_zero_and_corrupt_weights():
+    """Threshold 0 rejects every prediction, and a NaN output-layer bias
+    gives a NaN chi2 that the judge rejects: both end with the plain fit's own
+    difference image (the same chi2 as the plain path on the pair)."""
+    import torch
+    import paper_2603_08593_amd as sf
+    from paper_2603_08593_amd.learned import GatedDifferencer, load_weights
+    params, std, _ = load_weights(WEIGHTS)
+    R, S, C = _gated_pair(torch)
+    plain = sf.Differencer(2048, 4096, 11, 2, 2, image_dtype="float32")
+    plain.run(R, S, max_refine=1)
+    chi_plain = float(plain.buf.chi2.item())
+    g0 = GatedDifferencer(2048, 4096, 11, 2, 2, params, std, threshold=0.0)
+    acc, chi_pred, chi_final = g0.run(R, S, C)
+    print(f"  threshold 0: accepted {acc}, prediction chi2 {chi_pred:.4f}, final {chi_final:.6f} "
+          f"(plain {chi_plain:.6f})", flush=True)
+    assert not acc and chi_final == chi_plain
+    bad = params.copy()
+    bad[-732:] = np.nan                      # the output layer's bias
+    g1 = GatedDifferencer(2048, 4096, 11, 2, 2, bad, std)
+    acc, chi_pred, chi_final = g1.run(R, S, C)
+    print(f"  corrupt weights: accepted {acc}, prediction chi2 {chi_pred}, final {chi_final:.6f}", flush=True)
+    assert not acc and not np.isfinite(chi_pred) and chi_final == chi_plain
+    for o in (plain, g0.diff, g1.diff):
+        o.close()

@@ -190,8 +190,8 @@ def test_cfg2_full_size_sampled():
     torch = _torch()
     sf = _sf()
     p = synth.make_cfg2()
-    _say("cfg2 2048x4096 FP32 L=11 DK=2 DB=2 (sampled checks)")
-    g = _run_gpu(p)
+    _say("cfg2 2048x4096 FP32 L=11 DK=2 DB=2 (sampled checks), max_refine=1")
+    g = _run_gpu(p, refine=1)
     assert g["info"].status == 0
     G_o, h_o = O.build_fft64(p.R, p.S, 11, 2, 2)
     th_o, _ = O.solve_cholesky64(G_o, h_o)
