@@ -331,8 +331,9 @@ def run_batch(steps, warmup):
 
 
 def run_stamps(pair, R, S, steps, warmup):
-    """Precision form: stamp-restricted build (64 stamps of 41 x 41, bf16 x 3
-    split products on the matrix cores, FP64 image means as pedestals) +
+    """Precision form: stamp-restricted build (64 stamps of 41 x 41, FP32
+    operands split into three bfloat16 terms, six term products per operand
+    pair on the matrix cores, FP64 image means as pedestals) +
     FP64 solve + full-image subtract and chi2 on the 2048x4096 pair."""
     import numpy as np
     import torch
@@ -377,7 +378,7 @@ def run_stamps(pair, R, S, steps, warmup):
     ok = _ok(info.status, [chi2])
     K = len(c) * 41 * 41
     N = n_unknowns()
-    flops = 3.0 * K * (N + 1) * (N + 2)          # upper triangle of the augmented Gram, 3 split products
+    flops = 6.0 * K * (N + 1) * (N + 2)          # upper triangle of the augmented Gram, 6 split-term products
     ach = flops / avg["stamp_gram"] / 1e12
     roof = {"kernel": "stamp_gram", "bound": "mfma", "achieved": round(ach, 2), "peak": 2500.0,
             "unit": "TFLOP/s", "frac": round(ach / 2500.0, 4), "traffic": None,
@@ -495,9 +496,10 @@ def batch_line(args, r):
 def stamps_line(args, r):
     return {
         "metric": METRIC, "value": round(r["value"], 3), **BASE_KEYS, "steps": r["steps"], "warmup": args.warmup,
-        "ms_per_step": round(r["ms"], 4), "dtype": "bf16x3",
+        "ms_per_step": round(r["ms"], 4), "dtype": "bf16x6",
         "config": {"workload": "precision form: 2048x4096 FP32 pair, 64 stamps of 41x41, L=11 DK=2 DB=2, "
-                               "bf16x3 split-product Gram on matrix cores with FP64-mean pedestals, FP64 solve, "
+                               "split-product Gram on matrix cores (three bf16 terms per FP32 operand, six term "
+                               "products, FP32 runs flushed to FP64) with FP64-mean pedestals, FP64 solve, "
                                "FP64 subtract", "form": "stamps", "parallelism": "single GPU"},
         "chi2_nu": round(r["chi2"], 5), "phase_us": {k: round(v * 1e6, 2) for k, v in r["avg"].items()},
         "roofline": r["roofline"],

@@ -222,16 +222,19 @@ sfft_status sfft_batch_destroy(sfft_batch batch);
  * star pixels (the star-stamp mode of SFFT, paper Sec. 1 and Sec. 2.3.2),
  * with periodic indexing as above. Writes G_s = A_s^T A_s and h_s = A_s^T S'
  * where A_s holds the design rows of the stamp pixels. The Gram sums run on
- * the matrix cores: each operand is rounded to FP32 and split as
- * hi = bf16(a), lo = bf16(a - hi) (round to nearest even), each product is
- * taken as hi*hi + hi*lo + lo*hi, accumulated in FP32 within a workgroup's
- * share of the stamps and in FP64 across shares (relative error per entry
- * about 2^-15 of the sum of absolute products).
+ * the matrix cores: each operand is rounded to FP32 and split exactly into
+ * three bfloat16 terms, hi = bf16(a), mid = bf16(a - hi),
+ * lo = bf16(a - hi - mid) (round to nearest even), each product is taken as
+ * the six term products of order <= 2 (hi*hi, hi*mid, mid*hi, hi*lo, lo*hi,
+ * mid*mid; the dropped ones are below 2^-23 of |a b|), accumulated in FP32
+ * over runs of at most 8 x 32 stamp pixels and in FP64 beyond them (relative
+ * error per entry a few 2^-24 of the sum of absolute products).
  *   centers : device int32[n_stamps][2] = (x, y) stamp centre pixels
  *   size    : odd, 1..127, <= min(W, H); n_stamps in [1, 65536]
  *   G, h    : device, as for sfft_build_system
- *   ws      : device workspace of at least sfft_stamps_workspace_size bytes;
- *             it also serves sfft_solve and sfft_subtract for this descriptor
+ *   ws      : device workspace of at least sfft_stamps_workspace_size bytes
+ *             (partial tiles and the split planes of every stamp); it also
+ *             serves sfft_solve and sfft_subtract for this descriptor
  * SFFT_ERR_UNSUPPORTED when the planes a Gram tile reads do not fit in LDS
  * (large stamps with DB = 4). Non-finite pixels near the stamps are flagged
  * in ws for sfft_solve. The compute field of desc is ignored. */

@@ -395,9 +395,9 @@ def normal_entry(R, L, DK, row, col, ref_pedestal=0.0) -> float:
 # square stamps of side `size` centred on the given pixels (periodic
 # indexing). Its normal equations are the Gram sums G_s = A_s^T A_s,
 # h_s = A_s^T S'_s. The precision form evaluates these sums on matrix cores
-# with each FP32 operand split into two bfloat16 halves; stamp_normal_split
-# gives the exact value of that split-product sum (before any FP32
-# accumulation rounding), and bf16_rne / split_bf16 define the split.
+# with each FP32 operand split into bfloat16 terms; stamp_normal_split gives
+# the exact value of that split-product sum (before any FP32 accumulation
+# rounding), and bf16_rne / split_bf16 / split_bf16_3 define the splits.
 
 
 def stamp_pixels(W: int, H: int, centers, size: int):
@@ -455,20 +455,50 @@ def split_bf16(a):
     return hi, lo
 
 
-def stamp_normal_split(R, S, centers, size, L, DK, DB, ref_pedestal=0.0, sci_pedestal=0.0):
+def split_bf16_3(a):
+    """a (FP32) = hi + mid + lo with hi = bf16(a), mid = bf16(a - hi),
+    lo = bf16(a - hi - mid). Both differences are exact in FP32, and the
+    decomposition itself is exact whenever |a| >= 2^-100: a - hi is a whole
+    number of units in the last place of a below 2^15, a - hi - mid one below
+    2^7, which 8 significant bits hold."""
+    a = np.asarray(a, dtype=np.float32)
+    hi = bf16_rne(a)
+    r1 = a - hi
+    mid = bf16_rne(r1)
+    lo = bf16_rne(r1 - mid)
+    return hi, mid, lo
+
+
+def split_product_terms(terms: int):
+    """Index pairs (s, t) of the split terms kept in a product a*b: with two
+    terms per operand (hi, lo) hi*hi + hi*lo + lo*hi; with three
+    (hi, mid, lo) every pair of total order s + t <= 2: hi*hi, hi*mid,
+    mid*hi, hi*lo, lo*hi, mid*mid."""
+    if terms == 2:
+        return [(0, 0), (0, 1), (1, 0)]
+    if terms == 3:
+        return [(0, 0), (0, 1), (1, 0), (0, 2), (2, 0), (1, 1)]
+    raise ValueError("terms must be 2 or 3")
+
+
+def stamp_normal_split(R, S, centers, size, L, DK, DB, ref_pedestal=0.0, sci_pedestal=0.0, terms=3):
     """The Gram sums the split-product form computes, evaluated exactly:
     every design value and stamp value is first rounded to FP32, split into
-    (hi, lo), and each product a*b is replaced by hi_a hi_b + hi_a lo_b +
-    lo_a hi_b (the lo*lo term is dropped); all sums in FP64 (exact products).
+    `terms` bfloat16 terms, and each product a*b is replaced by the term
+    products of split_product_terms; all sums in FP64 (exact products).
     Returns (G, h)."""
     A = stamp_design(R, centers, size, L, DK, DB, ref_pedestal).astype(np.float32)
     _, Sp = _prep(R, S, ref_pedestal, sci_pedestal)
     ys, xs = stamp_pixels(Sp.shape[1], Sp.shape[0], centers, size)
     s = Sp[ys, xs].astype(np.float32)
-    Ah, Al = (t.astype(np.float64) for t in split_bf16(A))
-    sh, sl = (t.astype(np.float64) for t in split_bf16(s))
-    G = Ah.T @ Ah + Ah.T @ Al + Al.T @ Ah
-    h = Ah.T @ sh + Ah.T @ sl + Al.T @ sh
+    split = split_bf16 if terms == 2 else split_bf16_3
+    As = [t.astype(np.float64) for t in split(A)]
+    ss = [t.astype(np.float64) for t in split(s)]
+    G = np.zeros((A.shape[1], A.shape[1]))
+    h = np.zeros(A.shape[1])
+    for p, q in split_product_terms(terms):
+        G += As[p].T @ As[q]
+        h += As[p].T @ ss[q]
     return G, h
 
 

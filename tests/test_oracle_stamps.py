@@ -100,15 +100,72 @@ def test_split_error_bounds():
     assert np.all(np.abs(prod - a64 * b64) <= 3 * 2.0 ** -16 * np.abs(a64 * b64))
 
 
-# The split-product Gram is the exact Gram up to the split bound.
+# The two-term split-product Gram is the exact Gram up to the split bound.
 def test_split_gram_within_split_bound():
     W, H, L, DK, DB = 96, 64, 5, 2, 1
     p = synth.make_pair(W, H, L, DK, DB, seed=21, nstars=30, source="noisy", dtype=np.float32)
     c = [(20, 20), (70, 40), (50, 10)]
     G, h = O.stamp_normal64(p.R, p.S, c, 13, L, DK, DB)
-    Gs, hs = O.stamp_normal_split(p.R, p.S, c, 13, L, DK, DB)
+    Gs, hs = O.stamp_normal_split(p.R, p.S, c, 13, L, DK, DB, terms=2)
     Ga, ha = O.stamp_abs_gram(p.R, p.S, c, 13, L, DK, DB)
     # FP32 rounding of each operand (2^-24 each) plus the split (3 * 2^-16)
     tol = 3 * 2.0 ** -16 + 3 * 2.0 ** -24
     assert np.all(np.abs(Gs - G) <= tol * Ga)
     assert np.all(np.abs(hs - h) <= tol * ha)
+
+
+# Three-term split on hand-checked values: (1 + 2^-10 + 2^-19) keeps its
+# three bits in three terms; (1 + 2^-8 + 2^-9) rounds hi up and leaves a
+# negative mid.
+@pytest.mark.parametrize("x,want", [
+    (1.0 + 2.0 ** -10 + 2.0 ** -19, (1.0, 2.0 ** -10, 2.0 ** -19)),
+    (1.0 + 2.0 ** -8 + 2.0 ** -9, (1.0 + 2.0 ** -7, -(2.0 ** -9), 0.0)),
+    (-3.0, (-3.0, 0.0, 0.0)),
+    (1.0 + 2.0 ** -23, (1.0, 2.0 ** -23, 0.0)),
+])
+def test_split3_worked_values(x, want):
+    got = tuple(float(t) for t in O.split_bf16_3(np.float32(x)))
+    assert got == want
+
+
+def test_split3_is_exact_and_products_within_bound():
+    rng = np.random.default_rng(1)
+    a = (rng.standard_normal(50000) * np.exp(rng.uniform(-40, 40, 50000))).astype(np.float32)
+    b = (rng.standard_normal(50000) * np.exp(rng.uniform(-40, 40, 50000))).astype(np.float32)
+    parts_a = O.split_bf16_3(a)
+    parts_b = O.split_bf16_3(b)
+    for t in parts_a + parts_b:
+        assert not np.any(t.view(np.uint32) & 0xFFFF)          # bfloat16 values
+    a64, b64 = a.astype(np.float64), b.astype(np.float64)
+    A = [t.astype(np.float64) for t in parts_a]
+    B = [t.astype(np.float64) for t in parts_b]
+    assert np.array_equal(A[0] + A[1] + A[2], a64)              # exact decomposition
+    assert np.array_equal(B[0] + B[1] + B[2], b64)
+    # kept: every term pair of order <= 2; dropped: mid*lo, lo*mid, lo*lo,
+    # each below 2^-24 |ab|
+    prod = sum(A[p] * B[q] for p, q in O.split_product_terms(3))
+    assert np.all(np.abs(prod - a64 * b64) <= 2.0 ** -23 * np.abs(a64 * b64))
+    # the two-term form is coarser: its products sit near 2^-16
+    A2 = [t.astype(np.float64) for t in O.split_bf16(a)]
+    B2 = [t.astype(np.float64) for t in O.split_bf16(b)]
+    prod2 = sum(A2[p] * B2[q] for p, q in O.split_product_terms(2))
+    assert np.max(np.abs(prod2 - a64 * b64) / np.abs(a64 * b64)) > 2.0 ** -20
+
+
+# The three-term split Gram is the exact Gram up to the operands' FP32
+# rounding (2^-24 each) and the dropped term products (2^-23).
+def test_split3_gram_within_bound():
+    W, H, L, DK, DB = 96, 64, 5, 2, 1
+    p = synth.make_pair(W, H, L, DK, DB, seed=21, nstars=30, source="noisy", dtype=np.float32)
+    c = [(20, 20), (70, 40), (50, 10)]
+    G, h = O.stamp_normal64(p.R, p.S, c, 13, L, DK, DB)
+    Gs, hs = O.stamp_normal_split(p.R, p.S, c, 13, L, DK, DB, terms=3)
+    Ga, ha = O.stamp_abs_gram(p.R, p.S, c, 13, L, DK, DB)
+    tol = 2.0 ** -23 + 3 * 2.0 ** -24
+    assert np.all(np.abs(Gs - G) <= tol * Ga)
+    assert np.all(np.abs(hs - h) <= tol * ha)
+    # a planted error in the kept terms (mid*mid dropped) breaks the bound
+    A = O.stamp_design(p.R, c, 13, L, DK, DB).astype(np.float32)
+    Ah, Am, Al = (t.astype(np.float64) for t in O.split_bf16_3(A))
+    Gbad = Ah.T @ Ah + Ah.T @ Am + Am.T @ Ah + Ah.T @ Al + Al.T @ Ah
+    assert np.any(np.abs(Gbad - G) > tol * Ga)
