@@ -156,6 +156,19 @@ sfft_status sfft_subtract(sfft_handle handle, const sfft_desc* desc,
                           void* diff, double* chi2,
                           void* ws, size_t ws_bytes, void* stream);
 
+/* sfft_subtract without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation). The chi2 partial sums and kappa2 coefficients live in
+ * a fixed library-owned device array (one per GPU, about 0.5 MB, held until
+ * the process ends); the call allocates nothing. Limit: at most 65536 output
+ * tiles of 64 x 16 pixels (ceil(W/64) * ceil(H/16) <= 65536, e.g. 4096 x
+ * 16384), else SFFT_ERR_WORKSPACE. Calls that overlap on one GPU share the
+ * array and race (order them on one stream). Results are identical to
+ * sfft_subtract's. */
+sfft_status sfft_subtract_noalloc(sfft_handle handle, const sfft_desc* desc,
+                                  const void* ref, const void* sci, const double* coef,
+                                  void* diff, double* chi2, void* stream);
+
 /* ---- Batched form ------------------------------------------------------
  * All pairs of an exposure (equal-size CCDs and uneven cutouts, possibly
  * different L) differenced together: every phase of build, solve and

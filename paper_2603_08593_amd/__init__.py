@@ -94,6 +94,7 @@ _SIGS = {
     "sfft_solve": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, ctypes.c_int32, _P, _P,
                                   ctypes.c_size_t, _P]),
     "sfft_subtract": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "sfft_subtract_noalloc": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, _P, _P, _P]),
     "sfft_refit_background": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, _P, _P, _P, ctypes.c_size_t,
                                              _P]),
     "sfft_stamps_workspace_size": (ctypes.c_int, [_P, ctypes.POINTER(Desc), ctypes.c_int32, ctypes.c_int32,
@@ -238,6 +239,12 @@ def sfft_subtract(handle: Handle, desc: Desc, ref, sci, coef, diff, chi2, ws, st
     _check(lib().sfft_subtract(handle.ptr, ctypes.byref(desc), _dp(ref), _dp(sci), _dp(coef), _dp(diff),
                                _dp(chi2), _dp(ws), ws.numel() * ws.element_size(), _stream_ptr(stream)),
            "sfft_subtract")
+
+
+def sfft_subtract_noalloc(handle: Handle, desc: Desc, ref, sci, coef, diff, chi2, stream=None):
+    _check(lib().sfft_subtract_noalloc(handle.ptr, ctypes.byref(desc), _dp(ref), _dp(sci), _dp(coef), _dp(diff),
+                                       _dp(chi2), _stream_ptr(stream)),
+           "sfft_subtract_noalloc")
 
 
 def sfft_stamps_workspace_size(handle: Handle, desc: Desc, n_stamps: int, size: int) -> int:

@@ -29,6 +29,10 @@ hipError_t launch_solve(const sfft_desc& d, const double* G, const double* h, do
 hipError_t launch_subtract(const sfft_desc& d, const void* R, const void* S, const double* coef,
                            void* D, double* chi2, unsigned char* ws, const Prof* pf,
                            hipStream_t st);
+hipError_t noalloc_prepare(int device);
+int noalloc_max_partials();
+hipError_t launch_subtract_noalloc(int device, const sfft_desc& d, const void* R, const void* S,
+                                   const double* coef, void* D, double* chi2, hipStream_t st);
 hipError_t launch_stamps(const sfft_desc& d, const void* R, const void* S, const int32_t* centers,
                          int nst, int size, double* G, double* hv, unsigned char* ws, int num_cus,
                          const Prof* pf, hipStream_t st);
@@ -192,6 +196,11 @@ sfft_status sfft_create(sfft_handle* out) {
     (void)hipGetLastError();
     return SFFT_ERR_HIP;
   }
+  // device address of the allocation-free subtract's scratch array, once per device
+  if (noalloc_prepare(dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return SFFT_ERR_HIP;
+  }
   sfft_handle h = new (std::nothrow) sfft_handle_s();
   if (!h) return SFFT_ERR_INTERNAL;
   h->device = dev;
@@ -272,6 +281,19 @@ sfft_status sfft_subtract(sfft_handle h, const sfft_desc* d, const void* ref, co
   const hipError_t e = launch_subtract(*d, ref, sci, coef, diff, chi2,
                                        static_cast<unsigned char*>(ws), &h->prof,
                                        static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
+}
+
+sfft_status sfft_subtract_noalloc(sfft_handle h, const sfft_desc* d, const void* ref, const void* sci,
+                                  const double* coef, void* diff, double* chi2, void* stream) {
+  if (!h) return SFFT_ERR_INVALID_ARG;
+  sfft_status s = validate_core(d);
+  if (s != SFFT_OK) return s;
+  if (!ref || !sci || !coef || !diff || diff == ref || diff == sci) return SFFT_ERR_INVALID_ARG;
+  if (subtract_blocks(make_geometry(*d)) > noalloc_max_partials()) return SFFT_ERR_WORKSPACE;
+  if ((s = check_device(h)) != SFFT_OK) return s;
+  const hipError_t e = launch_subtract_noalloc(h->device, *d, ref, sci, coef, diff, chi2,
+                                               static_cast<hipStream_t>(stream));
   return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
 }
 

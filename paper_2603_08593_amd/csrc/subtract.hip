@@ -11,6 +11,7 @@
 // polynomial depends on the coefficients only: a one-workgroup kernel forms
 // it once per launch.
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -303,13 +304,12 @@ static hipError_t launch_sub_l(const SubArgs& a, int DK, bool f32, dim3 grid, hi
 }
 
 static SubArgs make_sub_args(const sfft_desc& d, const void* R, const void* S, const double* coef, void* D,
-                             bool want_chi2, unsigned char* ws) {
+                             bool want_chi2, double* partials, double* k2) {
   const Geometry g = make_geometry(d);
-  const Layout l = make_layout(g);
   SubArgs a{};
   a.R = R; a.S = S; a.D = D; a.ld = d.ld; a.coef = coef;
-  a.partials = reinterpret_cast<double*>(ws + l.partials);
-  a.k2 = reinterpret_cast<double*>(ws + l.k2);
+  a.partials = partials;
+  a.k2 = k2;
   a.W = g.W; a.H = g.H; a.N = g.N; a.DB = g.DB; a.want_chi2 = want_chi2; a.L = g.L; a.DK = g.DK;
   a.cR = d.ref_pedestal; a.cS = d.sci_pedestal;
   a.sx = g.W > 1 ? 2.0 / (double)(g.W - 1) : 0.0;
@@ -327,7 +327,9 @@ hipError_t launch_subtract(const sfft_desc& d, const void* R, const void* S, con
                            hipStream_t st) {
   const Geometry g = make_geometry(d);
   const Layout l = make_layout(g);
-  const SubArgs a = make_sub_args(d, R, S, coef, D, chi2 != nullptr, ws);
+  const SubArgs a = make_sub_args(d, R, S, coef, D, chi2 != nullptr,
+                                  reinterpret_cast<double*>(ws + l.partials),
+                                  reinterpret_cast<double*>(ws + l.k2));
   hipError_t e;
   const dim3 grid((g.W + kSubTX - 1) / kSubTX, (g.H + kSubTY - 1) / kSubTY);
   const bool f32 = d.image_dtype == SFFT_F32;
@@ -352,6 +354,75 @@ hipError_t launch_subtract(const sfft_desc& d, const void* R, const void* S, con
   if (chi2) {
     hipLaunchKernelGGL(k_chi2_final, dim3(1), dim3(1024), 0, st,
                        (const double*)a.partials, l.npartials, chi2_dof(g), chi2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// ---- allocation-free subtract ---------------------------------------------
+// For callers that cannot allocate (code under stream capture, serving loops):
+// the chi2 partial sums and the kappa2 coefficients live in this file-scope
+// device array instead of a caller workspace. Each device holds its own copy;
+// its address is looked up once per device (sfft_create, with the device
+// current) and only that address is used on the host. Calls on one device
+// share the array, so calls that overlap on one device race; every call
+// rewrites all the entries it reads (one partial per output tile, the kappa2
+// coefficients), so nothing needs clearing between calls.
+constexpr int kNoAllocMaxPartials = 1 << 16;   // 64 x 16 tiles: up to 2^26 pixels
+constexpr int kNoAllocK2 = 128;
+constexpr int kNoAllocMaxDevices = 64;
+static __device__ __align__(256) double scratch[kNoAllocMaxPartials + kNoAllocK2];
+static double* g_noalloc_ptr[kNoAllocMaxDevices] = {};
+static std::mutex g_noalloc_mu;
+
+hipError_t noalloc_prepare(int device) {
+  if (device < 0 || device >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (g_noalloc_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_noalloc_ptr[device] = static_cast<double*>(ptr);
+  return hipSuccess;
+}
+
+int noalloc_max_partials() { return kNoAllocMaxPartials; }
+
+hipError_t launch_subtract_noalloc(int device, const sfft_desc& d, const void* R, const void* S,
+                                   const double* coef, void* D, double* chi2, hipStream_t st) {
+  if (device < 0 || device >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+  double* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    base = g_noalloc_ptr[device];
+  }
+  if (!base) return hipErrorNotInitialized;
+  const Geometry g = make_geometry(d);
+  const int np = subtract_blocks(g);
+  if (np > kNoAllocMaxPartials) return hipErrorInvalidValue;
+  const SubArgs a = make_sub_args(d, R, S, coef, D, chi2 != nullptr, base, base + kNoAllocMaxPartials);
+  hipError_t e;
+  const dim3 grid((g.W + kSubTX - 1) / kSubTX, (g.H + kSubTY - 1) / kSubTY);
+  const bool f32 = d.image_dtype == SFFT_F32;
+  if (chi2) {
+    hipLaunchKernelGGL(k_kappa2, dim3(1), dim3(kK2Threads), 0, st, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  switch (g.L) {
+    case 1: e = launch_sub_l<1>(a, g.DK, f32, grid, st); break;
+    case 3: e = launch_sub_l<3>(a, g.DK, f32, grid, st); break;
+    case 5: e = launch_sub_l<5>(a, g.DK, f32, grid, st); break;
+    case 7: e = launch_sub_l<7>(a, g.DK, f32, grid, st); break;
+    case 9: e = launch_sub_l<9>(a, g.DK, f32, grid, st); break;
+    case 11: e = launch_sub_l<11>(a, g.DK, f32, grid, st); break;
+    case 13: e = launch_sub_l<13>(a, g.DK, f32, grid, st); break;
+    case 15: e = launch_sub_l<15>(a, g.DK, f32, grid, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  if (chi2) {
+    hipLaunchKernelGGL(k_chi2_final, dim3(1), dim3(1024), 0, st, (const double*)a.partials, np,
+                       chi2_dof(g), chi2);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
@@ -414,14 +485,16 @@ SubBatch* sub_batch_create(const SubItem* items, int n, hipError_t* err) {
       b->tabs.emplace_back();
       b->blocks.push_back(0);
     }
-    b->args[slot].push_back(make_sub_args(it.d, it.R, it.S, it.coef, it.D, true, it.ws));
+    const Layout l = make_layout(g);
+    b->args[slot].push_back(make_sub_args(it.d, it.R, it.S, it.coef, it.D, true,
+                                          reinterpret_cast<double*>(it.ws + l.partials),
+                                          reinterpret_cast<double*>(it.ws + l.k2)));
     BatchTab t{};
     t.start = b->blocks[slot];
     t.nx = (g.W + kSubTX - 1) / kSubTX;
     t.ny = (g.H + kSubTY - 1) / kSubTY;
     b->tabs[slot].push_back(t);
     b->blocks[slot] += t.nx * t.ny;
-    const Layout l = make_layout(g);
     Chi2Item c{};
     c.partials = reinterpret_cast<const double*>(it.ws + l.partials);
     c.out = it.chi2;
