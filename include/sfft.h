@@ -274,6 +274,81 @@ sfft_status sfft_refit_background(sfft_handle handle, const sfft_desc* desc, con
                                   const void* sci, double* coef, double* G, double* h,
                                   void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Multi-template differencing -----------------------------------------
+ * Paper Sec. 2.3.2 (image differencing) with the multi-exposure template set
+ * of Sec. 2.2.1 (N_TEMP templates, default 5): the science image is
+ * differenced against each template separately, every difference image is
+ * brought to one common photometric zero point and the stack is
+ * median-combined pixel by pixel. A difference image with zero point zp[t]
+ * is scaled by 10^(0.4 (zp_common - zp[t])) (magnitudes m = zp - 2.5
+ * log10(flux)); the median of an even count is the mean of the two middle
+ * values; a NaN in any input gives NaN. At most SFFT_MAX_TEMPLATES images. */
+#define SFFT_MAX_TEMPLATES 16
+
+/* out = median_t( scale_t * diffs[t] ). diffs: host array of n device
+ * pointers to W x H images (image_dtype, pitch ld of desc; only width,
+ * height, ld and image_dtype are used); zp: host array of n zero points;
+ * out: device image of the same layout (may alias none of the inputs). */
+sfft_status sfft_median_combine(sfft_handle handle, const sfft_desc* desc, const void* const* diffs,
+                                int32_t n, const double* zp, double zp_common, void* out,
+                                void* stream);
+
+/* The whole multi-template path for one science image: for each template t,
+ * sfft_build_system (reference refs[t], pedestal ref_pedestals[t] when that
+ * host array is non-NULL, else desc's), sfft_solve (max_refine steps) and
+ * sfft_subtract into diffs[t] with its chi2, then sfft_median_combine into
+ * `combined`. The science image's row spectrum and row moments are computed
+ * by the first template's build and reused by the others (when the
+ * workspace layout keeps them across the solve; otherwise every build takes
+ * them again). All templates share desc's L, DK, DB, compute and science
+ * pedestal.
+ *   refs, diffs : host arrays of n device image pointers (diffs written)
+ *   G, h        : device scratch, N*N and N doubles (hold the last template's system)
+ *   coefs       : device, n*N doubles (template t at t*N)
+ *   infos       : device, n sfft_solve_info; chi2s: device, n doubles
+ *   combined    : device image (written)
+ *   ws          : device workspace of at least sfft_workspace_size(desc) bytes
+ * Errors as for the single-pair calls; n outside [1, SFFT_MAX_TEMPLATES]
+ * or aliased outputs: SFFT_ERR_INVALID_ARG. */
+sfft_status sfft_difference_multi(sfft_handle handle, const sfft_desc* desc, const void* const* refs,
+                                  const void* sci, int32_t n, const double* ref_pedestals,
+                                  const double* zp, double zp_common, int32_t max_refine,
+                                  double* G, double* h, double* coefs, sfft_solve_info* infos,
+                                  double* chi2s, void* const* diffs, void* combined,
+                                  void* ws, size_t ws_bytes, void* stream);
+
+/* ---- Aperture photometry on difference images ---------------------------
+ * Paper Sec. 2.3.3 (differential photometry: aperture fluxes at random
+ * background positions give the 5-sigma limiting magnitude) and Sec. 2.4.3
+ * (forced aperture photometry at fixed positions). The flux in a circle of
+ * `radius` pixels (0 < radius <= 64) centred on (x, y) is the sum over pixels
+ * of the pixel value times the exact area of the pixel square
+ * [px - 1/2, px + 1/2] x [py - 1/2, py + 1/2] inside the circle (pixel
+ * centres at integer coordinates; pixels outside the image contribute
+ * nothing), accumulated in FP64. Only width, height, ld and image_dtype of
+ * desc are used. xy: device double[n][2] = (x, y); 1 <= n <= 2^24. */
+sfft_status sfft_aperture_flux(sfft_handle handle, const sfft_desc* desc, const void* image,
+                               const double* xy, int32_t n, double radius, double* flux,
+                               void* stream);
+
+/* Aperture fluxes at n >= 2 background positions (written to flux, device
+ * double[n]) and result (device double[3]) = {sigma, m_lim, mean flux}:
+ * sigma = sample standard deviation of the fluxes (n - 1 in the
+ * denominator), m_lim = zp - 2.5 log10(nsigma * sigma) (nsigma = 5 for the
+ * paper's 5-sigma limit). */
+sfft_status sfft_limiting_magnitude(sfft_handle handle, const sfft_desc* desc, const void* image,
+                                    const double* xy, int32_t n, double radius, double zp,
+                                    double nsigma, double* flux, double* result, void* stream);
+
+/* Forced photometry: flux (device double[n]); mag (nullable) = zp - 2.5
+ * log10(flux), NaN for flux <= 0; mag_err (nullable; needs sigma, a device
+ * scalar such as result[0] of sfft_limiting_magnitude) = (2.5 / ln 10)
+ * sigma / |flux|, NaN for flux == 0. */
+sfft_status sfft_forced_photometry(sfft_handle handle, const sfft_desc* desc, const void* image,
+                                   const double* xy, int32_t n, double radius, double zp,
+                                   const double* sigma, double* flux, double* mag, double* mag_err,
+                                   void* stream);
+
 /* ---- Learned form ------------------------------------------------------
  * A small convolutional network predicts the kernel and background
  * coefficients of the fit from star-stamp pairs, so that a pair whose

@@ -94,6 +94,18 @@ _SIGS = {
     "sfft_solve": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, ctypes.c_int32, _P, _P,
                                   ctypes.c_size_t, _P]),
     "sfft_subtract": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "sfft_median_combine": (ctypes.c_int, [_P, ctypes.POINTER(Desc), ctypes.POINTER(_P), ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_double), ctypes.c_double, _P, _P]),
+    "sfft_difference_multi": (ctypes.c_int, [_P, ctypes.POINTER(Desc), ctypes.POINTER(_P), _P, ctypes.c_int32,
+                                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                             ctypes.c_double, ctypes.c_int32, _P, _P, _P, _P, _P,
+                                             ctypes.POINTER(_P), _P, _P, ctypes.c_size_t, _P]),
+    "sfft_aperture_flux": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, ctypes.c_int32, ctypes.c_double, _P,
+                                          _P]),
+    "sfft_limiting_magnitude": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, ctypes.c_int32, ctypes.c_double,
+                                               ctypes.c_double, ctypes.c_double, _P, _P, _P]),
+    "sfft_forced_photometry": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, ctypes.c_int32, ctypes.c_double,
+                                              ctypes.c_double, _P, _P, _P, _P, _P]),
     "sfft_subtract_noalloc": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, _P, _P, _P]),
     "sfft_refit_background": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, _P, _P, _P, ctypes.c_size_t,
                                              _P]),
@@ -195,11 +207,13 @@ class Handle:
             lib().sfft_destroy(self._h)
             self._h = _P()
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # During interpreter shutdown the HIP runtime and torch's allocator may
         # already be finalising: leave the tables to process exit rather than
         # call into HIP from a finaliser. Explicit close() is the normal path.
-        if sys.is_finalizing():
+        # (The check is bound at definition: module globals such as `sys` may
+        # already be cleared when a finaliser runs at shutdown.)
+        if _finalizing():
             return
         try:
             self.close()
@@ -365,6 +379,111 @@ class Differencer:
 
     def close(self):
         """Release the handle now; the torch buffers go with the object."""
+        self.handle.close()
+
+
+# ---------------------------------------------------------------------------
+# multi-template differencing and aperture photometry
+# ---------------------------------------------------------------------------
+
+MAX_TEMPLATES = 16
+
+
+def _ptr_array(ts):
+    return (_P * len(ts))(*[_P(t.data_ptr()) for t in ts])
+
+
+def _dbl_array(v):
+    v = [float(x) for x in v]
+    return (ctypes.c_double * len(v))(*v)
+
+
+def image_desc(img) -> Desc:
+    """Descriptor of a 2-D torch image for the photometry and combine calls
+    (only width, height, pitch and element type are used)."""
+    import torch
+    H, W = img.shape
+    dt = SFFT_F32 if img.dtype == torch.float32 else SFFT_F64
+    return make_desc(W, H, 1, 0, 0, ld=img.stride(0), image_dtype=dt)
+
+
+def sfft_median_combine(handle: Handle, desc: Desc, diffs, zps, zp_common, out, stream=None):
+    _check(lib().sfft_median_combine(handle.ptr, ctypes.byref(desc), _ptr_array(diffs), len(diffs),
+                                     _dbl_array(zps), float(zp_common), _dp(out), _stream_ptr(stream)),
+           "sfft_median_combine")
+
+
+def sfft_difference_multi(handle: Handle, desc: Desc, refs, sci, zps, zp_common, G, h, coefs, infos, chi2s,
+                          diffs, combined, ws, max_refine=2, ref_pedestals=None, stream=None):
+    peds = None if ref_pedestals is None else _dbl_array(ref_pedestals)
+    _check(lib().sfft_difference_multi(handle.ptr, ctypes.byref(desc), _ptr_array(refs), _dp(sci), len(refs), peds,
+                                       _dbl_array(zps), float(zp_common), int(max_refine), _dp(G), _dp(h),
+                                       _dp(coefs), _dp(infos), _dp(chi2s), _ptr_array(diffs), _dp(combined),
+                                       _dp(ws), ws.numel() * ws.element_size(), _stream_ptr(stream)),
+           "sfft_difference_multi")
+
+
+def sfft_aperture_flux(handle: Handle, desc: Desc, image, xy, radius, flux, stream=None):
+    _check(lib().sfft_aperture_flux(handle.ptr, ctypes.byref(desc), _dp(image), _dp(xy), int(xy.shape[0]),
+                                    float(radius), _dp(flux), _stream_ptr(stream)), "sfft_aperture_flux")
+
+
+def sfft_limiting_magnitude(handle: Handle, desc: Desc, image, xy, radius, zp, flux, result, nsigma=5.0,
+                            stream=None):
+    _check(lib().sfft_limiting_magnitude(handle.ptr, ctypes.byref(desc), _dp(image), _dp(xy), int(xy.shape[0]),
+                                         float(radius), float(zp), float(nsigma), _dp(flux), _dp(result),
+                                         _stream_ptr(stream)), "sfft_limiting_magnitude")
+
+
+def sfft_forced_photometry(handle: Handle, desc: Desc, image, xy, radius, zp, sigma, flux, mag=None, mag_err=None,
+                           stream=None):
+    _check(lib().sfft_forced_photometry(handle.ptr, ctypes.byref(desc), _dp(image), _dp(xy), int(xy.shape[0]),
+                                        float(radius), float(zp), _dp(sigma), _dp(flux), _dp(mag), _dp(mag_err),
+                                        _stream_ptr(stream)), "sfft_forced_photometry")
+
+
+class MultiDifferencer:
+    """One science image against n templates (sfft_difference_multi): every
+    difference image, its coefficients, solve info and chi2, and the
+    zero-point-normalised median combine, in caller-owned torch buffers."""
+
+    def __init__(self, width, height, L, dk, db, n_templates, *, image_dtype="float32", compute="fp64",
+                 sci_pedestal=0.0, device="cuda"):
+        import torch
+        self.torch = torch
+        self.dtype = torch.float32 if image_dtype in ("float32", torch.float32) else torch.float64
+        self.desc = make_desc(width, height, L, dk, db,
+                              image_dtype=SFFT_F32 if self.dtype == torch.float32 else SFFT_F64,
+                              compute=SFFT_COMPUTE_FP32 if compute == "fp32" else SFFT_COMPUTE_FP64,
+                              sci_pedestal=sci_pedestal)
+        st = sfft_validate(self.desc)
+        if st != SFFT_OK:
+            raise SfftError(st, "sfft_validate")
+        self.handle = Handle()
+        self.n = int(n_templates)
+        self.N = N = sfft_num_unknowns(self.desc)
+        dev = torch.device(device)
+        nbytes = sfft_workspace_size(self.handle, self.desc)
+        self.G = torch.empty((N, N), dtype=torch.float64, device=dev)
+        self.h = torch.empty((N,), dtype=torch.float64, device=dev)
+        self.coefs = torch.empty((self.n, N), dtype=torch.float64, device=dev)
+        self.infos = torch.zeros((self.n, SOLVE_INFO_BYTES), dtype=torch.uint8, device=dev)
+        self.chi2s = torch.zeros((self.n,), dtype=torch.float64, device=dev)
+        self.diffs = [torch.empty((height, width), dtype=self.dtype, device=dev) for _ in range(self.n)]
+        self.combined = torch.empty((height, width), dtype=self.dtype, device=dev)
+        self.ws = torch.empty((nbytes + 255) // 256 * 256, dtype=torch.uint8, device=dev)
+
+    def run(self, refs, sci, zps, zp_common, max_refine=2, ref_pedestals=None, stream=None):
+        assert len(refs) == self.n
+        sfft_difference_multi(self.handle, self.desc, refs, sci, zps, zp_common, self.G, self.h, self.coefs,
+                              self.infos, self.chi2s, self.diffs, self.combined, self.ws, max_refine,
+                              ref_pedestals, stream)
+        return self.combined
+
+    def info(self, t) -> SolveInfo:
+        return read_info(self.infos[t])
+
+    def close(self):
         self.handle.close()
 
 
@@ -575,8 +694,8 @@ class Batch:
         if getattr(self, "_own_handle", False):
             self.handle.close()
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.close()

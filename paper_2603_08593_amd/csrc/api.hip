@@ -18,11 +18,14 @@
 #include "batch.hpp"
 #include "stamps.hpp"
 #include "surrogate.hpp"
+#include "products.hpp"
 
 namespace sfft {
 
 hipError_t launch_build(const sfft_desc& d, const void* R, const void* S, double* G, double* hv,
-                        unsigned char* ws, const BuildPlan& p, const Prof* pf, hipStream_t st);
+                        unsigned char* ws, const BuildPlan& p, const Prof* pf, hipStream_t st,
+                        bool reuse_sci = false);
+bool sci_reusable(const sfft_desc& d);
 hipError_t launch_solve(const sfft_desc& d, const double* G, const double* h, double* coef,
                         int max_refine, sfft_solve_info* info, unsigned char* ws, int num_cus,
                         const Prof* pf, hipStream_t st);
@@ -358,6 +361,133 @@ sfft_status sfft_refit_background(sfft_handle h, const sfft_desc* d, const void*
   BuildPlan p{nullptr, nullptr, nullptr, h->num_cus};
   const hipError_t e = launch_bg_refit(*d, ref, sci, coef, G, hv, static_cast<unsigned char*>(ws), p,
                                        static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
+}
+
+// ---- multi-template differencing and photometry ---------------------------
+
+static sfft_status validate_image(const sfft_desc* d) {
+  if (!d) return SFFT_ERR_INVALID_ARG;
+  if (d->width < 1 || d->height < 1 || d->ld < d->width) return SFFT_ERR_INVALID_ARG;
+  if (d->image_dtype != SFFT_F32 && d->image_dtype != SFFT_F64) return SFFT_ERR_INVALID_ARG;
+  if ((int64_t)d->height * d->ld > ((int64_t)1 << 40)) return SFFT_ERR_UNSUPPORTED;
+  return SFFT_OK;
+}
+
+static bool zp_ok(const double* zp, int n, double zp_common) {
+  if (!zp || !std::isfinite(zp_common)) return false;
+  for (int t = 0; t < n; ++t)
+    if (!std::isfinite(zp[t])) return false;
+  return true;
+}
+
+static CombineArgs make_combine(const sfft_desc& d, const void* const* diffs, int n, const double* zp,
+                                double zp_common, void* out) {
+  CombineArgs a{};
+  for (int t = 0; t < n; ++t) {
+    a.D[t] = diffs[t];
+    a.scale[t] = std::pow(10.0, 0.4 * (zp_common - zp[t]));
+  }
+  a.out = out;
+  a.ld = d.ld;
+  a.W = d.width;
+  a.H = d.height;
+  return a;
+}
+
+sfft_status sfft_median_combine(sfft_handle h, const sfft_desc* d, const void* const* diffs, int32_t n,
+                                const double* zp, double zp_common, void* out, void* stream) {
+  if (!h) return SFFT_ERR_INVALID_ARG;
+  sfft_status s = validate_image(d);
+  if (s != SFFT_OK) return s;
+  if (!diffs || !out || n < 1 || n > kMaxTemplates || !zp_ok(zp, n, zp_common)) return SFFT_ERR_INVALID_ARG;
+  for (int t = 0; t < n; ++t)
+    if (!diffs[t]) return SFFT_ERR_INVALID_ARG;
+  if ((s = check_device(h)) != SFFT_OK) return s;
+  const CombineArgs a = make_combine(*d, diffs, n, zp, zp_common, out);
+  const hipError_t e = launch_median_combine(a, n, d->image_dtype == SFFT_F32, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
+}
+
+sfft_status sfft_difference_multi(sfft_handle h, const sfft_desc* d, const void* const* refs, const void* sci,
+                                  int32_t n, const double* ref_pedestals, const double* zp, double zp_common,
+                                  int32_t max_refine, double* G, double* hv, double* coefs,
+                                  sfft_solve_info* infos, double* chi2s, void* const* diffs, void* combined,
+                                  void* ws, size_t ws_bytes, void* stream) {
+  if (!h) return SFFT_ERR_INVALID_ARG;
+  sfft_status s = sfft_validate(d);
+  if (s != SFFT_OK) return s;
+  if (!refs || !sci || !G || !hv || !coefs || !infos || !chi2s || !diffs || !combined) return SFFT_ERR_INVALID_ARG;
+  if (n < 1 || n > kMaxTemplates || max_refine < 0 || max_refine > 8 || !zp_ok(zp, n, zp_common))
+    return SFFT_ERR_INVALID_ARG;
+  for (int t = 0; t < n; ++t) {
+    if (!refs[t] || !diffs[t] || diffs[t] == sci || diffs[t] == combined) return SFFT_ERR_INVALID_ARG;
+    if (ref_pedestals && !std::isfinite(ref_pedestals[t])) return SFFT_ERR_INVALID_ARG;
+    for (int u = 0; u < n; ++u)
+      if (diffs[t] == refs[u] || (u != t && diffs[t] == diffs[u])) return SFFT_ERR_INVALID_ARG;
+  }
+  if (combined == sci) return SFFT_ERR_INVALID_ARG;
+  if ((s = check_ws(ws, ws_bytes, make_layout(make_geometry(*d)).total)) != SFFT_OK) return s;
+  if ((s = check_device(h)) != SFFT_OK) return s;
+  Twiddles tw, t128;
+  if (get_twiddles(h, d->width, tw) != hipSuccess) return SFFT_ERR_HIP;
+  if (get_twiddles(h, kTP, t128) != hipSuccess) return SFFT_ERR_HIP;
+  const bool f32 = d->compute == SFFT_COMPUTE_FP32;
+  const BuildPlan p{f32 ? tw.w32 : tw.w64, tw.w64, f32 ? t128.w32 : t128.w64, h->num_cus};
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  const int64_t N = sfft_num_unknowns(d);
+  // the science image's row spectrum and moments are computed once, by the
+  // first template's build, when they survive the solve and subtract
+  const bool reuse = sci_reusable(*d);
+  for (int t = 0; t < n; ++t) {
+    sfft_desc dt = *d;
+    if (ref_pedestals) dt.ref_pedestal = ref_pedestals[t];
+    hipError_t e = launch_build(dt, refs[t], sci, G, hv, w, p, &h->prof, st, reuse && t > 0);
+    if (e == hipSuccess)
+      e = launch_solve(dt, G, hv, coefs + t * N, max_refine, infos + t, w, h->num_cus, &h->prof, st);
+    if (e == hipSuccess)
+      e = launch_subtract(dt, refs[t], sci, coefs + t * N, diffs[t], chi2s + t, w, &h->prof, st);
+    if (e != hipSuccess) return SFFT_ERR_HIP;
+  }
+  const CombineArgs a = make_combine(*d, diffs, n, zp, zp_common, combined);
+  const hipError_t e = launch_median_combine(a, n, d->image_dtype == SFFT_F32, st);
+  return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
+}
+
+static bool ap_args_ok(const double* xy, int32_t n, double radius) {
+  return xy && n >= 1 && n <= (1 << 24) && std::isfinite(radius) && radius > 0.0 && radius <= 64.0;
+}
+
+sfft_status sfft_aperture_flux(sfft_handle h, const sfft_desc* d, const void* image, const double* xy, int32_t n,
+                               double radius, double* flux, void* stream) {
+  return sfft_forced_photometry(h, d, image, xy, n, radius, 0.0, nullptr, flux, nullptr, nullptr, stream);
+}
+
+sfft_status sfft_forced_photometry(sfft_handle h, const sfft_desc* d, const void* image, const double* xy,
+                                   int32_t n, double radius, double zp, const double* sigma, double* flux,
+                                   double* mag, double* mag_err, void* stream) {
+  if (!h) return SFFT_ERR_INVALID_ARG;
+  sfft_status s = validate_image(d);
+  if (s != SFFT_OK) return s;
+  if (!image || !flux || !ap_args_ok(xy, n, radius) || !std::isfinite(zp)) return SFFT_ERR_INVALID_ARG;
+  if (mag_err && !sigma) return SFFT_ERR_INVALID_ARG;
+  if ((s = check_device(h)) != SFFT_OK) return s;
+  ApArgs a{};
+  a.img = image; a.ld = d->ld; a.W = d->width; a.H = d->height; a.xy = xy; a.n = n; a.radius = radius;
+  a.flux = flux; a.mag = mag; a.mag_err = mag_err; a.sigma = sigma; a.zp = zp;
+  const hipError_t e = launch_aperture(a, d->image_dtype == SFFT_F32, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
+}
+
+sfft_status sfft_limiting_magnitude(sfft_handle h, const sfft_desc* d, const void* image, const double* xy,
+                                    int32_t n, double radius, double zp, double nsigma, double* flux,
+                                    double* result, void* stream) {
+  if (!h) return SFFT_ERR_INVALID_ARG;
+  if (n < 2 || !result || !std::isfinite(nsigma) || !(nsigma > 0.0)) return SFFT_ERR_INVALID_ARG;
+  sfft_status s = sfft_forced_photometry(h, d, image, xy, n, radius, zp, nullptr, flux, nullptr, nullptr, stream);
+  if (s != SFFT_OK) return s;
+  const hipError_t e = launch_limiting_mag(flux, n, zp, nsigma, result, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
 }
 

@@ -37,6 +37,15 @@ __global__ void k_fill_i32(int* p, int n, int v) {
   if (i < n) p[i] = v;
 }
 
+// Clears the flag words of a build that reuses the science image's spectra
+// and moments from an earlier build in the same workspace: the science
+// image's non-finite bit (kNonfiniteSci) of word 0 is kept, since that image
+// is not read again.
+__global__ void k_clear_flags_keep_sci(int* p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (i == 0) ? (p[0] & kNonfiniteSci) : 0;
+}
+
 __device__ __forceinline__ double ipow(double x, int n) {
   double r = 1.0;
   for (int k = 0; k < n; ++k) r *= x;
@@ -154,6 +163,8 @@ struct RowArgs {
   int* flags;
   const void* twW;    // cx<T>[W]
   double* edge;       // [nsig][2][H]: real k_x = 0 and k_x = W/2 values
+  int sci;            // 1: transform S' and take its moments; 0: they are
+                      // already in the workspace (a second template)
 };
 
 // NQ: row elements per thread, max(1, ceil(W / 256)); MIXED: W has factors 3 or 5
@@ -168,7 +179,8 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const VB vb) {
   for (int i = threadIdx.x; i < 64; i += kRowThreads) twl[i] = twg[i < W ? i : 0];
   for (int i = threadIdx.x; 64 * i < W; i += kRowThreads) twh[i] = twg[64 * i];
   constexpr int MAXQ = NQ;
-  const int nsig = a.DK + 2;
+  // signals transformed: xt^a R' (a <= DK), then S' unless it is reused
+  const int nsig = a.DK + 1 + a.sci;
   cx<T>* F = static_cast<cx<T>*>(a.F);
 
   // Row moments, edge pixels and the input check are done by k_row_moments.
@@ -184,7 +196,7 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const VB vb) {
       const int x = threadIdx.x + q * kRowThreads;
       const bool in = x < W && vb.x < a.H;
       rn[q] = in ? Rg[(int64_t)vb.x * a.ld + x] : (TIN)0;
-      sn[q] = in ? Sg[(int64_t)vb.x * a.ld + x] : (TIN)0;
+      sn[q] = (in && a.sci) ? Sg[(int64_t)vb.x * a.ld + x] : (TIN)0;
     }
   }
 
@@ -202,7 +214,7 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const VB vb) {
       const int x = threadIdx.x + q * kRowThreads;
       const bool in = x < W && yl < a.H;
       const TIN rv = in ? Rg[(int64_t)yl * a.ld + x] : (TIN)0;
-      const TIN sv = in ? Sg[(int64_t)yl * a.ld + x] : (TIN)0;
+      const TIN sv = (in && a.sci) ? Sg[(int64_t)yl * a.ld + x] : (TIN)0;
       if constexpr (PF) {
         rn[q] = rv;
         sn[q] = sv;
@@ -957,9 +969,10 @@ __device__ __forceinline__ void row_moments_body(const RowArgs& a, const VB vb) 
   for (int m = 0; m < kMR; ++m) mr[m] = 0.0;
 #pragma unroll
   for (int m = 0; m < kMS; ++m) ms[m] = 0.0;
-  bool bad = false;
+  bool bad_r = false, bad_s = false;
   auto accumulate = [&](int x, double rv, double sv) {
-    bad |= !(is_finite_d(rv) && is_finite_d(sv));
+    bad_r |= !is_finite_d(rv);
+    bad_s |= !is_finite_d(sv);
     const double xt = (double)x * a.sx - 1.0;
     double pw = 1.0;
 #pragma unroll
@@ -980,6 +993,9 @@ __device__ __forceinline__ void row_moments_body(const RowArgs& a, const VB vb) 
   if (y < a.H) {
     const TIN* Rr = static_cast<const TIN*>(a.R) + (int64_t)y * a.ld;
     const TIN* Sr = static_cast<const TIN*>(a.S) + (int64_t)y * a.ld;
+    // with a.sci == 0 the science image is not read (its moments are kept
+    // from an earlier build): its pixels enter as zeros and MS is not written
+    const bool sci = a.sci != 0;
     const bool vec = sizeof(TIN) == 4 && ((reinterpret_cast<uintptr_t>(Rr) | reinterpret_cast<uintptr_t>(Sr)) & 15) == 0;
     // 4 spans of 128 pixels per round; the next round's loads are issued
     // before this round's pixels are accumulated
@@ -990,14 +1006,14 @@ __device__ __forceinline__ void row_moments_body(const RowArgs& a, const VB vb) 
         const int x0 = x00 + u * 128 + cc * 4;
         if (vec && x0 + 3 < W) {
           const float4 r4 = *reinterpret_cast<const float4*>(Rr + x0);
-          const float4 s4 = *reinterpret_cast<const float4*>(Sr + x0);
+          const float4 s4 = sci ? *reinterpret_cast<const float4*>(Sr + x0) : float4{0.f, 0.f, 0.f, 0.f};
           rr[u][0] = r4.x; rr[u][1] = r4.y; rr[u][2] = r4.z; rr[u][3] = r4.w;
           ss[u][0] = s4.x; ss[u][1] = s4.y; ss[u][2] = s4.z; ss[u][3] = s4.w;
         } else {
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             rr[u][k] = (x0 + k < W) ? Rr[x0 + k] : (TIN)0;
-            ss[u][k] = (x0 + k < W) ? Sr[x0 + k] : (TIN)0;
+            ss[u][k] = (sci && x0 + k < W) ? Sr[x0 + k] : (TIN)0;
           }
         }
       }
@@ -1017,19 +1033,20 @@ __device__ __forceinline__ void row_moments_body(const RowArgs& a, const VB vb) 
         for (int u = 0; u < 4; ++u)
 #pragma unroll
           for (int k = 0; k < 4; ++k)
-            accumulate(x00 + u * 128 + cc * 4 + k, (double)rv[u][k] - a.cR, (double)sv[u][k] - a.cS);
+            accumulate(x00 + u * 128 + cc * 4 + k, (double)rv[u][k] - a.cR, (double)sv[u][k] - (sci ? a.cS : 0.0));
       } else {
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             const int x = x00 + u * 128 + cc * 4 + k;
-            if (x < W) accumulate(x, (double)rv[u][k] - a.cR, (double)sv[u][k] - a.cS);
+            if (x < W) accumulate(x, (double)rv[u][k] - a.cR, (double)sv[u][k] - (sci ? a.cS : 0.0));
           }
       }
     }
   }
-  if (bad) atomicOr(a.flags, 1);
+  if (bad_r) atomicOr(a.flags, kNonfiniteRef);
+  if (bad_s) atomicOr(a.flags, kNonfiniteSci);
   // sum over the 32 lanes of each row (fixed order: butterfly 16, 8, 4, 2, 1)
 #pragma unroll
   for (int m = 0; m < kMR; ++m) {
@@ -1042,7 +1059,7 @@ __device__ __forceinline__ void row_moments_body(const RowArgs& a, const VB vb) 
   }
 #pragma unroll
   for (int m = 0; m < kMS; ++m) {
-    if (m <= a.DB) {
+    if (m <= a.DB && a.sci) {
       double v = ms[m];
 #pragma unroll
       for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 32);
@@ -1192,6 +1209,7 @@ static RowArgs make_row_args(const Geometry& g, const sfft_desc& d, const void* 
   a.flags = reinterpret_cast<int*>(ws + l.flags);
   a.twW = p.twW;
   a.edge = reinterpret_cast<double*>(ws + l.edge);
+  a.sci = 1;
   return a;
 }
 
@@ -1258,8 +1276,9 @@ static GatherArgs make_gather_args(const Geometry& g, const XinvArgs& xa, double
 template <typename T>
 static hipError_t launch_row(const Geometry& g, const sfft_desc& d, const void* R, const void* S,
                              unsigned char* ws, const Layout& l, const BuildPlan& p,
-                             hipStream_t st) {
-  const RowArgs a = make_row_args(g, d, R, S, ws, l, p);
+                             hipStream_t st, bool reuse_sci) {
+  RowArgs a = make_row_args(g, d, R, S, ws, l, p);
+  a.sci = reuse_sci ? 0 : 1;
   const size_t shmem = row_shmem<T>(g.W);
   // one resident wave of workgroups (3 per CU for rows up to 2048 pixels)
   const int per_cu = (g.W + kRowThreads - 1) / kRowThreads >= 16 ? 2 : 3;
@@ -1298,17 +1317,35 @@ static hipError_t launch_col(const Geometry& g, unsigned char* ws, const Layout&
   return hipGetLastError();
 }
 
+// The science image's row spectrum (the last plane of F), its DC / Nyquist
+// values, its row moments and its non-finite bit survive a solve and a
+// subtract in the same workspace when the solve and subtract regions end
+// before that plane; a build for another reference against the same science
+// image (and science pedestal) can then reuse them.
+bool sci_reusable(const sfft_desc& d) {
+  const Geometry g = make_geometry(d);
+  const Layout l = make_layout(g);
+  const size_t sci_plane = l.F + (size_t)(g.nsig - 1) * g.planeK * g.cxsize;
+  return l.solve_end <= sci_plane && l.sub_end <= sci_plane;
+}
+
 hipError_t launch_build(const sfft_desc& d, const void* R, const void* S, double* G, double* hv,
-                        unsigned char* ws, const BuildPlan& p, const Prof* pf, hipStream_t st) {
+                        unsigned char* ws, const BuildPlan& p, const Prof* pf, hipStream_t st,
+                        bool reuse_sci) {
   const Geometry g = make_geometry(d);
   const Layout l = make_layout(g);
   hipError_t e;
   prof_begin(pf, SFFT_PROF_BUILD, st);
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st,
-                     reinterpret_cast<int*>(ws + l.flags), 64, 0);
+  if (reuse_sci)
+    hipLaunchKernelGGL(k_clear_flags_keep_sci, dim3(1), dim3(64), 0, st,
+                       reinterpret_cast<int*>(ws + l.flags), 64);
+  else
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st,
+                       reinterpret_cast<int*>(ws + l.flags), 64, 0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   {
-    const RowArgs ra = make_row_args(g, d, R, S, ws, l, p);
+    RowArgs ra = make_row_args(g, d, R, S, ws, l, p);
+    ra.sci = reuse_sci ? 0 : 1;
     if (d.image_dtype == SFFT_F32)
       hipLaunchKernelGGL(k_row_moments<float>, dim3(row_moments_grid(g.H)), dim3(kRowThreads), 0, st, ra);
     else
@@ -1316,8 +1353,8 @@ hipError_t launch_build(const sfft_desc& d, const void* R, const void* S, double
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   prof_begin(pf, SFFT_PROF_ROW_PASS, st);
-  e = g.fp32 ? launch_row<float>(g, d, R, S, ws, l, p, st)
-             : launch_row<double>(g, d, R, S, ws, l, p, st);
+  e = g.fp32 ? launch_row<float>(g, d, R, S, ws, l, p, st, reuse_sci)
+             : launch_row<double>(g, d, R, S, ws, l, p, st, reuse_sci);
   prof_end(pf, SFFT_PROF_ROW_PASS, st);
   if (e != hipSuccess) return e;
   prof_begin(pf, SFFT_PROF_COL_PASS, st);

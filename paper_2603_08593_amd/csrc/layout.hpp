@@ -21,6 +21,8 @@ constexpr int kMaxW = 4096;
 constexpr int kSyncWords = 512;
 constexpr int kMaxTeam = 128;   // workgroups of one solve
 constexpr int kSyncClear = kSyncWords + 2 * 256;
+// bits of flag word 0: a non-finite pixel in the reference / science image
+constexpr int kNonfiniteRef = 1, kNonfiniteSci = 2;
 
 struct Geometry {
   int W, H, L, r, h, DK, DB, nK, nB, N, NKK, NP, nkx, TP, T, nsig;

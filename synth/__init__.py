@@ -322,3 +322,82 @@ def surrogate_init(n_out: int, seed: int) -> np.ndarray:
         else:
             parts.append(np.zeros(n))
     return np.concatenate(parts).astype(np.float32)
+
+
+# ----------------------------------------------------------------------------
+# multi-template workload and photometry positions
+# ----------------------------------------------------------------------------
+
+@dataclass
+class MultiTemplate:
+    S: np.ndarray                 # science image (H, W)
+    templates: list               # n_temp reference images (H, W)
+    zp_sci: float                 # science zero point
+    zp_templates: np.ndarray      # zero point of each template
+    transients: np.ndarray        # (n, 3): x, y, flux in science counts
+    meta: dict = field(default_factory=dict)
+
+
+def make_multi_template(W, H, n_temp=5, *, seed, nstars=None, fwhm_sci=4.2, fwhm_tmpl=(2.8, 3.6),
+                        flux=(1e2, 1e5), n_transients=6, transient_flux=(2e3, 2e4), zp_sci=30.0,
+                        background=True, dtype=np.float32) -> MultiTemplate:
+    """One science image and n_temp aligned templates of the same star field
+    (the multi-exposure template set of the paper's Sec. 2.2.1, N_TEMP = 5
+    by default). Templates: Gaussian PSFs with FWHM U[fwhm_tmpl], flux
+    scales U[0.7, 1.4] (so zero points zp_sci + 2.5 log10(scale)), skies
+    U[800, 1500], Poisson noise. Science: a broader Gaussian PSF (fwhm_sci),
+    sky U[800, 1500] plus a linear gradient, point-source transients present
+    in it only, Poisson noise. Each template maps onto the science image by a
+    Gaussian kernel of variance sigma_sci^2 - sigma_t^2 and sum 1/scale_t (up
+    to pixel integration), so the fit of every template is close to the
+    model class."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if nstars is None:
+        nstars = max(8, int(round(3000 * (W * H) / (2048 * 4096))))
+    xs = rng.uniform(0, W, nstars)
+    ys = rng.uniform(0, H, nstars)
+    fl = np.exp(rng.uniform(math.log(flux[0]), math.log(flux[1]), nstars))
+    k = 2.0 * math.sqrt(2.0 * math.log(2.0))
+    templates, zps, fws, scales = [], [], [], []
+    for _ in range(n_temp):
+        fw = float(rng.uniform(*fwhm_tmpl))
+        sc = float(rng.uniform(0.7, 1.4))
+        sky = float(rng.uniform(800, 1500))
+        model = sky + sc * render_gaussian_stars(W, H, xs, ys, fl, fw / k)
+        templates.append(rng.poisson(model).astype(dtype))
+        zps.append(zp_sci + 2.5 * math.log10(sc))
+        fws.append(fw)
+        scales.append(sc)
+    # transients: away from the edges, in the science image only
+    m = 16
+    tx = rng.uniform(m, W - m, n_transients)
+    ty = rng.uniform(m, H - m, n_transients)
+    tf = np.exp(rng.uniform(math.log(transient_flux[0]), math.log(transient_flux[1]), n_transients))
+    sky_s = float(rng.uniform(800, 1500))
+    smodel = sky_s + render_gaussian_stars(W, H, np.concatenate([xs, tx]), np.concatenate([ys, ty]),
+                                           np.concatenate([fl, tf]), fwhm_sci / k)
+    if background:
+        xt = _norm_coord(W)[None, :]
+        yt = _norm_coord(H)[:, None]
+        smodel = smodel + rng.uniform(-20, 20) * xt + rng.uniform(-20, 20) * yt
+    S = rng.poisson(np.maximum(smodel, 0.0)).astype(dtype)
+    return MultiTemplate(S, templates, zp_sci, np.array(zps), np.stack([tx, ty, tf], axis=1),
+                         dict(seed=seed, fwhm_templates=fws, scales=scales, fwhm_sci=fwhm_sci))
+
+
+def background_positions(W, H, n, radius, *, seed, avoid=None, avoid_radius=0.0):
+    """n aperture centres (x, y) drawn uniformly with the whole aperture
+    inside the image (at least radius + 1 px from every edge); positions
+    closer than avoid_radius to any (x, y) row of `avoid` are redrawn. Real
+    positions (sub-pixel). float64 array (n, 2)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m = radius + 1.0
+    out = []
+    av = None if avoid is None else np.asarray(avoid, dtype=np.float64)[:, :2]
+    while len(out) < n:
+        x = float(rng.uniform(m, W - 1 - m))
+        y = float(rng.uniform(m, H - 1 - m))
+        if av is not None and len(av) and np.min(np.hypot(av[:, 0] - x, av[:, 1] - y)) < avoid_radius:
+            continue
+        out.append((x, y))
+    return np.asarray(out, dtype=np.float64)
