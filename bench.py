@@ -512,6 +512,72 @@ def run_multi(steps, warmup, n_temp=5):
                 detected=det, n_transients=len(td), steps=steps)
 
 
+def rb_flops_per_candidate():
+    """Multiply-adds x 2 of the scorer's convolutions (no padding terms), four
+    rotated copies: stem 32x32x32x27, block 1 2 x 32x32x32x288, block 2
+    16x16x64x(288 + 576 + 32), block 3 8x8x128x(576 + 1152 + 64)."""
+    macs = (32 * 32 * 32 * 27 + 2 * 32 * 32 * 32 * 288 + 16 * 16 * 64 * (288 + 576 + 32)
+            + 8 * 8 * 128 * (576 + 1152 + 64))
+    return 4 * 2 * macs
+
+
+def run_realbogus(steps, warmup, n=4096):
+    """Real-bogus scorer on n candidates of the 2048x4096 pair's difference
+    image (random positions), seeded random weights: stamp extraction + the
+    network, candidates per second, and the network's matrix-core rate
+    against the bf16 peak."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2603_08593_amd as sf
+    pair = synth.make_cfg2(0)
+    R = torch.from_numpy(pair.R).cuda()
+    S = torch.from_numpy(pair.S).cuda()
+    d = sf.Differencer(W, H, L, DK, DB)
+    d.run(R, S, max_refine=1)
+    c = torch.from_numpy(synth.rb_candidates((H, W), n, seed=synth.seed_for(8, 0))).cuda()
+    params = torch.from_numpy(synth.rb_init(1)).cuda()
+    stamps = torch.zeros((n, 3, 32, 32), dtype=torch.float32, device="cuda")
+    logits = torch.zeros(n, dtype=torch.float32, device="cuda")
+    probs = torch.zeros(n, dtype=torch.float32, device="cuda")
+    ws = torch.empty(sf.sfft_rb_workspace_size(n), dtype=torch.uint8, device="cuda")
+    desc = sf.image_desc(S)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        sf.sfft_rb_extract(d.handle, desc, S, R, d.buf.diff, c, (1000.0, 1000.0, 0.0), (0.01, 0.01, 0.05), stamps,
+                           stream)
+        sf.sfft_rb_score(d.handle, params, stamps, logits, probs, ws, stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ev = HipEvents()
+    a, b = ev.create(), ev.create()
+    ev.hip.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    ev.hip.hipEventRecord(a, ctypes.c_void_p(stream.cuda_stream))
+    for _ in range(steps):
+        sf.sfft_rb_score(d.handle, params, stamps, logits, probs, ws, stream)
+    ev.hip.hipEventRecord(b, ctypes.c_void_p(stream.cuda_stream))
+    torch.cuda.synchronize()
+    score_s = ev.elapsed_ms(a, b) / steps / 1e3
+    ev.close()
+    fin = bool(torch.isfinite(logits).all().item())
+    d.close()
+    t_step = (t1 - t0) / steps
+    fl = rb_flops_per_candidate() * n
+    ach = fl / score_s / 1e12
+    return dict(value=n / t_step if fin else 0.0, ms=t_step * 1e3, n=n, steps=steps, score_us=score_s * 1e6,
+                roofline={"kernel": "rb_score (7 conv GEMMs + head)", "bound": "mfma", "achieved": round(ach, 2),
+                          "peak": 2500.0, "unit": "TFLOP/s", "frac": round(ach / 2500.0, 4), "traffic": None,
+                          "avg_us": round(score_s * 1e6, 2), "alg_flops": fl})
+
+
 # ---------------------------------------------------------------------------
 # JSON lines
 # ---------------------------------------------------------------------------
@@ -606,6 +672,19 @@ def multi_line(args, r):
     }
 
 
+def rb_line(args, r):
+    return {
+        "metric": "real-bogus candidates scored/sec", "value": round(r["value"], 1), "unit": "candidates/s",
+        "n_gpus": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic",
+        "steps": r["steps"], "warmup": args.warmup, "ms_per_step": round(r["ms"], 4), "dtype": "bf16",
+        "config": {"workload": f"real-bogus scorer: {r['n']} candidates of a 2048x4096 difference image, "
+                               "3x32x32 stamps, 4 rotated copies through a residual CNN (stem 32, blocks 32/64/128),"
+                               " seeded random weights, bf16 matrix cores with FP32 accumulation",
+                   "form": "realbogus", "parallelism": "single GPU"},
+        "roofline": r["roofline"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -616,7 +695,7 @@ def main():
     ap.add_argument("--compute", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
-    ap.add_argument("--form", choices=["plain", "batch", "stamps", "learned", "multi"], default="plain")
+    ap.add_argument("--form", choices=["plain", "batch", "stamps", "learned", "multi", "realbogus"], default="plain")
     ap.add_argument("--learned-batch", type=int, default=10, help="pairs per network launch (learned form)")
     ap.add_argument("--learned-pairs", type=int, default=60, help="held-out pairs timed (learned form)")
     ap.add_argument("--batch-steps", type=int, default=10, help="graph replays timed (batched form)")
@@ -632,6 +711,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.form == "batch":
         print(json.dumps(batch_line(args, run_batch(args.steps, args.warmup))), flush=True)
+        return
+    if args.form == "realbogus":
+        print(json.dumps(rb_line(args, run_realbogus(args.steps, args.warmup))), flush=True)
         return
     if args.form == "multi":
         print(json.dumps(multi_line(args, run_multi(args.steps, args.warmup))), flush=True)
@@ -667,6 +749,8 @@ def main():
         torch.cuda.empty_cache()
         mu = run_multi(min(args.steps, 5), 1)
         torch.cuda.empty_cache()
+        rb = run_realbogus(min(args.steps, 10), 2)
+        torch.cuda.empty_cache()
         out["precision_fp32_pairs_per_s"] = round(p32["value"], 3)
         out["batched_ccd_equiv_per_s"] = bt["value"]
         out["batched_items_per_s"] = round(bt["items_per_s"], 2) if bt["value"] else 0.0
@@ -676,12 +760,14 @@ def main():
         out["learned_gain_vs_plain"] = round(ln["gain"], 4)
         out["multi_template_pairs_per_s"] = round(mu["pairs"], 3)
         out["multi_template_science_per_s"] = round(mu["value"], 3)
+        out["realbogus_candidates_per_s"] = round(rb["value"], 1)
         out["forms"] = {
             "precision_fp32": plain_line(args, p32, "fp32"),
             "batched": batch_line(args, bt),
             "stamps": stamps_line(args, st),
             "learned": learned_line(args, ln),
             "multi_template": multi_line(args, mu),
+            "realbogus": rb_line(args, rb),
         }
         for v in out["forms"].values():
             for k in ("metric", "unit", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data"):

@@ -65,6 +65,20 @@ typedef enum {
   SFFT_COMPUTE_FP32 = 1       /* FP32 spectra and products, FP32 accumulation; FP64 solve */
 } sfft_compute;
 
+/* Where the kernel's spatial polynomial is evaluated (paper Sec. 1 leaves it
+ * open). INPUT_PIXEL: M(x) = sum_i sum_d a_(i,d) p_i(x-d) R'(x-d) + ... (the
+ * default, every call). OUTPUT_PIXEL: M(x) = sum_i p_i(x) sum_d a_(i,d)
+ * R'(x-d) + ...; the FFT builds then fit with R' taken as zero on the
+ * r-pixel frame of the image (there the periodic wrap would make the
+ * output-pixel polynomial differ from a shifted input-pixel one), which
+ * makes the output-pixel normal equations exactly T^T G T, T^T h of the
+ * input-pixel ones (T: binomial expansion of the shifted monomials, per
+ * kernel offset). Dropping the frame leaves the model without the sky of
+ * those pixels: take the sky out with the pedestals (e.g. image means). Supported by sfft_build_system, sfft_build_system_masked,
+ * sfft_solve, sfft_subtract(_noalloc) and sfft_difference_multi; the stamp,
+ * batched and background-refit calls return SFFT_ERR_UNSUPPORTED. */
+typedef enum { SFFT_CONV_INPUT_PIXEL = 0, SFFT_CONV_OUTPUT_PIXEL = 1 } sfft_convention;
+
 typedef struct {
   int32_t width;              /* W: columns (x) */
   int32_t height;             /* H: rows (y) */
@@ -74,7 +88,7 @@ typedef struct {
   int32_t db;                 /* background polynomial degree, 0..4 */
   int32_t image_dtype;        /* sfft_dtype of R, S, D */
   int32_t compute;            /* sfft_compute of the build */
-  int32_t reserved;           /* must be 0 */
+  int32_t convention;         /* sfft_convention: where the kernel polynomial is evaluated */
   double ref_pedestal;        /* c_R, subtracted from R before fitting */
   double sci_pedestal;        /* c_S, subtracted from S before fitting */
 } sfft_desc;
@@ -133,6 +147,20 @@ sfft_status sfft_build_system(sfft_handle handle, const sfft_desc* desc,
                               double* G, double* h,
                               void* ws, size_t ws_bytes, void* stream);
 
+/* Masked fit (SFFT's way of fitting on star stamps only): as
+ * sfft_build_system with R' and S' taken as zero wherever mask == 0, i.e. the
+ * periodic least-squares problem above on the masked images (every pixel
+ * still enters the sum). The difference image is then formed by
+ * sfft_subtract from the unmasked images. With the output-pixel convention R'
+ * is also zero on the r-pixel frame.
+ *   mask    : device uint8, W x H, row pitch mask_ld >= W bytes; nonzero = use
+ * Non-finite pixels outside the mask are ignored (neither used nor flagged). */
+sfft_status sfft_build_system_masked(sfft_handle handle, const sfft_desc* desc,
+                                     const void* ref, const void* sci,
+                                     const uint8_t* mask, int64_t mask_ld,
+                                     double* G, double* h,
+                                     void* ws, size_t ws_bytes, void* stream);
+
 /* theta = G^-1 h in FP64: equilibrate with D = diag(G)^-1/2, Cholesky-factor
  * the equilibrated matrix, forward/back substitution, then up to max_refine
  * (0..8) steps of iterative refinement on the residual h - G theta.
@@ -145,7 +173,8 @@ sfft_status sfft_solve(sfft_handle handle, const sfft_desc* desc,
                        int32_t max_refine, sfft_solve_info* info,
                        void* ws, size_t ws_bytes, void* stream);
 
-/* D = S' - M_coef(R') with periodic boundaries, accumulated in FP64.
+/* D = S' - M_coef(R') with periodic boundaries, accumulated in FP64, in the
+ * descriptor's kernel convention (the whole image; no mask).
  * chi2 (nullable, device double): reduced chi^2 of D over the image minus an
  * r-pixel frame, dof = |frame interior| - N, variance per pixel
  * max(S,1) + kappa2(x) max(R,1), kappa2(x) = sum_d (sum_i a_(i,d) p_i(x))^2
@@ -348,6 +377,48 @@ sfft_status sfft_forced_photometry(sfft_handle handle, const sfft_desc* desc, co
                                    const double* xy, int32_t n, double radius, double zp,
                                    const double* sigma, double* flux, double* mag, double* mag_err,
                                    void* stream);
+
+/* ---- Real-bogus scorer (inference) ---------------------------------------
+ * Paper Sec. 2.3.4: every candidate of a difference image is scored by a
+ * rotation-invariant convolutional network with residual connections (after
+ * ResNet-18) on a three-channel stamp (science, template, difference)
+ * centred on it; output: the probability that it is real. The trained
+ * weights and layer sizes are not published; this network (the reading used
+ * here, weights supplied by the caller):
+ *   the 3 x 32 x 32 stamp is rotated by 0, 90, 180, 270 degrees; each copy:
+ *     conv 3x3 3->32 + ReLU; residual block (conv 3x3 32->32 + ReLU,
+ *     conv 3x3 32->32, + block input, ReLU); block (conv 3x3 stride 2
+ *     32->64 + ReLU, conv 3x3 64->64, + conv 1x1 stride 2 32->64 of the
+ *     block input, ReLU); block (the same, 64->128); global average pool;
+ *   mean of the four copies' 128 features (invariant under quarter turns);
+ *   linear 128->64 + ReLU; linear 64->1 = logit; probability = sigmoid.
+ * Convolutions: cross-correlation, zero padding 1 for 3x3; output (i, j)
+ * reads input (s i + ky - 1, s j + kx - 1). They run on the bf16 matrix
+ * cores: stamps, convolution weights and every activation are rounded to
+ * bfloat16 (nearest even), sums in FP32; pooling and linear layers in FP32.
+ * Parameters: one flat FP32 vector (sfft_rb_num_params() = 315009 values):
+ * conv weights [out][in][3][3] (1x1: [out][in]) each followed by its bias,
+ * in the order stem, block 1 (a, b), block 2 (a, b, projection), block 3
+ * (a, b, projection); then fc1 [64][128], bias [64], fc2 [1][64], bias [1]. */
+int64_t sfft_rb_num_params(void);
+
+/* Device workspace bytes for sfft_rb_score on n candidates (1..16384). */
+sfft_status sfft_rb_workspace_size(int32_t n, size_t* bytes);
+
+/* stamps (device FP32 [n][3][32][32]): channel c of candidate k is
+ * (I_c[cy - 16 + i][cx - 16 + j] - offsets[c]) * scales[c], I = (sci, ref,
+ * diff) (periodic indices; only width, height, ld and image_dtype of desc
+ * are used); centers: device int32 [n][2] = (cx, cy); offsets, scales: host
+ * float[3]. */
+sfft_status sfft_rb_extract(sfft_handle handle, const sfft_desc* desc, const void* sci, const void* ref,
+                            const void* diff, const int32_t* centers, int32_t n, const float* offsets,
+                            const float* scales, float* stamps, void* stream);
+
+/* logits (device FP32 [n]) and, when probs is not NULL, probabilities of n
+ * stamps; params: device FP32 [sfft_rb_num_params()]; ws: device workspace
+ * of sfft_rb_workspace_size(n) bytes (packed bf16 weights and activations). */
+sfft_status sfft_rb_score(sfft_handle handle, const float* params, const float* stamps, int32_t n,
+                          float* logits, float* probs, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- Learned form ------------------------------------------------------
  * A small convolutional network predicts the kernel and background

@@ -45,7 +45,7 @@ class Desc(ctypes.Structure):
         ("db", ctypes.c_int32),
         ("image_dtype", ctypes.c_int32),
         ("compute", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("convention", ctypes.c_int32),
         ("ref_pedestal", ctypes.c_double),
         ("sci_pedestal", ctypes.c_double),
     ]
@@ -91,6 +91,8 @@ _SIGS = {
     "sfft_validate": (ctypes.c_int, [ctypes.POINTER(Desc)]),
     "sfft_workspace_size": (ctypes.c_int, [_P, ctypes.POINTER(Desc), ctypes.POINTER(ctypes.c_size_t)]),
     "sfft_build_system": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "sfft_build_system_masked": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, ctypes.c_int64, _P, _P, _P,
+                                                ctypes.c_size_t, _P]),
     "sfft_solve": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, ctypes.c_int32, _P, _P,
                                   ctypes.c_size_t, _P]),
     "sfft_subtract": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
@@ -106,6 +108,11 @@ _SIGS = {
                                                ctypes.c_double, ctypes.c_double, _P, _P, _P]),
     "sfft_forced_photometry": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, ctypes.c_int32, ctypes.c_double,
                                               ctypes.c_double, _P, _P, _P, _P, _P]),
+    "sfft_rb_num_params": (ctypes.c_int64, []),
+    "sfft_rb_workspace_size": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "sfft_rb_extract": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, _P, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float), _P, _P]),
+    "sfft_rb_score": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, _P, ctypes.c_size_t, _P]),
     "sfft_subtract_noalloc": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, _P, _P, _P]),
     "sfft_refit_background": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, _P, _P, _P, ctypes.c_size_t,
                                              _P]),
@@ -175,10 +182,13 @@ def _check(status: int, where: str):
         raise SfftError(status, where)
 
 
+SFFT_CONV_INPUT_PIXEL, SFFT_CONV_OUTPUT_PIXEL = 0, 1
+
+
 def make_desc(width, height, L, dk, db, *, ld=None, image_dtype=SFFT_F32, compute=SFFT_COMPUTE_FP64,
-              ref_pedestal=0.0, sci_pedestal=0.0) -> Desc:
+              ref_pedestal=0.0, sci_pedestal=0.0, convention=SFFT_CONV_INPUT_PIXEL) -> Desc:
     return Desc(int(width), int(height), int(width if ld is None else ld), int(L), int(dk), int(db),
-                int(image_dtype), int(compute), 0, float(ref_pedestal), float(sci_pedestal))
+                int(image_dtype), int(compute), int(convention), float(ref_pedestal), float(sci_pedestal))
 
 
 def sfft_num_unknowns(desc: Desc) -> int:
@@ -243,6 +253,14 @@ def sfft_build_system(handle: Handle, desc: Desc, ref, sci, G, h, ws, stream=Non
            "sfft_build_system")
 
 
+def sfft_build_system_masked(handle: Handle, desc: Desc, ref, sci, mask, G, h, ws, stream=None):
+    """mask: uint8 (H, W) device tensor, nonzero = the pixel enters the fit."""
+    _check(lib().sfft_build_system_masked(handle.ptr, ctypes.byref(desc), _dp(ref), _dp(sci), _dp(mask),
+                                          int(mask.stride(0)), _dp(G), _dp(h), _dp(ws),
+                                          ws.numel() * ws.element_size(), _stream_ptr(stream)),
+           "sfft_build_system_masked")
+
+
 def sfft_solve(handle: Handle, desc: Desc, G, h, coef, info, ws, max_refine=2, stream=None):
     _check(lib().sfft_solve(handle.ptr, ctypes.byref(desc), _dp(G), _dp(h), _dp(coef), int(max_refine),
                             _dp(info), _dp(ws), ws.numel() * ws.element_size(), _stream_ptr(stream)),
@@ -303,14 +321,15 @@ class Differencer:
     """Reusable device buffers + handle for one image shape and fit."""
 
     def __init__(self, width, height, L, dk, db, *, image_dtype="float32", compute="fp64",
-                 ref_pedestal=0.0, sci_pedestal=0.0, device="cuda", stamps=None):
+                 ref_pedestal=0.0, sci_pedestal=0.0, device="cuda", stamps=None, convention="input"):
         import torch
         self.torch = torch
         self.dtype = torch.float32 if image_dtype in ("float32", torch.float32) else torch.float64
         self.desc = make_desc(width, height, L, dk, db,
                               image_dtype=SFFT_F32 if self.dtype == torch.float32 else SFFT_F64,
                               compute=SFFT_COMPUTE_FP32 if compute == "fp32" else SFFT_COMPUTE_FP64,
-                              ref_pedestal=ref_pedestal, sci_pedestal=sci_pedestal)
+                              ref_pedestal=ref_pedestal, sci_pedestal=sci_pedestal,
+                              convention=SFFT_CONV_OUTPUT_PIXEL if convention == "output" else SFFT_CONV_INPUT_PIXEL)
         self.handle = Handle()
         self.N = sfft_num_unknowns(self.desc)
         # stamps = (n_stamps, size): size the workspace for the stamp build as well
@@ -340,9 +359,13 @@ class Differencer:
         self.desc.ref_pedestal = float(ref_pedestal)
         self.desc.sci_pedestal = float(sci_pedestal)
 
-    def build(self, ref, sci, stream=None):
+    def build(self, ref, sci, stream=None, mask=None):
+        """Normal equations (mask: optional uint8 device image, the masked fit)."""
         b = self.buf
-        sfft_build_system(self.handle, self.desc, ref, sci, b.G, b.h, b.ws, stream)
+        if mask is None:
+            sfft_build_system(self.handle, self.desc, ref, sci, b.G, b.h, b.ws, stream)
+        else:
+            sfft_build_system_masked(self.handle, self.desc, ref, sci, mask, b.G, b.h, b.ws, stream)
 
     def refit_background(self, ref, sci, coef=None, stream=None):
         """Overwrite the background part of coef with the least-squares
@@ -367,9 +390,9 @@ class Differencer:
         sfft_subtract(self.handle, self.desc, ref, sci, b.coef if coef is None else coef, b.diff,
                       b.chi2 if chi2 else None, b.ws, stream)
 
-    def run(self, ref, sci, max_refine=2, stream=None):
+    def run(self, ref, sci, max_refine=2, stream=None, mask=None):
         """build + solve + subtract (+ chi2) on the stream; asynchronous."""
-        self.build(ref, sci, stream)
+        self.build(ref, sci, stream, mask)
         self.solve(max_refine, stream)
         self.subtract(ref, sci, stream=stream)
         return self.buf
@@ -440,6 +463,31 @@ def sfft_forced_photometry(handle: Handle, desc: Desc, image, xy, radius, zp, si
     _check(lib().sfft_forced_photometry(handle.ptr, ctypes.byref(desc), _dp(image), _dp(xy), int(xy.shape[0]),
                                         float(radius), float(zp), _dp(sigma), _dp(flux), _dp(mag), _dp(mag_err),
                                         _stream_ptr(stream)), "sfft_forced_photometry")
+
+
+def sfft_rb_num_params() -> int:
+    return int(lib().sfft_rb_num_params())
+
+
+def sfft_rb_workspace_size(n: int) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().sfft_rb_workspace_size(int(n), ctypes.byref(b)), "sfft_rb_workspace_size")
+    return int(b.value)
+
+
+def _flt3(v):
+    return (ctypes.c_float * 3)(*[float(x) for x in v])
+
+
+def sfft_rb_extract(handle: Handle, desc: Desc, sci, ref, diff, centers, offsets, scales, stamps, stream=None):
+    _check(lib().sfft_rb_extract(handle.ptr, ctypes.byref(desc), _dp(sci), _dp(ref), _dp(diff), _dp(centers),
+                                 int(centers.shape[0]), _flt3(offsets), _flt3(scales), _dp(stamps),
+                                 _stream_ptr(stream)), "sfft_rb_extract")
+
+
+def sfft_rb_score(handle: Handle, params, stamps, logits, probs, ws, stream=None):
+    _check(lib().sfft_rb_score(handle.ptr, _dp(params), _dp(stamps), int(stamps.shape[0]), _dp(logits), _dp(probs),
+                               _dp(ws), ws.numel() * ws.element_size(), _stream_ptr(stream)), "sfft_rb_score")
 
 
 class MultiDifferencer:

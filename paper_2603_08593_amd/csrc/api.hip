@@ -19,6 +19,7 @@
 #include "stamps.hpp"
 #include "surrogate.hpp"
 #include "products.hpp"
+#include "realbogus.hpp"
 
 namespace sfft {
 
@@ -26,6 +27,9 @@ hipError_t launch_build(const sfft_desc& d, const void* R, const void* S, double
                         unsigned char* ws, const BuildPlan& p, const Prof* pf, hipStream_t st,
                         bool reuse_sci = false);
 bool sci_reusable(const sfft_desc& d);
+hipError_t launch_build_masked(const sfft_desc& d, const void* R, const void* S, const unsigned char* mask,
+                               int64_t mask_ld, double* G, double* hv, unsigned char* ws, const BuildPlan& p,
+                               const Prof* pf, hipStream_t st, bool reuse_sci);
 hipError_t launch_solve(const sfft_desc& d, const double* G, const double* h, double* coef,
                         int max_refine, sfft_solve_info* info, unsigned char* ws, int num_cus,
                         const Prof* pf, hipStream_t st);
@@ -167,7 +171,8 @@ static sfft_status validate_core(const sfft_desc* d) {
   if (d->dk < 0 || d->dk > 4 || d->db < 0 || d->db > 4) return SFFT_ERR_INVALID_ARG;
   if (d->image_dtype != SFFT_F32 && d->image_dtype != SFFT_F64) return SFFT_ERR_INVALID_ARG;
   if (d->compute != SFFT_COMPUTE_FP64 && d->compute != SFFT_COMPUTE_FP32) return SFFT_ERR_INVALID_ARG;
-  if (d->reserved != 0) return SFFT_ERR_INVALID_ARG;
+  if (d->convention != SFFT_CONV_INPUT_PIXEL && d->convention != SFFT_CONV_OUTPUT_PIXEL)
+    return SFFT_ERR_INVALID_ARG;
   if (!std::isfinite(d->ref_pedestal) || !std::isfinite(d->sci_pedestal)) return SFFT_ERR_INVALID_ARG;
   if (d->L > 15 || d->dk > 2) return SFFT_ERR_UNSUPPORTED;
   if ((int64_t)d->height * d->ld > ((int64_t)1 << 40)) return SFFT_ERR_UNSUPPORTED;
@@ -257,6 +262,25 @@ sfft_status sfft_build_system(sfft_handle h, const sfft_desc* d, const void* ref
   return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
 }
 
+sfft_status sfft_build_system_masked(sfft_handle h, const sfft_desc* d, const void* ref, const void* sci,
+                                     const uint8_t* mask, int64_t mask_ld, double* G, double* hv, void* ws,
+                                     size_t ws_bytes, void* stream) {
+  if (!h) return SFFT_ERR_INVALID_ARG;
+  sfft_status s = sfft_validate(d);
+  if (s != SFFT_OK) return s;
+  if (!ref || !sci || !G || !hv || !mask || mask_ld < d->width) return SFFT_ERR_INVALID_ARG;
+  if ((s = check_ws(ws, ws_bytes, make_layout(make_geometry(*d)).total)) != SFFT_OK) return s;
+  if ((s = check_device(h)) != SFFT_OK) return s;
+  Twiddles tw, t128;
+  if (get_twiddles(h, d->width, tw) != hipSuccess) return SFFT_ERR_HIP;
+  if (get_twiddles(h, kTP, t128) != hipSuccess) return SFFT_ERR_HIP;
+  const bool f32 = d->compute == SFFT_COMPUTE_FP32;
+  BuildPlan p{f32 ? tw.w32 : tw.w64, tw.w64, f32 ? t128.w32 : t128.w64, h->num_cus};
+  const hipError_t e = launch_build_masked(*d, ref, sci, mask, mask_ld, G, hv, static_cast<unsigned char*>(ws), p,
+                                           &h->prof, static_cast<hipStream_t>(stream), false);
+  return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
+}
+
 sfft_status sfft_solve(sfft_handle h, const sfft_desc* d, const double* G, const double* hv,
                        double* coef, int32_t max_refine, sfft_solve_info* info, void* ws,
                        size_t ws_bytes, void* stream) {
@@ -304,6 +328,7 @@ sfft_status sfft_subtract_noalloc(sfft_handle h, const sfft_desc* d, const void*
 static sfft_status validate_stamps(const sfft_desc* d, int32_t n, int32_t size) {
   sfft_status s = validate_core(d);
   if (s != SFFT_OK) return s;
+  if (d->convention != SFFT_CONV_INPUT_PIXEL) return SFFT_ERR_UNSUPPORTED;
   if (n < 1 || n > kStMaxStamps || size < 1 || (size % 2) == 0 || size > kStMaxSize)
     return SFFT_ERR_INVALID_ARG;
   if (size > d->width || size > d->height) return SFFT_ERR_INVALID_ARG;
@@ -356,6 +381,7 @@ sfft_status sfft_refit_background(sfft_handle h, const sfft_desc* d, const void*
   sfft_status s = validate_core(d);
   if (s != SFFT_OK) return s;
   if (!ref || !sci || !coef || !G || !hv) return SFFT_ERR_INVALID_ARG;
+  if (d->convention != SFFT_CONV_INPUT_PIXEL) return SFFT_ERR_UNSUPPORTED;
   if ((s = check_ws(ws, ws_bytes, make_layout(make_geometry(*d)).build_end)) != SFFT_OK) return s;
   if ((s = check_device(h)) != SFFT_OK) return s;
   BuildPlan p{nullptr, nullptr, nullptr, h->num_cus};
@@ -488,6 +514,46 @@ sfft_status sfft_limiting_magnitude(sfft_handle h, const sfft_desc* d, const voi
   sfft_status s = sfft_forced_photometry(h, d, image, xy, n, radius, zp, nullptr, flux, nullptr, nullptr, stream);
   if (s != SFFT_OK) return s;
   const hipError_t e = launch_limiting_mag(flux, n, zp, nsigma, result, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
+}
+
+// ---- real-bogus scorer ----------------------------------------------------
+
+int64_t sfft_rb_num_params(void) { return kRbNumParams; }
+
+sfft_status sfft_rb_workspace_size(int32_t n, size_t* bytes) {
+  if (!bytes || n < 1 || n > kRbMaxN) return SFFT_ERR_INVALID_ARG;
+  *bytes = rb_plan(n).total;
+  return SFFT_OK;
+}
+
+sfft_status sfft_rb_extract(sfft_handle h, const sfft_desc* d, const void* sci, const void* ref, const void* diff,
+                            const int32_t* centers, int32_t n, const float* offsets, const float* scales,
+                            float* stamps, void* stream) {
+  if (!h) return SFFT_ERR_INVALID_ARG;
+  sfft_status s = validate_image(d);
+  if (s != SFFT_OK) return s;
+  if (!sci || !ref || !diff || !centers || !offsets || !scales || !stamps || n < 1 || n > (1 << 20))
+    return SFFT_ERR_INVALID_ARG;
+  for (int c = 0; c < 3; ++c)
+    if (!std::isfinite(offsets[c]) || !std::isfinite(scales[c])) return SFFT_ERR_INVALID_ARG;
+  if ((s = check_device(h)) != SFFT_OK) return s;
+  RbExtractArgs a{};
+  a.img[0] = sci; a.img[1] = ref; a.img[2] = diff;
+  a.ld = d->ld; a.W = d->width; a.H = d->height; a.centers = centers; a.n = n; a.stamps = stamps;
+  for (int c = 0; c < 3; ++c) { a.offset[c] = offsets[c]; a.scale[c] = scales[c]; }
+  const hipError_t e = launch_rb_extract(a, d->image_dtype == SFFT_F32, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
+}
+
+sfft_status sfft_rb_score(sfft_handle h, const float* params, const float* stamps, int32_t n, float* logits,
+                          float* probs, void* ws, size_t ws_bytes, void* stream) {
+  if (!h || !params || !stamps || !logits || n < 1 || n > kRbMaxN) return SFFT_ERR_INVALID_ARG;
+  sfft_status s;
+  if ((s = check_ws(ws, ws_bytes, rb_plan(n).total)) != SFFT_OK) return s;
+  if ((s = check_device(h)) != SFFT_OK) return s;
+  const hipError_t e = launch_rb_score(params, stamps, n, logits, probs, static_cast<unsigned char*>(ws),
+                                       static_cast<hipStream_t>(stream));
   return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
 }
 
@@ -686,7 +752,7 @@ sfft_status sfft_batch_create(sfft_handle h, const sfft_batch_item* items, int32
     if ((s = check_ws(it.ws, it.ws_bytes, make_layout(make_geometry(it.desc)).total)) != SFFT_OK) return s;
     if (it.desc.compute != SFFT_COMPUTE_FP32 || it.desc.image_dtype != SFFT_F32 || it.desc.width > 2048)
       return SFFT_ERR_UNSUPPORTED;
-    if (it.desc.dk != items[0].desc.dk) return SFFT_ERR_UNSUPPORTED;
+    if (it.desc.dk != items[0].desc.dk || it.desc.convention != SFFT_CONV_INPUT_PIXEL) return SFFT_ERR_UNSUPPORTED;
   }
   sfft_batch b = new (std::nothrow) sfft_batch_s();
   if (!b) return SFFT_ERR_INTERNAL;

@@ -165,7 +165,20 @@ struct RowArgs {
   double* edge;       // [nsig][2][H]: real k_x = 0 and k_x = W/2 values
   int sci;            // 1: transform S' and take its moments; 0: they are
                       // already in the workspace (a second template)
+  // masked fit: R' and S' are taken as zero where mask[y * mask_ld + x] == 0
+  // (null: no mask); R' also on the `frame`-pixel border (output-pixel
+  // convention: frame = r, else 0)
+  const unsigned char* mask;
+  int64_t mask_ld;
+  int frame;
 };
+
+// mask and frame of a build: whether R' and S' at (x, y) enter the fit
+__device__ __forceinline__ void pixel_mask(const RowArgs& a, int x, int y, bool& mr, bool& ms) {
+  ms = true;
+  if (a.mask) ms = a.mask[(int64_t)y * a.mask_ld + x] != 0;
+  mr = ms && (a.frame == 0 || (x >= a.frame && x < a.W - a.frame && y >= a.frame && y < a.H - a.frame));
+}
 
 // NQ: row elements per thread, max(1, ceil(W / 256)); MIXED: W has factors 3 or 5
 template <typename T, typename TIN, int NQ, bool MIXED, bool PF>
@@ -232,7 +245,13 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const VB vb) {
         const int x = threadIdx.x + q * kRowThreads;
         if (x < W) {
           const double xt = (double)x * a.sx - 1.0;
-          const double rv = (double)rc[q] - a.cR, sv = (double)sc[q] - a.cS;
+          double rv = (double)rc[q] - a.cR, sv = (double)sc[q] - a.cS;
+          if (a.mask || a.frame) {
+            bool mr, ms;
+            pixel_mask(a, x, y, mr, ms);
+            rv = mr ? rv : 0.0;
+            sv = ms ? sv : 0.0;
+          }
           const double v0 = (s0 <= a.DK) ? ipow(xt, s0) * rv : sv;
           double v1 = 0.0;
           if (s1 < nsig) v1 = (s1 <= a.DK) ? ipow(xt, s1) * rv : sv;
@@ -971,6 +990,13 @@ __device__ __forceinline__ void row_moments_body(const RowArgs& a, const VB vb) 
   for (int m = 0; m < kMS; ++m) ms[m] = 0.0;
   bool bad_r = false, bad_s = false;
   auto accumulate = [&](int x, double rv, double sv) {
+    if (a.mask || a.frame) {
+      // pixels outside the mask are not part of the fit (nor of the check)
+      bool mr, ms;
+      pixel_mask(a, x, y, mr, ms);
+      rv = mr ? rv : 0.0;
+      sv = ms ? sv : 0.0;
+    }
     bad_r |= !is_finite_d(rv);
     bad_s |= !is_finite_d(sv);
     const double xt = (double)x * a.sx - 1.0;
@@ -987,7 +1013,13 @@ __device__ __forceinline__ void row_moments_body(const RowArgs& a, const VB vb) 
     const TIN* Rr = static_cast<const TIN*>(a.R) + (int64_t)y * a.ld;
     for (int e = cc; e < 2 * a.r; e += 32) {
       const int x = e < a.r ? e : W - 2 * a.r + e;
-      a.ER[(int64_t)y * 2 * a.r + e] = (double)Rr[x] - a.cR;
+      double ev = (double)Rr[x] - a.cR;
+      if (a.mask || a.frame) {
+        bool mr, ms;
+        pixel_mask(a, x, y, mr, ms);
+        ev = mr ? ev : 0.0;
+      }
+      a.ER[(int64_t)y * 2 * a.r + e] = ev;
     }
   }
   if (y < a.H) {
@@ -1210,6 +1242,9 @@ static RowArgs make_row_args(const Geometry& g, const sfft_desc& d, const void* 
   a.twW = p.twW;
   a.edge = reinterpret_cast<double*>(ws + l.edge);
   a.sci = 1;
+  a.mask = nullptr;
+  a.mask_ld = 0;
+  a.frame = 0;
   return a;
 }
 
@@ -1276,9 +1311,13 @@ static GatherArgs make_gather_args(const Geometry& g, const XinvArgs& xa, double
 template <typename T>
 static hipError_t launch_row(const Geometry& g, const sfft_desc& d, const void* R, const void* S,
                              unsigned char* ws, const Layout& l, const BuildPlan& p,
-                             hipStream_t st, bool reuse_sci) {
+                             hipStream_t st, bool reuse_sci, const unsigned char* mask, int64_t mask_ld,
+                             int frame) {
   RowArgs a = make_row_args(g, d, R, S, ws, l, p);
   a.sci = reuse_sci ? 0 : 1;
+  a.mask = mask;
+  a.mask_ld = mask_ld;
+  a.frame = frame;
   const size_t shmem = row_shmem<T>(g.W);
   // one resident wave of workgroups (3 per CU for rows up to 2048 pixels)
   const int per_cu = (g.W + kRowThreads - 1) / kRowThreads >= 16 ? 2 : 3;
@@ -1317,6 +1356,90 @@ static hipError_t launch_col(const Geometry& g, unsigned char* ws, const Layout&
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Output-pixel convention. With the kernel polynomial evaluated at the output
+// pixel, design column (i, d) is p_i(x) R'(x - d). Where R'(u) is nonzero
+// only at least r pixels from every edge, x = u + d never wraps and
+// p_i(u + d) = sum_m T_d[m][i] p_m(u) exactly (binomial expansion in the
+// shifted normalised coordinates, xt(u + dx) = xt(u) + 2 dx / (W - 1)):
+//   T_d[(a', b')][(a, b)] = C(a, a') C(b, b') ex^(a - a') ey^(b - b'),
+//   ex = 2 dx / (W - 1), ey = 2 dy / (H - 1), a' <= a, b' <= b.
+// So the output-pixel design is the input-pixel one times the block-diagonal
+// T (identity on the background), and its normal equations are
+// G_out = T^T G T, h_out = T^T h. The build zeroes R' on the r-pixel frame
+// (RowArgs::frame), assembles the input-pixel system, copies it aside and
+// forms G_out, h_out entry by entry (at most (n(DK))^2 terms each).
+// ---------------------------------------------------------------------------
+
+struct OutpixArgs {
+  const double* Gi;   // input-pixel G (copy), N x N
+  const double* hi;   // input-pixel h (copy)
+  double* G;
+  double* hv;
+  int N, L, r, nK, W, H;
+  int ea[6], eb[6];   // monomial exponents (DK <= 2)
+};
+
+__device__ __forceinline__ double binom_small(int n, int k) {
+  // n <= 2
+  return (k == 0 || k == n) ? 1.0 : (double)n;
+}
+
+// T_d[m][i] for unknown block d (tap index) and monomials m, i
+__device__ __forceinline__ double outpix_t(const OutpixArgs& a, int d, int m, int i) {
+  const int am = a.ea[m], bm = a.eb[m], ai = a.ea[i], bi = a.eb[i];
+  if (am > ai || bm > bi) return 0.0;
+  const int dx = d % a.L - a.r, dy = d / a.L - a.r;
+  const double ex = a.W > 1 ? 2.0 * dx / (double)(a.W - 1) : 0.0;
+  const double ey = a.H > 1 ? 2.0 * dy / (double)(a.H - 1) : 0.0;
+  double v = binom_small(ai, am) * binom_small(bi, bm);
+  for (int k = am; k < ai; ++k) v *= ex;
+  for (int k = bm; k < bi; ++k) v *= ey;
+  return v;
+}
+
+// one thread per entry of G_out (and of h_out on row N); fixed summation order
+__global__ __launch_bounds__(256) void k_outpix_transform(OutpixArgs a) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = (int64_t)a.N * a.N + a.N;
+  if (idx >= total) return;
+  const int LL = a.L * a.L, nKL = a.nK * LL;
+  if (idx >= (int64_t)a.N * a.N) {
+    const int p = (int)(idx - (int64_t)a.N * a.N);
+    double v;
+    if (p >= nKL) {
+      v = a.hi[p];
+    } else {
+      const int i = p / LL, d = p % LL;
+      v = 0.0;
+      for (int m = 0; m < a.nK; ++m) {
+        const double t = outpix_t(a, d, m, i);
+        if (t != 0.0) v = fma(t, a.hi[m * LL + d], v);
+      }
+    }
+    a.hv[p] = v;
+    return;
+  }
+  const int p = (int)(idx / a.N), q = (int)(idx % a.N);
+  const int ip = p < nKL ? p / LL : -1, dp = p % LL;
+  const int iq = q < nKL ? q / LL : -1, dq = q % LL;
+  double v = 0.0;
+  for (int m = 0; m < (ip >= 0 ? a.nK : 1); ++m) {
+    const double tp = ip >= 0 ? outpix_t(a, dp, m, ip) : 1.0;
+    if (tp == 0.0) continue;
+    const int row = ip >= 0 ? m * LL + dp : p;
+    double u = 0.0;
+    for (int n = 0; n < (iq >= 0 ? a.nK : 1); ++n) {
+      const double tq = iq >= 0 ? outpix_t(a, dq, n, iq) : 1.0;
+      if (tq == 0.0) continue;
+      const int col = iq >= 0 ? n * LL + dq : q;
+      u = fma(tq, a.Gi[(int64_t)row * a.N + col], u);
+    }
+    v = fma(tp, u, v);
+  }
+  a.G[(int64_t)p * a.N + q] = v;
+}
+
 // The science image's row spectrum (the last plane of F), its DC / Nyquist
 // values, its row moments and its non-finite bit survive a solve and a
 // subtract in the same workspace when the solve and subtract regions end
@@ -1329,11 +1452,22 @@ bool sci_reusable(const sfft_desc& d) {
   return l.solve_end <= sci_plane && l.sub_end <= sci_plane;
 }
 
+hipError_t launch_build_masked(const sfft_desc& d, const void* R, const void* S, const unsigned char* mask,
+                               int64_t mask_ld, double* G, double* hv, unsigned char* ws, const BuildPlan& p,
+                               const Prof* pf, hipStream_t st, bool reuse_sci);
+
 hipError_t launch_build(const sfft_desc& d, const void* R, const void* S, double* G, double* hv,
                         unsigned char* ws, const BuildPlan& p, const Prof* pf, hipStream_t st,
                         bool reuse_sci) {
+  return launch_build_masked(d, R, S, nullptr, 0, G, hv, ws, p, pf, st, reuse_sci);
+}
+
+hipError_t launch_build_masked(const sfft_desc& d, const void* R, const void* S, const unsigned char* mask,
+                               int64_t mask_ld, double* G, double* hv, unsigned char* ws, const BuildPlan& p,
+                               const Prof* pf, hipStream_t st, bool reuse_sci) {
   const Geometry g = make_geometry(d);
   const Layout l = make_layout(g);
+  const bool outpix = d.convention == 1;
   hipError_t e;
   prof_begin(pf, SFFT_PROF_BUILD, st);
   if (reuse_sci)
@@ -1346,6 +1480,9 @@ hipError_t launch_build(const sfft_desc& d, const void* R, const void* S, double
   {
     RowArgs ra = make_row_args(g, d, R, S, ws, l, p);
     ra.sci = reuse_sci ? 0 : 1;
+    ra.mask = mask;
+    ra.mask_ld = mask_ld;
+    ra.frame = outpix ? g.r : 0;
     if (d.image_dtype == SFFT_F32)
       hipLaunchKernelGGL(k_row_moments<float>, dim3(row_moments_grid(g.H)), dim3(kRowThreads), 0, st, ra);
     else
@@ -1353,8 +1490,8 @@ hipError_t launch_build(const sfft_desc& d, const void* R, const void* S, double
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   prof_begin(pf, SFFT_PROF_ROW_PASS, st);
-  e = g.fp32 ? launch_row<float>(g, d, R, S, ws, l, p, st, reuse_sci)
-             : launch_row<double>(g, d, R, S, ws, l, p, st, reuse_sci);
+  e = g.fp32 ? launch_row<float>(g, d, R, S, ws, l, p, st, reuse_sci, mask, mask_ld, outpix ? g.r : 0)
+             : launch_row<double>(g, d, R, S, ws, l, p, st, reuse_sci, mask, mask_ld, outpix ? g.r : 0);
   prof_end(pf, SFFT_PROF_ROW_PASS, st);
   if (e != hipSuccess) return e;
   prof_begin(pf, SFFT_PROF_COL_PASS, st);
@@ -1380,8 +1517,26 @@ hipError_t launch_build(const sfft_desc& d, const void* R, const void* S, double
   const GatherArgs ga = make_gather_args(g, xa, G, hv);
   const int nKL = g.nK * g.L * g.L;
   hipLaunchKernelGGL(k_gather_kk, dim3((nKL + 255) / 256, nKL), dim3(256), 0, st, ga);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (outpix && g.DK > 0) {
+    // the input-pixel system is copied aside into the solve's matrix region
+    // (N^2 + N doubles fit in it; every build kernel that used it is done)
+    double* Gi = reinterpret_cast<double*>(ws + l.A);
+    double* hi = Gi + (int64_t)g.N * g.N;
+    if ((e = hipMemcpyAsync(Gi, G, sizeof(double) * g.N * g.N, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+      return e;
+    if ((e = hipMemcpyAsync(hi, hv, sizeof(double) * g.N, hipMemcpyDeviceToDevice, st)) != hipSuccess) return e;
+    OutpixArgs oa{};
+    oa.Gi = Gi; oa.hi = hi; oa.G = G; oa.hv = hv;
+    oa.N = g.N; oa.L = g.L; oa.r = g.r; oa.nK = g.nK; oa.W = g.W; oa.H = g.H;
+    const MonoTable mt = make_monos(g.DK);
+    for (int i = 0; i < g.nK; ++i) { oa.ea[i] = mt.a[i]; oa.eb[i] = mt.b[i]; }
+    const int64_t total = (int64_t)g.N * g.N + g.N;
+    hipLaunchKernelGGL(k_outpix_transform, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, oa);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   prof_end(pf, SFFT_PROF_BUILD, st);
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------

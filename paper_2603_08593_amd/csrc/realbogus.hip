@@ -1,0 +1,366 @@
+// Real-bogus scorer inference (paper Sec. 2.3.4): a rotation-invariant
+// convolutional network with residual connections scores three-channel
+// (science, template, difference) stamps of candidates. Layer sizes (not
+// published; the reading documented with the C declarations): per rotated copy
+// of a 32 x 32 stamp, stem conv 3 -> 32, residual block 32, strided residual
+// blocks 64 and 128 with 1x1 projections, global average pool; the four
+// copies' features averaged; linear 128 -> 64, ReLU, linear 64 -> 1.
+//
+// The convolutions run as implicit GEMMs on the bf16 matrix cores
+// (v_mfma_f32_16x16x32_bf16): rows = output pixels of all copies (NHWC
+// activations, bf16), columns = output channels, k = (tap, input channel)
+// with the input channels padded to a multiple of 8 so that every lane's 8
+// consecutive k values are one 16-byte load of one pixel; a block's 1x1
+// projection shortcut is appended to the same k range (one accumulator), an
+// identity shortcut is added in the epilogue. FP32 accumulation; bias,
+// shortcut, ReLU and the rounding to bf16 in the epilogue. Each wave computes
+// 64 output pixels x all output channels, so a weight load serves four
+// matrix-core tiles and an activation load COUT / 16 of them.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.hpp"
+#include "layout.hpp"
+#include "realbogus.hpp"
+
+namespace sfft {
+
+typedef __bf16 bf16x8_rb __attribute__((ext_vector_type(8)));
+typedef float floatx4_rb __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short f32_to_bf16_rne(float f) {
+  const unsigned u = __builtin_bit_cast(unsigned, f);
+  return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) {
+  return __builtin_bit_cast(float, (unsigned)h << 16);
+}
+
+// ---------------------------------------------------------------------------
+// weights: FP32 [out][in][ky][kx] (+ projection [out][in]) -> bf16 [out][KP]
+// with k = tap * CINP + c for the 3x3 part and 9 CINP + c for the projection
+// ---------------------------------------------------------------------------
+
+struct RbPackArgs {
+  const float* w;        // main conv weights [co][ci][3][3]
+  const float* b;        // main bias [co]
+  const float* wp;       // projection [co][cip] or null
+  const float* bp;       // projection bias or null
+  unsigned short* out;   // [co][KP]
+  float* bias;           // [co]
+  int co, ci, cinp, cip, cipp, KP;
+};
+
+__global__ __launch_bounds__(256) void k_rb_pack(RbPackArgs a) {
+  const int64_t total = (int64_t)a.co * a.KP;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+    const int o = (int)(i / a.KP), k = (int)(i % a.KP);
+    float v = 0.0f;
+    if (k < 9 * a.cinp) {
+      const int tap = k / a.cinp, c = k % a.cinp;
+      if (c < a.ci) v = a.w[((int64_t)o * a.ci + c) * 9 + tap];
+    } else if (a.wp && k < 9 * a.cinp + a.cipp) {
+      const int c = k - 9 * a.cinp;
+      if (c < a.cip) v = a.wp[(int64_t)o * a.cip + c];
+    }
+    a.out[i] = f32_to_bf16_rne(v);
+    if (k == 0) a.bias[o] = a.b[o] + (a.bp ? a.bp[o] : 0.0f);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// input: stamps FP32 [n][3][32][32] -> bf16 NHWC [4n][32][32][8], copy
+// 4k + rot = the stamp rotated by rot quarter turns (numpy's rot90 on the
+// two image axes: out[i][j] = s[j][31 - i] for one turn)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_rb_input(const float* stamps, int n, unsigned short* x0) {
+  const int64_t total = (int64_t)n * 4 * kRbStamp * kRbStamp;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= total) return;
+  const int j = (int)(i % kRbStamp);
+  const int r = (int)((i / kRbStamp) % kRbStamp);
+  const int copy = (int)(i / (kRbStamp * kRbStamp));
+  const int k = copy >> 2, rot = copy & 3;
+  constexpr int e = kRbStamp - 1;
+  int sy, sx;
+  switch (rot) {
+    case 0: sy = r; sx = j; break;
+    case 1: sy = j; sx = e - r; break;
+    case 2: sy = e - r; sx = e - j; break;
+    default: sy = e - j; sx = r; break;
+  }
+  unsigned short v[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+    v[c] = c < 3 ? f32_to_bf16_rne(stamps[(((int64_t)k * 3 + c) * kRbStamp + sy) * kRbStamp + sx]) : 0;
+  uint4 pk;
+  pk.x = v[0] | ((unsigned)v[1] << 16);
+  pk.y = v[2] | ((unsigned)v[3] << 16);
+  pk.z = v[4] | ((unsigned)v[5] << 16);
+  pk.w = v[6] | ((unsigned)v[7] << 16);
+  reinterpret_cast<uint4*>(x0)[i] = pk;
+}
+
+// ---------------------------------------------------------------------------
+// implicit-GEMM convolution
+// ---------------------------------------------------------------------------
+
+constexpr int kRbThreads = 256;
+constexpr int kRbMT = 4;                   // 16-pixel row tiles per wave
+constexpr int kRbPix = 64 * kRbMT;         // output pixels per workgroup (4 waves x 64)
+
+// an output pixel's copy index and coordinates (or img = -1 past the end)
+struct RbPix {
+  int img, oy, ox;
+};
+
+__device__ __forceinline__ RbPix rb_pix(const RbConvArgs& a, int P) {
+  if (P >= a.npix) return RbPix{-1, 0, 0};
+  const int hw = a.Ho * a.Wo;
+  const int img = P / hw, rem = P - img * hw;
+  const int oy = rem / a.Wo;
+  return RbPix{img, oy, rem - oy * a.Wo};
+}
+
+// 8 bf16 of k-chunk lane group g for output pixel q: the 3x3 part from x,
+// the projection part from x2, zeros past either (and for padding taps)
+__device__ __forceinline__ uint4 rb_load_a(const RbConvArgs& a, const RbPix& q, int k0) {
+  const uint4 zero = {0u, 0u, 0u, 0u};
+  if (q.img < 0) return zero;
+  if (k0 < 9 * a.cinp) {
+    const int tap = k0 / a.cinp, c0 = k0 - tap * a.cinp;
+    const int ky = tap / 3, kx = tap - ky * 3;
+    const int iy = q.oy * a.stride + ky - 1, ix = q.ox * a.stride + kx - 1;
+    if (iy < 0 || iy >= a.H || ix < 0 || ix >= a.W) return zero;
+    return *reinterpret_cast<const uint4*>(a.x + (((int64_t)q.img * a.H + iy) * a.W + ix) * a.cinp + c0);
+  }
+  const int c0 = k0 - 9 * a.cinp;
+  if (!a.x2 || c0 >= a.cinp2) return zero;
+  const int iy = q.oy * a.stride2, ix = q.ox * a.stride2;
+  return *reinterpret_cast<const uint4*>(a.x2 + (((int64_t)q.img * a.H2 + iy) * a.W2 + ix) * a.cinp2 + c0);
+}
+
+template <int COUT>
+__global__ __launch_bounds__(kRbThreads) void k_rb_conv(RbConvArgs a) {
+  constexpr int NT = COUT / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, g = lane >> 4;
+  const int base = blockIdx.x * kRbPix + wave * 64;
+  floatx4_rb acc[kRbMT][NT];
+#pragma unroll
+  for (int m = 0; m < kRbMT; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = floatx4_rb{0.f, 0.f, 0.f, 0.f};
+  const int nkc = a.KP / 32;
+  RbPix px[kRbMT];
+#pragma unroll
+  for (int m = 0; m < kRbMT; ++m) px[m] = rb_pix(a, base + 16 * m + l16);
+  uint4 A[kRbMT], B[NT], An[kRbMT], Bn[NT];
+  auto load = [&](int kc, uint4 (&As)[kRbMT], uint4 (&Bs)[NT]) {
+    const int k0 = kc * 32 + 8 * g;
+#pragma unroll
+    for (int m = 0; m < kRbMT; ++m) As[m] = rb_load_a(a, px[m], k0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      Bs[t] = *reinterpret_cast<const uint4*>(a.w + (int64_t)(16 * t + l16) * a.KP + k0);
+  };
+  load(0, A, B);
+  for (int kc = 0; kc < nkc; ++kc) {
+    // the next chunk's loads are issued before this chunk's products
+    if (kc + 1 < nkc) load(kc + 1, An, Bn);
+#pragma unroll
+    for (int m = 0; m < kRbMT; ++m) {
+      const bf16x8_rb av = __builtin_bit_cast(bf16x8_rb, A[m]);
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf16x8_rb, B[t]), acc[m][t],
+                                                            0, 0, 0);
+    }
+    if (kc + 1 < nkc) {
+#pragma unroll
+      for (int m = 0; m < kRbMT; ++m) A[m] = An[m];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) B[t] = Bn[t];
+    }
+  }
+  // epilogue: lane (g, l16), element q -> pixel 16 m + 4 g + q, channel 16 t + l16
+#pragma unroll
+  for (int m = 0; m < kRbMT; ++m)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int P = base + 16 * m + 4 * g + q;
+      if (P >= a.npix) continue;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int co = 16 * t + l16;
+        float v = acc[m][t][q] + a.bias[co];
+        if (a.res) v += bf16_to_f32(a.res[(int64_t)P * COUT + co]);
+        v = fmaxf(v, 0.0f);
+        a.y[(int64_t)P * COUT + co] = f32_to_bf16_rne(v);
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// head: mean over the 8 x 8 pixels and the 4 copies, linear 128 -> 64, ReLU,
+// linear 64 -> 1, sigmoid. One workgroup of 128 threads per candidate, FP32,
+// fixed order.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(128) void k_rb_head(const unsigned short* a4, const float* w1, const float* b1,
+                                                 const float* w2, const float* b2, int n, float* logits,
+                                                 float* probs) {
+  __shared__ float f[128];
+  __shared__ float hbuf[64];
+  const int k = blockIdx.x, c = threadIdx.x;
+  if (k >= n) return;
+  float s = 0.0f;
+  for (int rot = 0; rot < 4; ++rot) {
+    const unsigned short* p = a4 + ((int64_t)(4 * k + rot) * 64) * 128 + c;
+    float sr = 0.0f;
+    for (int px = 0; px < 64; ++px) sr += bf16_to_f32(p[(int64_t)px * 128]);
+    s += sr * (1.0f / 64.0f);
+  }
+  f[c] = s * 0.25f;
+  __syncthreads();
+  if (c < 64) {
+    float v = b1[c];
+    for (int j = 0; j < 128; ++j) v = fmaf(w1[c * 128 + j], f[j], v);
+    hbuf[c] = fmaxf(v, 0.0f);
+  }
+  __syncthreads();
+  if (c == 0) {
+    float v = b2[0];
+    for (int j = 0; j < 64; ++j) v = fmaf(w2[j], hbuf[j], v);
+    logits[k] = v;
+    if (probs) probs[k] = 1.0f / (1.0f + expf(-v));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// stamp extraction: (I_c - offset_c) * scale_c on the 32 x 32 window
+// [cx - 16, cx + 16) x [cy - 16, cy + 16), periodic
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_rb_extract(RbExtractArgs a) {
+  const int64_t total = (int64_t)a.n * 3 * kRbStamp * kRbStamp;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= total) return;
+  const int j = (int)(i % kRbStamp), r = (int)((i / kRbStamp) % kRbStamp);
+  const int c = (int)((i / (kRbStamp * kRbStamp)) % 3), k = (int)(i / (3 * kRbStamp * kRbStamp));
+  int y = a.centers[2 * k + 1] - kRbStamp / 2 + r, x = a.centers[2 * k] - kRbStamp / 2 + j;
+  y %= a.H;
+  if (y < 0) y += a.H;
+  x %= a.W;
+  if (x < 0) x += a.W;
+  const T* img = static_cast<const T*>(a.img[c]);
+  a.stamps[i] = (float)(((double)img[(int64_t)y * a.ld + x] - (double)a.offset[c]) * (double)a.scale[c]);
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+RbPlan rb_plan(int n) {
+  RbPlan p{};
+  p.n = n;
+  const int64_t copies = 4 * (int64_t)n;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { const size_t at = o; o = align256(o + bytes); return at; };
+  for (int l = 0; l < kRbGemms; ++l) {
+    const RbGemm& gm = kRbGemm[l];
+    const int kp = (9 * gm.cinp + gm.cipp + 31) / 32 * 32;
+    p.KP[l] = kp;
+    p.w[l] = take((size_t)gm.co * kp * 2);
+    p.bias[l] = take((size_t)gm.co * 4);
+  }
+  p.x0 = take((size_t)copies * 32 * 32 * 8 * 2);
+  for (int b = 0; b < 3; ++b) p.act[b] = take((size_t)copies * 32 * 32 * 32 * 2);
+  p.total = o;
+  return p;
+}
+
+hipError_t launch_rb_score(const float* params, const float* stamps, int n, float* logits, float* probs,
+                           unsigned char* ws, hipStream_t st) {
+  const RbPlan p = rb_plan(n);
+  hipError_t e;
+  // pack the weights of every GEMM (main conv + projection)
+  for (int l = 0; l < kRbGemms; ++l) {
+    const RbGemm& gm = kRbGemm[l];
+    RbPackArgs pa{};
+    pa.w = params + gm.w_off;
+    pa.b = params + gm.b_off;
+    pa.wp = gm.wp_off >= 0 ? params + gm.wp_off : nullptr;
+    pa.bp = gm.bp_off >= 0 ? params + gm.bp_off : nullptr;
+    pa.out = reinterpret_cast<unsigned short*>(ws + p.w[l]);
+    pa.bias = reinterpret_cast<float*>(ws + p.bias[l]);
+    pa.co = gm.co; pa.ci = gm.ci; pa.cinp = gm.cinp; pa.cip = gm.cip; pa.cipp = gm.cipp; pa.KP = p.KP[l];
+    const int64_t total = (int64_t)gm.co * p.KP[l];
+    hipLaunchKernelGGL(k_rb_pack, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 4096)), dim3(256), 0,
+                       st, pa);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  const int64_t copies = 4 * (int64_t)n;
+  unsigned short* x0 = reinterpret_cast<unsigned short*>(ws + p.x0);
+  {
+    const int64_t total = copies * 32 * 32;
+    hipLaunchKernelGGL(k_rb_input, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, stamps, n, x0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  unsigned short* B0 = reinterpret_cast<unsigned short*>(ws + p.act[0]);
+  unsigned short* B1 = reinterpret_cast<unsigned short*>(ws + p.act[1]);
+  unsigned short* B2 = reinterpret_cast<unsigned short*>(ws + p.act[2]);
+  // (input, H, projection input, H2, residual, output) per GEMM
+  struct Step { const unsigned short* x; int H; const unsigned short* x2; int H2; const unsigned short* res;
+                unsigned short* y; };
+  const Step steps[kRbGemms] = {
+      {x0, 32, nullptr, 0, nullptr, B0},       // stem            -> a1 (B0)
+      {B0, 32, nullptr, 0, nullptr, B1},       // block 1 conv a  -> t  (B1)
+      {B1, 32, nullptr, 0, B0, B2},            // block 1 conv b + a1 -> a2 (B2)
+      {B2, 32, nullptr, 0, nullptr, B0},       // block 2 conv a  -> t16 (B0)
+      {B0, 16, B2, 32, nullptr, B1},           // block 2 conv b + proj(a2) -> a3 (B1)
+      {B1, 16, nullptr, 0, nullptr, B0},       // block 3 conv a  -> t8 (B0)
+      {B0, 8, B1, 16, nullptr, B2},            // block 3 conv b + proj(a3) -> a4 (B2)
+  };
+  for (int l = 0; l < kRbGemms; ++l) {
+    const RbGemm& gm = kRbGemm[l];
+    const Step& s = steps[l];
+    RbConvArgs ca{};
+    ca.x = s.x; ca.x2 = s.x2; ca.res = s.res; ca.y = s.y;
+    ca.w = reinterpret_cast<const unsigned short*>(ws + p.w[l]);
+    ca.bias = reinterpret_cast<const float*>(ws + p.bias[l]);
+    ca.H = ca.W = s.H;
+    ca.cinp = gm.cinp;
+    ca.stride = gm.stride;
+    ca.Ho = ca.Wo = s.H / gm.stride;
+    ca.H2 = ca.W2 = s.H2;
+    ca.cinp2 = gm.cipp;
+    ca.stride2 = 2;
+    ca.KP = p.KP[l];
+    ca.npix = (int)(copies * ca.Ho * ca.Wo);
+    const dim3 grid((unsigned)((ca.npix + kRbPix - 1) / kRbPix));
+    switch (gm.co) {
+      case 32: hipLaunchKernelGGL(k_rb_conv<32>, grid, dim3(kRbThreads), 0, st, ca); break;
+      case 64: hipLaunchKernelGGL(k_rb_conv<64>, grid, dim3(kRbThreads), 0, st, ca); break;
+      case 128: hipLaunchKernelGGL(k_rb_conv<128>, grid, dim3(kRbThreads), 0, st, ca); break;
+      default: return hipErrorInvalidValue;
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_rb_head, dim3(n), dim3(128), 0, st, B2, params + kRbFc1W, params + kRbFc1B,
+                     params + kRbFc2W, params + kRbFc2B, n, logits, probs);
+  return hipGetLastError();
+}
+
+hipError_t launch_rb_extract(const RbExtractArgs& a, bool f32, hipStream_t st) {
+  const int64_t total = (int64_t)a.n * 3 * 32 * 32;
+  const dim3 grid((unsigned)((total + 255) / 256));
+  if (f32) hipLaunchKernelGGL(k_rb_extract<float>, grid, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL(k_rb_extract<double>, grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace sfft

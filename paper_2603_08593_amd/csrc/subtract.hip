@@ -93,7 +93,10 @@ __device__ __forceinline__ void kappa2_body(const SubArgs& a) {
 __global__ __launch_bounds__(kK2Threads) void k_kappa2(SubArgs a) { kappa2_body(a); }
 __global__ __launch_bounds__(kK2Threads) void k_kappa2_batch(const SubArgs* args) { kappa2_body(args[blockIdx.x]); }
 
-template <int L, int DK, typename TIO>
+// OUTPIX: the kernel polynomial is evaluated at the output pixel x (the
+// output-pixel convention) instead of the input pixel x - d: the Horner
+// coordinates are those of the output row and pixel.
+template <int L, int DK, typename TIO, bool OUTPIX = false>
 __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
   constexpr int r = (L - 1) / 2;
   constexpr int NK = (DK + 1) * (DK + 2) / 2;
@@ -148,6 +151,11 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
   double acc[P];
 #pragma unroll
   for (int p = 0; p < P; ++p) acc[p] = 0.0;
+  // output-pixel convention: xt of the thread's own pixels (no wrap needed;
+  // values of pixels past the image are never stored)
+  double xo[OUTPIX ? P : 1];
+#pragma unroll
+  for (int p = 0; p < (OUTPIX ? P : 1); ++p) xo[p] = (double)(xb + p) * a.sx - 1.0;
 #pragma unroll 1
   for (int dyi = 0; dyi < L; ++dyi) {
     const int lr = ty + (L - 1 - dyi);           // local row of u_y = y - dy
@@ -155,7 +163,7 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
     uy = (uy < 0) ? uy + H : uy;
     uy = (uy >= H) ? uy - H : uy;
     uy = (uy >= H) ? uy - H : uy;
-    const double yt = (double)uy * a.sy - 1.0;
+    const double yt = OUTPIX ? (double)y * a.sy - 1.0 : (double)uy * a.sy - 1.0;
     double win[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) win[q] = Rt[lr][P * tx + q];
@@ -184,7 +192,7 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
 #pragma unroll
       for (int m = DK - 1; m >= 0; --m)
 #pragma unroll
-        for (int p = 0; p < P; ++p) w[p] = fma(w[p], xq[p + (L - 1 - dxi)], cm[m]);
+        for (int p = 0; p < P; ++p) w[p] = fma(w[p], OUTPIX ? xo[OUTPIX ? p : 0] : xq[p + (L - 1 - dxi)], cm[m]);
 #pragma unroll
       for (int p = 0; p < P; ++p) acc[p] = fma(w[p], win[p + (L - 1 - dxi)], acc[p]);
     }
@@ -264,9 +272,9 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
 template <int L, int DK>
 constexpr int subtract_waves() { return (DK == 0 || (DK == 2 && L >= 7 && L <= 11)) ? 4 : 1; }
 
-template <int L, int DK, typename TIO>
+template <int L, int DK, typename TIO, bool OUTPIX>
 __global__ __launch_bounds__(128, (subtract_waves<L, DK>())) void k_subtract(SubArgs a) {
-  subtract_body<L, DK, TIO>(a, vb_grid());
+  subtract_body<L, DK, TIO, OUTPIX>(a, vb_grid());
 }
 
 template <int L, int DK, typename TIO>
@@ -287,18 +295,24 @@ __global__ __launch_bounds__(1024) void k_chi2_final(const double* partials, int
 }
 
 template <int L, int DK>
-static hipError_t launch_sub_ldk(const SubArgs& a, bool f32, dim3 grid, hipStream_t st) {
-  if (f32) hipLaunchKernelGGL((k_subtract<L, DK, float>), grid, dim3(128), 0, st, a);
-  else hipLaunchKernelGGL((k_subtract<L, DK, double>), grid, dim3(128), 0, st, a);
+static hipError_t launch_sub_ldk(const SubArgs& a, bool f32, bool outpix, dim3 grid, hipStream_t st) {
+  if (outpix) {
+    if (f32) hipLaunchKernelGGL((k_subtract<L, DK, float, true>), grid, dim3(128), 0, st, a);
+    else hipLaunchKernelGGL((k_subtract<L, DK, double, true>), grid, dim3(128), 0, st, a);
+  } else {
+    if (f32) hipLaunchKernelGGL((k_subtract<L, DK, float, false>), grid, dim3(128), 0, st, a);
+    else hipLaunchKernelGGL((k_subtract<L, DK, double, false>), grid, dim3(128), 0, st, a);
+  }
   return hipGetLastError();
 }
 
 template <int L>
-static hipError_t launch_sub_l(const SubArgs& a, int DK, bool f32, dim3 grid, hipStream_t st) {
+static hipError_t launch_sub_l(const SubArgs& a, int DK, bool f32, bool outpix, dim3 grid, hipStream_t st) {
+  // DK = 0: the two conventions coincide (the polynomial is a constant)
   switch (DK) {
-    case 0: return launch_sub_ldk<L, 0>(a, f32, grid, st);
-    case 1: return launch_sub_ldk<L, 1>(a, f32, grid, st);
-    case 2: return launch_sub_ldk<L, 2>(a, f32, grid, st);
+    case 0: return launch_sub_ldk<L, 0>(a, f32, false, grid, st);
+    case 1: return launch_sub_ldk<L, 1>(a, f32, outpix, grid, st);
+    case 2: return launch_sub_ldk<L, 2>(a, f32, outpix, grid, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -339,14 +353,14 @@ hipError_t launch_subtract(const sfft_desc& d, const void* R, const void* S, con
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   switch (g.L) {
-    case 1: e = launch_sub_l<1>(a, g.DK, f32, grid, st); break;
-    case 3: e = launch_sub_l<3>(a, g.DK, f32, grid, st); break;
-    case 5: e = launch_sub_l<5>(a, g.DK, f32, grid, st); break;
-    case 7: e = launch_sub_l<7>(a, g.DK, f32, grid, st); break;
-    case 9: e = launch_sub_l<9>(a, g.DK, f32, grid, st); break;
-    case 11: e = launch_sub_l<11>(a, g.DK, f32, grid, st); break;
-    case 13: e = launch_sub_l<13>(a, g.DK, f32, grid, st); break;
-    case 15: e = launch_sub_l<15>(a, g.DK, f32, grid, st); break;
+    case 1: e = launch_sub_l<1>(a, g.DK, f32, d.convention == 1, grid, st); break;
+    case 3: e = launch_sub_l<3>(a, g.DK, f32, d.convention == 1, grid, st); break;
+    case 5: e = launch_sub_l<5>(a, g.DK, f32, d.convention == 1, grid, st); break;
+    case 7: e = launch_sub_l<7>(a, g.DK, f32, d.convention == 1, grid, st); break;
+    case 9: e = launch_sub_l<9>(a, g.DK, f32, d.convention == 1, grid, st); break;
+    case 11: e = launch_sub_l<11>(a, g.DK, f32, d.convention == 1, grid, st); break;
+    case 13: e = launch_sub_l<13>(a, g.DK, f32, d.convention == 1, grid, st); break;
+    case 15: e = launch_sub_l<15>(a, g.DK, f32, d.convention == 1, grid, st); break;
     default: return hipErrorInvalidValue;
   }
   prof_end(pf, SFFT_PROF_SUBTRACT, st);
@@ -409,14 +423,14 @@ hipError_t launch_subtract_noalloc(int device, const sfft_desc& d, const void* R
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   switch (g.L) {
-    case 1: e = launch_sub_l<1>(a, g.DK, f32, grid, st); break;
-    case 3: e = launch_sub_l<3>(a, g.DK, f32, grid, st); break;
-    case 5: e = launch_sub_l<5>(a, g.DK, f32, grid, st); break;
-    case 7: e = launch_sub_l<7>(a, g.DK, f32, grid, st); break;
-    case 9: e = launch_sub_l<9>(a, g.DK, f32, grid, st); break;
-    case 11: e = launch_sub_l<11>(a, g.DK, f32, grid, st); break;
-    case 13: e = launch_sub_l<13>(a, g.DK, f32, grid, st); break;
-    case 15: e = launch_sub_l<15>(a, g.DK, f32, grid, st); break;
+    case 1: e = launch_sub_l<1>(a, g.DK, f32, d.convention == 1, grid, st); break;
+    case 3: e = launch_sub_l<3>(a, g.DK, f32, d.convention == 1, grid, st); break;
+    case 5: e = launch_sub_l<5>(a, g.DK, f32, d.convention == 1, grid, st); break;
+    case 7: e = launch_sub_l<7>(a, g.DK, f32, d.convention == 1, grid, st); break;
+    case 9: e = launch_sub_l<9>(a, g.DK, f32, d.convention == 1, grid, st); break;
+    case 11: e = launch_sub_l<11>(a, g.DK, f32, d.convention == 1, grid, st); break;
+    case 13: e = launch_sub_l<13>(a, g.DK, f32, d.convention == 1, grid, st); break;
+    case 15: e = launch_sub_l<15>(a, g.DK, f32, d.convention == 1, grid, st); break;
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;

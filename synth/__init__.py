@@ -401,3 +401,38 @@ def background_positions(W, H, n, radius, *, seed, avoid=None, avoid_radius=0.0)
             continue
         out.append((x, y))
     return np.asarray(out, dtype=np.float64)
+
+
+def rb_init(seed: int, n_params: int = 315009) -> np.ndarray:
+    """Seeded random parameters of the real-bogus scorer as one flat FP32
+    vector in its parameter layout: conv and
+    linear weights uniform in +-sqrt(6 / fan_in) (He), biases uniform in
+    +-0.05. The layout: conv (out, in, k) in the order stem (32, 3, 3),
+    b1a (32, 32, 3), b1b (32, 32, 3), b2a (64, 32, 3), b2b (64, 64, 3),
+    b2p (64, 32, 1), b3a (128, 64, 3), b3b (128, 128, 3), b3p (128, 64, 1),
+    each weight then bias; fc1 (64, 128), fc2 (1, 64)."""
+    rng = np.random.default_rng(seed)
+    convs = [(32, 3, 3), (32, 32, 3), (32, 32, 3), (64, 32, 3), (64, 64, 3), (64, 32, 1),
+             (128, 64, 3), (128, 128, 3), (128, 64, 1)]
+    parts = []
+    for co, ci, k in convs:
+        fan = ci * k * k
+        parts.append(rng.uniform(-1, 1, co * ci * k * k) * math.sqrt(6.0 / fan))
+        parts.append(rng.uniform(-0.05, 0.05, co))
+    for co, ci in ((64, 128), (1, 64)):
+        parts.append(rng.uniform(-1, 1, co * ci) * math.sqrt(6.0 / ci))
+        parts.append(rng.uniform(-0.05, 0.05, co))
+    p = np.concatenate(parts).astype(np.float32)
+    assert p.size == n_params
+    return p
+
+
+def rb_candidates(pair_or_shape, n, *, seed, margin=20):
+    """n candidate centres (x, y) (int32) uniformly inside the image, at least
+    `margin` px from the edges (positions of detections on a difference image
+    stand in for a detector's output)."""
+    H, W = pair_or_shape
+    rng = np.random.Generator(np.random.PCG64(seed))
+    xs = rng.integers(margin, W - margin, n)
+    ys = rng.integers(margin, H - margin, n)
+    return np.stack([xs, ys], axis=1).astype(np.int32)

@@ -58,6 +58,9 @@ def test_validation_codes():
     assert sf.sfft_validate(sf.make_desc(95, 64, 5, 0, 0)) == sf.SFFT_ERR_UNSUPPORTED    # W odd
     assert sf.sfft_validate(sf.make_desc(96, 64, 5, 0, 0)) == sf.SFFT_OK                 # 2^5 3
     assert sf.sfft_validate(sf.make_desc(1500, 64, 5, 0, 0)) == sf.SFFT_OK               # 2^2 3 5^3
+    out = sf.make_desc(2048, 4096, 11, 2, 2, convention=sf.SFFT_CONV_OUTPUT_PIXEL)
+    assert sf.sfft_validate(out) == sf.SFFT_OK                                          # output-pixel convention
+    assert sf.sfft_validate(sf.make_desc(64, 64, 5, 0, 0, convention=2)) == sf.SFFT_ERR_INVALID_ARG
     assert sf.sfft_validate(sf.make_desc(64, 64, 5, 3, 0)) == sf.SFFT_ERR_UNSUPPORTED    # DK = 3
     assert sf.sfft_validate(sf.make_desc(64, 64, 17, 0, 0)) == sf.SFFT_ERR_UNSUPPORTED   # L > 15
     assert sf.sfft_validate(sf.make_desc(16, 64, 11, 0, 0)) == sf.SFFT_ERR_UNSUPPORTED   # W < 2L
