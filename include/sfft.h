@@ -190,7 +190,7 @@ sfft_status sfft_subtract(sfft_handle handle, const sfft_desc* desc,
  * forbid allocation). The chi2 partial sums and kappa2 coefficients live in
  * a fixed library-owned device array (one per GPU, about 0.5 MB, held until
  * the process ends); the call allocates nothing. Limit: at most 65536 output
- * tiles of 64 x 16 pixels (ceil(W/64) * ceil(H/16) <= 65536, e.g. 4096 x
+ * tiles of 64 x 32 pixels (ceil(W/64) * ceil(H/32) <= 65536, e.g. 8192 x
  * 16384), else SFFT_ERR_WORKSPACE. Calls that overlap on one GPU share the
  * array and race (order them on one stream). Results are identical to
  * sfft_subtract's. */
@@ -326,11 +326,10 @@ sfft_status sfft_median_combine(sfft_handle handle, const sfft_desc* desc, const
  * sfft_build_system (reference refs[t], pedestal ref_pedestals[t] when that
  * host array is non-NULL, else desc's), sfft_solve (max_refine steps) and
  * sfft_subtract into diffs[t] with its chi2, then sfft_median_combine into
- * `combined`. The science image's row spectrum and row moments are computed
- * by the first template's build and reused by the others (when the
- * workspace layout keeps them across the solve; otherwise every build takes
- * them again). All templates share desc's L, DK, DB, compute and science
- * pedestal.
+ * `combined`. The science image's row spectrum is computed by the first
+ * template's build and reused by the others (when the workspace layout keeps
+ * it across the solve; otherwise every build transforms it again). All
+ * templates share desc's L, DK, DB, compute, convention and science pedestal.
  *   refs, diffs : host arrays of n device image pointers (diffs written)
  *   G, h        : device scratch, N*N and N doubles (hold the last template's system)
  *   coefs       : device, n*N doubles (template t at t*N)

@@ -37,14 +37,6 @@ __global__ void k_fill_i32(int* p, int n, int v) {
   if (i < n) p[i] = v;
 }
 
-// Clears the flag words of a build that reuses the science image's spectra
-// and moments from an earlier build in the same workspace: the science
-// image's non-finite bit (kNonfiniteSci) of word 0 is kept, since that image
-// is not read again.
-__global__ void k_clear_flags_keep_sci(int* p, int n) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = (i == 0) ? (p[0] & kNonfiniteSci) : 0;
-}
 
 __device__ __forceinline__ double ipow(double x, int n) {
   double r = 1.0;
@@ -163,8 +155,8 @@ struct RowArgs {
   int* flags;
   const void* twW;    // cx<T>[W]
   double* edge;       // [nsig][2][H]: real k_x = 0 and k_x = W/2 values
-  int sci;            // 1: transform S' and take its moments; 0: they are
-                      // already in the workspace (a second template)
+  int sci;            // row pass: 1: transform S'; 0: its spectrum is already
+                      // in the workspace (a second template against it)
   // masked fit: R' and S' are taken as zero where mask[y * mask_ld + x] == 0
   // (null: no mask); R' also on the `frame`-pixel border (output-pixel
   // convention: frame = r, else 0)
@@ -181,7 +173,9 @@ __device__ __forceinline__ void pixel_mask(const RowArgs& a, int x, int y, bool&
 }
 
 // NQ: row elements per thread, max(1, ceil(W / 256)); MIXED: W has factors 3 or 5
-template <typename T, typename TIN, int NQ, bool MIXED, bool PF>
+// MASK: the build applies a mask or the output-pixel frame (RowArgs::mask,
+// ::frame); a separate instantiation, so that the plain path carries none of it
+template <typename T, typename TIN, int NQ, bool MIXED, bool PF, bool MASK = false>
 __device__ __forceinline__ void row_pass_body(const RowArgs& a, const VB vb) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int W = a.W;
@@ -246,7 +240,7 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const VB vb) {
         if (x < W) {
           const double xt = (double)x * a.sx - 1.0;
           double rv = (double)rc[q] - a.cR, sv = (double)sc[q] - a.cS;
-          if (a.mask || a.frame) {
+          if (MASK) {
             bool mr, ms;
             pixel_mask(a, x, y, mr, ms);
             rv = mr ? rv : 0.0;
@@ -280,9 +274,9 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const VB vb) {
   }
 }
 
-template <typename T, typename TIN, int NQ, bool MIXED>
+template <typename T, typename TIN, int NQ, bool MIXED, bool MASK>
 __global__ __launch_bounds__(kRowThreads, NQ >= 16 ? 2 : 3) void k_row_pass(RowArgs a) {
-  row_pass_body<T, TIN, NQ, MIXED, true>(a, vb_grid());
+  row_pass_body<T, TIN, NQ, MIXED, true, MASK>(a, vb_grid());
 }
 
 template <typename T, typename TIN, int NQ, bool MIXED>
@@ -973,7 +967,7 @@ __global__ __launch_bounds__(256) void k_gather_kk_batch(const GatherArgs* args,
 constexpr int kMomRowsPerWave = 2;
 constexpr int kMomRowsPerWG = kMomRowsPerWave * (kRowThreads / 64);
 
-template <typename TIN>
+template <typename TIN, bool MASK = false>
 __device__ __forceinline__ void row_moments_body(const RowArgs& a, const VB vb) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rr = lane >> 5, cc = lane & 31;
@@ -988,17 +982,16 @@ __device__ __forceinline__ void row_moments_body(const RowArgs& a, const VB vb) 
   for (int m = 0; m < kMR; ++m) mr[m] = 0.0;
 #pragma unroll
   for (int m = 0; m < kMS; ++m) ms[m] = 0.0;
-  bool bad_r = false, bad_s = false;
+  bool bad = false;
   auto accumulate = [&](int x, double rv, double sv) {
-    if (a.mask || a.frame) {
+    if (MASK) {
       // pixels outside the mask are not part of the fit (nor of the check)
       bool mr, ms;
       pixel_mask(a, x, y, mr, ms);
       rv = mr ? rv : 0.0;
       sv = ms ? sv : 0.0;
     }
-    bad_r |= !is_finite_d(rv);
-    bad_s |= !is_finite_d(sv);
+    bad |= !(is_finite_d(rv) && is_finite_d(sv));
     const double xt = (double)x * a.sx - 1.0;
     double pw = 1.0;
 #pragma unroll
@@ -1014,7 +1007,7 @@ __device__ __forceinline__ void row_moments_body(const RowArgs& a, const VB vb) 
     for (int e = cc; e < 2 * a.r; e += 32) {
       const int x = e < a.r ? e : W - 2 * a.r + e;
       double ev = (double)Rr[x] - a.cR;
-      if (a.mask || a.frame) {
+      if (MASK) {
         bool mr, ms;
         pixel_mask(a, x, y, mr, ms);
         ev = mr ? ev : 0.0;
@@ -1025,9 +1018,6 @@ __device__ __forceinline__ void row_moments_body(const RowArgs& a, const VB vb) 
   if (y < a.H) {
     const TIN* Rr = static_cast<const TIN*>(a.R) + (int64_t)y * a.ld;
     const TIN* Sr = static_cast<const TIN*>(a.S) + (int64_t)y * a.ld;
-    // with a.sci == 0 the science image is not read (its moments are kept
-    // from an earlier build): its pixels enter as zeros and MS is not written
-    const bool sci = a.sci != 0;
     const bool vec = sizeof(TIN) == 4 && ((reinterpret_cast<uintptr_t>(Rr) | reinterpret_cast<uintptr_t>(Sr)) & 15) == 0;
     // 4 spans of 128 pixels per round; the next round's loads are issued
     // before this round's pixels are accumulated
@@ -1038,14 +1028,14 @@ __device__ __forceinline__ void row_moments_body(const RowArgs& a, const VB vb) 
         const int x0 = x00 + u * 128 + cc * 4;
         if (vec && x0 + 3 < W) {
           const float4 r4 = *reinterpret_cast<const float4*>(Rr + x0);
-          const float4 s4 = sci ? *reinterpret_cast<const float4*>(Sr + x0) : float4{0.f, 0.f, 0.f, 0.f};
+          const float4 s4 = *reinterpret_cast<const float4*>(Sr + x0);
           rr[u][0] = r4.x; rr[u][1] = r4.y; rr[u][2] = r4.z; rr[u][3] = r4.w;
           ss[u][0] = s4.x; ss[u][1] = s4.y; ss[u][2] = s4.z; ss[u][3] = s4.w;
         } else {
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             rr[u][k] = (x0 + k < W) ? Rr[x0 + k] : (TIN)0;
-            ss[u][k] = (sci && x0 + k < W) ? Sr[x0 + k] : (TIN)0;
+            ss[u][k] = (x0 + k < W) ? Sr[x0 + k] : (TIN)0;
           }
         }
       }
@@ -1065,20 +1055,19 @@ __device__ __forceinline__ void row_moments_body(const RowArgs& a, const VB vb) 
         for (int u = 0; u < 4; ++u)
 #pragma unroll
           for (int k = 0; k < 4; ++k)
-            accumulate(x00 + u * 128 + cc * 4 + k, (double)rv[u][k] - a.cR, (double)sv[u][k] - (sci ? a.cS : 0.0));
+            accumulate(x00 + u * 128 + cc * 4 + k, (double)rv[u][k] - a.cR, (double)sv[u][k] - a.cS);
       } else {
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             const int x = x00 + u * 128 + cc * 4 + k;
-            if (x < W) accumulate(x, (double)rv[u][k] - a.cR, (double)sv[u][k] - (sci ? a.cS : 0.0));
+            if (x < W) accumulate(x, (double)rv[u][k] - a.cR, (double)sv[u][k] - a.cS);
           }
       }
     }
   }
-  if (bad_r) atomicOr(a.flags, kNonfiniteRef);
-  if (bad_s) atomicOr(a.flags, kNonfiniteSci);
+  if (bad) atomicOr(a.flags, 1);
   // sum over the 32 lanes of each row (fixed order: butterfly 16, 8, 4, 2, 1)
 #pragma unroll
   for (int m = 0; m < kMR; ++m) {
@@ -1091,7 +1080,7 @@ __device__ __forceinline__ void row_moments_body(const RowArgs& a, const VB vb) 
   }
 #pragma unroll
   for (int m = 0; m < kMS; ++m) {
-    if (m <= a.DB && a.sci) {
+    if (m <= a.DB) {
       double v = ms[m];
 #pragma unroll
       for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 32);
@@ -1100,9 +1089,9 @@ __device__ __forceinline__ void row_moments_body(const RowArgs& a, const VB vb) 
   }
 }
 
-template <typename TIN>
+template <typename TIN, bool MASK>
 __global__ __launch_bounds__(kRowThreads) void k_row_moments(RowArgs a) {
-  row_moments_body<TIN>(a, vb_grid());
+  row_moments_body<TIN, MASK>(a, vb_grid());
 }
 
 __global__ __launch_bounds__(kRowThreads) void k_row_moments_batch(const RowArgs* args, const BatchTab* tab,
@@ -1163,6 +1152,20 @@ __global__ __launch_bounds__(256) void k_bg_refit(const double* G, const double*
 // host-side launchers
 // ---------------------------------------------------------------------------
 
+template <typename T, typename TIN, bool MASK, class Set>
+static void set_row_attrs(Set& set) {
+  set(reinterpret_cast<const void*>(&k_row_pass<T, TIN, 1, false, MASK>));
+  set(reinterpret_cast<const void*>(&k_row_pass<T, TIN, 1, true, MASK>));
+  set(reinterpret_cast<const void*>(&k_row_pass<T, TIN, 2, false, MASK>));
+  set(reinterpret_cast<const void*>(&k_row_pass<T, TIN, 2, true, MASK>));
+  set(reinterpret_cast<const void*>(&k_row_pass<T, TIN, 4, false, MASK>));
+  set(reinterpret_cast<const void*>(&k_row_pass<T, TIN, 4, true, MASK>));
+  set(reinterpret_cast<const void*>(&k_row_pass<T, TIN, 8, false, MASK>));
+  set(reinterpret_cast<const void*>(&k_row_pass<T, TIN, 8, true, MASK>));
+  set(reinterpret_cast<const void*>(&k_row_pass<T, TIN, 16, false, MASK>));
+  set(reinterpret_cast<const void*>(&k_row_pass<T, TIN, 16, true, MASK>));
+}
+
 hipError_t prepare_kernel_attributes() {
   static const hipError_t once = [] {
     const int lim = 160 * 1024;
@@ -1170,46 +1173,14 @@ hipError_t prepare_kernel_attributes() {
     auto set = [&](const void* f) {
       if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     };
-    set(reinterpret_cast<const void*>(&k_row_pass<double, double, 1, false>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, double, 1, true>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, double, 2, false>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, double, 2, true>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, double, 4, false>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, double, 4, true>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, double, 8, false>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, double, 8, true>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, double, 16, false>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, double, 16, true>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, float, 1, false>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, float, 1, true>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, float, 2, false>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, float, 2, true>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, float, 4, false>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, float, 4, true>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, float, 8, false>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, float, 8, true>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, float, 16, false>));
-    set(reinterpret_cast<const void*>(&k_row_pass<double, float, 16, true>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, double, 1, false>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, double, 1, true>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, double, 2, false>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, double, 2, true>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, double, 4, false>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, double, 4, true>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, double, 8, false>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, double, 8, true>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, double, 16, false>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, double, 16, true>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, float, 1, false>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, float, 1, true>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, float, 2, false>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, float, 2, true>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, float, 4, false>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, float, 4, true>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, float, 8, false>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, float, 8, true>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, float, 16, false>));
-    set(reinterpret_cast<const void*>(&k_row_pass<float, float, 16, true>));
+    set_row_attrs<double, double, false>(set);
+    set_row_attrs<double, float, false>(set);
+    set_row_attrs<float, double, false>(set);
+    set_row_attrs<float, float, false>(set);
+    set_row_attrs<double, double, true>(set);
+    set_row_attrs<double, float, true>(set);
+    set_row_attrs<float, double, true>(set);
+    set_row_attrs<float, float, true>(set);
     set(reinterpret_cast<const void*>(&k_col_pass<double, 1>));
     set(reinterpret_cast<const void*>(&k_col_pass<double, 3>));
     set(reinterpret_cast<const void*>(&k_col_pass<double, 6>));
@@ -1324,19 +1295,25 @@ static hipError_t launch_row(const Geometry& g, const sfft_desc& d, const void* 
   int grid = g.H < per_cu * p.num_cus ? g.H : per_cu * p.num_cus;
   const bool f32 = d.image_dtype == SFFT_F32;
   const bool mixed = (g.W % 3 == 0) || (g.W % 5 == 0);
-#define SFFT_ROW(NQ)                                                                              \
-  do {                                                                                            \
-    if (mixed) {                                                                                  \
-      if (f32) hipLaunchKernelGGL((k_row_pass<T, float, NQ, true>), dim3(grid), dim3(kRowThreads), \
-                                  shmem, st, a);                                                 \
-      else hipLaunchKernelGGL((k_row_pass<T, double, NQ, true>), dim3(grid), dim3(kRowThreads),    \
-                              shmem, st, a);                                                     \
-    } else {                                                                                      \
-      if (f32) hipLaunchKernelGGL((k_row_pass<T, float, NQ, false>), dim3(grid),                  \
-                                  dim3(kRowThreads), shmem, st, a);                               \
-      else hipLaunchKernelGGL((k_row_pass<T, double, NQ, false>), dim3(grid), dim3(kRowThreads),  \
-                              shmem, st, a);                                                     \
-    }                                                                                             \
+  const bool masked = mask != nullptr || frame > 0;
+#define SFFT_ROW_M(NQ, M)                                                                            \
+  do {                                                                                               \
+    if (mixed) {                                                                                     \
+      if (f32) hipLaunchKernelGGL((k_row_pass<T, float, NQ, true, M>), dim3(grid), dim3(kRowThreads), \
+                                  shmem, st, a);                                                    \
+      else hipLaunchKernelGGL((k_row_pass<T, double, NQ, true, M>), dim3(grid), dim3(kRowThreads),    \
+                              shmem, st, a);                                                        \
+    } else {                                                                                         \
+      if (f32) hipLaunchKernelGGL((k_row_pass<T, float, NQ, false, M>), dim3(grid),                  \
+                                  dim3(kRowThreads), shmem, st, a);                                  \
+      else hipLaunchKernelGGL((k_row_pass<T, double, NQ, false, M>), dim3(grid), dim3(kRowThreads),  \
+                              shmem, st, a);                                                        \
+    }                                                                                                \
+  } while (0)
+#define SFFT_ROW(NQ)                     \
+  do {                                   \
+    if (masked) SFFT_ROW_M(NQ, true);    \
+    else SFFT_ROW_M(NQ, false);          \
   } while (0)
   const int nq = (g.W + kRowThreads - 1) / kRowThreads;
   if (nq <= 1) SFFT_ROW(1);
@@ -1345,6 +1322,7 @@ static hipError_t launch_row(const Geometry& g, const sfft_desc& d, const void* 
   else if (nq <= 8) SFFT_ROW(8);
   else SFFT_ROW(16);
 #undef SFFT_ROW
+#undef SFFT_ROW_M
   return hipGetLastError();
 }
 
@@ -1440,11 +1418,12 @@ __global__ __launch_bounds__(256) void k_outpix_transform(OutpixArgs a) {
   a.G[(int64_t)p * a.N + q] = v;
 }
 
-// The science image's row spectrum (the last plane of F), its DC / Nyquist
-// values, its row moments and its non-finite bit survive a solve and a
-// subtract in the same workspace when the solve and subtract regions end
-// before that plane; a build for another reference against the same science
-// image (and science pedestal) can then reuse them.
+// The science image's row spectrum (the last plane of F) and its DC /
+// Nyquist values survive a solve and a subtract in the same workspace when
+// the solve and subtract regions end before that plane; a build for another
+// reference against the same science image (and science pedestal) can then
+// skip its transform (the row moments still read the science image, cheaply,
+// and check it for non-finite pixels).
 bool sci_reusable(const sfft_desc& d) {
   const Geometry g = make_geometry(d);
   const Layout l = make_layout(g);
@@ -1470,12 +1449,7 @@ hipError_t launch_build_masked(const sfft_desc& d, const void* R, const void* S,
   const bool outpix = d.convention == 1;
   hipError_t e;
   prof_begin(pf, SFFT_PROF_BUILD, st);
-  if (reuse_sci)
-    hipLaunchKernelGGL(k_clear_flags_keep_sci, dim3(1), dim3(64), 0, st,
-                       reinterpret_cast<int*>(ws + l.flags), 64);
-  else
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st,
-                       reinterpret_cast<int*>(ws + l.flags), 64, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, reinterpret_cast<int*>(ws + l.flags), 64, 0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   {
     RowArgs ra = make_row_args(g, d, R, S, ws, l, p);
@@ -1483,10 +1457,15 @@ hipError_t launch_build_masked(const sfft_desc& d, const void* R, const void* S,
     ra.mask = mask;
     ra.mask_ld = mask_ld;
     ra.frame = outpix ? g.r : 0;
-    if (d.image_dtype == SFFT_F32)
-      hipLaunchKernelGGL(k_row_moments<float>, dim3(row_moments_grid(g.H)), dim3(kRowThreads), 0, st, ra);
-    else
-      hipLaunchKernelGGL(k_row_moments<double>, dim3(row_moments_grid(g.H)), dim3(kRowThreads), 0, st, ra);
+    const bool masked = mask != nullptr || outpix;
+    const dim3 mg(row_moments_grid(g.H));
+    if (d.image_dtype == SFFT_F32) {
+      if (masked) hipLaunchKernelGGL((k_row_moments<float, true>), mg, dim3(kRowThreads), 0, st, ra);
+      else hipLaunchKernelGGL((k_row_moments<float, false>), mg, dim3(kRowThreads), 0, st, ra);
+    } else {
+      if (masked) hipLaunchKernelGGL((k_row_moments<double, true>), mg, dim3(kRowThreads), 0, st, ra);
+      else hipLaunchKernelGGL((k_row_moments<double, false>), mg, dim3(kRowThreads), 0, st, ra);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   prof_begin(pf, SFFT_PROF_ROW_PASS, st);
@@ -1667,9 +1646,9 @@ hipError_t launch_bg_refit(const sfft_desc& d, const void* R, const void* S, dou
   const Layout l = make_layout(g);
   const RowArgs ra = make_row_args(g, d, R, S, ws, l, p);
   if (d.image_dtype == SFFT_F32)
-    hipLaunchKernelGGL(k_row_moments<float>, dim3(row_moments_grid(g.H)), dim3(kRowThreads), 0, st, ra);
+    hipLaunchKernelGGL((k_row_moments<float, false>), dim3(row_moments_grid(g.H)), dim3(kRowThreads), 0, st, ra);
   else
-    hipLaunchKernelGGL(k_row_moments<double>, dim3(row_moments_grid(g.H)), dim3(kRowThreads), 0, st, ra);
+    hipLaunchKernelGGL((k_row_moments<double, false>), dim3(row_moments_grid(g.H)), dim3(kRowThreads), 0, st, ra);
   hipError_t e;
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const MomArgs ma = make_mom_args(g, ws, l);

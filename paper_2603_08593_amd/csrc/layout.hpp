@@ -14,15 +14,14 @@ constexpr int kColsPerWG = 4;   // k_x columns per column-pass workgroup
 constexpr int kColThreads = 512;
 constexpr int kRowThreads = 256;
 constexpr int kTile = 64;       // Cholesky tile
-constexpr int kSubTX = 64, kSubTY = 16;   // subtract output tile
+constexpr int kSubTX = 64, kSubTY = 32;   // subtract output tile
+constexpr int kSubThreads = kSubTX * kSubTY / 8;   // 8 pixels of a row per thread
 constexpr int kMaxW = 4096;
 // solve synchronisation words: [0, 256) barrier flags, [256, 512) progress
 // flags, then 256 64-bit time stamps
 constexpr int kSyncWords = 512;
 constexpr int kMaxTeam = 128;   // workgroups of one solve
 constexpr int kSyncClear = kSyncWords + 2 * 256;
-// bits of flag word 0: a non-finite pixel in the reference / science image
-constexpr int kNonfiniteRef = 1, kNonfiniteSci = 2;
 
 struct Geometry {
   int W, H, L, r, h, DK, DB, nK, nB, N, NKK, NP, nkx, TP, T, nsig;

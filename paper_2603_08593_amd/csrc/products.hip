@@ -49,7 +49,9 @@ __device__ __forceinline__ void sort_net(double* v) {
   }
 }
 
-template <typename T, int NT>
+// VEC: FP32 images whose rows start 16-byte aligned; a thread's 4 pixels of
+// every template are one 16-byte load each
+template <typename T, int NT, bool VEC>
 __global__ __launch_bounds__(kCombThreads) void k_median_combine(CombineArgs a) {
   const int y = blockIdx.y;
   const int x0 = (blockIdx.x * kCombThreads + threadIdx.x) * kCombPix;
@@ -60,13 +62,22 @@ __global__ __launch_bounds__(kCombThreads) void k_median_combine(CombineArgs a) 
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const T* D = static_cast<const T*>(a.D[t]) + row;
+    if (VEC && x0 + kCombPix <= a.W) {
+      const float4 q = *reinterpret_cast<const float4*>(D + x0);
+      v[0][t] = q.x;
+      v[1][t] = q.y;
+      v[2][t] = q.z;
+      v[3][t] = q.w;
+    } else {
 #pragma unroll
-    for (int p = 0; p < kCombPix; ++p) {
-      const int x = x0 + p;
-      v[p][t] = x < a.W ? (double)D[x] : 0.0;
+      for (int p = 0; p < kCombPix; ++p) {
+        const int x = x0 + p;
+        v[p][t] = x < a.W ? (double)D[x] : 0.0;
+      }
     }
   }
   T* out = static_cast<T*>(a.out) + row;
+  T res[kCombPix];
 #pragma unroll
   for (int p = 0; p < kCombPix; ++p) {
     bool nan = false;
@@ -78,17 +89,24 @@ __global__ __launch_bounds__(kCombThreads) void k_median_combine(CombineArgs a) 
     sort_net<NT>(v[p]);
     double m = (NT & 1) ? v[p][NT / 2] : 0.5 * (v[p][NT / 2 - 1] + v[p][NT / 2]);
     if (nan) m = __builtin_nan("");
-    if (x0 + p < a.W) out[x0 + p] = (T)m;
+    res[p] = (T)m;
+  }
+  if (VEC && x0 + kCombPix <= a.W) {
+    *reinterpret_cast<float4*>(out + x0) = float4{(float)res[0], (float)res[1], (float)res[2], (float)res[3]};
+  } else {
+#pragma unroll
+    for (int p = 0; p < kCombPix; ++p)
+      if (x0 + p < a.W) out[x0 + p] = res[p];
   }
 }
 
-template <typename T>
+template <typename T, bool VEC>
 static hipError_t launch_combine_t(const CombineArgs& a, int n, hipStream_t st) {
   const dim3 grid((unsigned)((a.W + kCombThreads * kCombPix - 1) / (kCombThreads * kCombPix)), (unsigned)a.H);
   const dim3 blk(kCombThreads);
   switch (n) {
 #define SFFT_COMB_CASE(K) \
-    case K: hipLaunchKernelGGL((k_median_combine<T, K>), grid, blk, 0, st, a); break;
+    case K: hipLaunchKernelGGL((k_median_combine<T, K, VEC>), grid, blk, 0, st, a); break;
     SFFT_COMB_CASE(1) SFFT_COMB_CASE(2) SFFT_COMB_CASE(3) SFFT_COMB_CASE(4)
     SFFT_COMB_CASE(5) SFFT_COMB_CASE(6) SFFT_COMB_CASE(7) SFFT_COMB_CASE(8)
     SFFT_COMB_CASE(9) SFFT_COMB_CASE(10) SFFT_COMB_CASE(11) SFFT_COMB_CASE(12)
@@ -101,7 +119,10 @@ static hipError_t launch_combine_t(const CombineArgs& a, int n, hipStream_t st) 
 
 hipError_t launch_median_combine(const CombineArgs& a, int n, bool f32, hipStream_t st) {
   if (n < 1 || n > kMaxTemplates) return hipErrorInvalidValue;
-  return f32 ? launch_combine_t<float>(a, n, st) : launch_combine_t<double>(a, n, st);
+  if (!f32) return launch_combine_t<double, false>(a, n, st);
+  bool aligned = (a.ld % 4) == 0 && (reinterpret_cast<uintptr_t>(a.out) & 15) == 0;
+  for (int t = 0; t < n; ++t) aligned = aligned && (reinterpret_cast<uintptr_t>(a.D[t]) & 15) == 0;
+  return aligned ? launch_combine_t<float, true>(a, n, st) : launch_combine_t<float, false>(a, n, st);
 }
 
 // ---------------------------------------------------------------------------

@@ -142,10 +142,19 @@ __device__ __forceinline__ uint4 rb_load_a(const RbConvArgs& a, const RbPix& q, 
   return *reinterpret_cast<const uint4*>(a.x2 + (((int64_t)q.img * a.H2 + iy) * a.W2 + ix) * a.cinp2 + c0);
 }
 
+// The weights of a 32-wide k chunk (COUT x 32 bf16) are staged in LDS once
+// per workgroup (double-buffered, one barrier per chunk) and read by the
+// four waves; rows padded to 40 bf16 against bank conflicts.
+constexpr int kRbBPitch = 40;
+
 template <int COUT>
-__global__ __launch_bounds__(kRbThreads) void k_rb_conv(RbConvArgs a) {
+__global__ __launch_bounds__(kRbThreads, 2) void k_rb_conv(RbConvArgs a) {
   constexpr int NT = COUT / 16;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int BV = COUT * 4;                         // 16-byte pieces of one chunk of weights
+  constexpr int BPT = (BV + kRbThreads - 1) / kRbThreads;
+  __shared__ __align__(16) unsigned short Bs[2][COUT * kRbBPitch];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, g = lane >> 4;
   const int base = blockIdx.x * kRbPix + wave * 64;
   floatx4_rb acc[kRbMT][NT];
@@ -157,33 +166,54 @@ __global__ __launch_bounds__(kRbThreads) void k_rb_conv(RbConvArgs a) {
   RbPix px[kRbMT];
 #pragma unroll
   for (int m = 0; m < kRbMT; ++m) px[m] = rb_pix(a, base + 16 * m + l16);
-  uint4 A[kRbMT], B[NT], An[kRbMT], Bn[NT];
-  auto load = [&](int kc, uint4 (&As)[kRbMT], uint4 (&Bs)[NT]) {
+  uint4 A[kRbMT], An[kRbMT], Bg[BPT];
+  auto load_a = [&](int kc, uint4 (&As)[kRbMT]) {
     const int k0 = kc * 32 + 8 * g;
 #pragma unroll
     for (int m = 0; m < kRbMT; ++m) As[m] = rb_load_a(a, px[m], k0);
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-      Bs[t] = *reinterpret_cast<const uint4*>(a.w + (int64_t)(16 * t + l16) * a.KP + k0);
   };
-  load(0, A, B);
+  // piece i of a chunk: output channel i / 4, k offset 8 (i % 4)
+  auto load_b = [&](int kc) {
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+      const int i = tid + u * kRbThreads;
+      if (i < BV)
+        Bg[u] = *reinterpret_cast<const uint4*>(a.w + (int64_t)(i >> 2) * a.KP + kc * 32 + 8 * (i & 3));
+    }
+  };
+  auto store_b = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+      const int i = tid + u * kRbThreads;
+      if (i < BV) *reinterpret_cast<uint4*>(&Bs[buf][(i >> 2) * kRbBPitch + 8 * (i & 3)]) = Bg[u];
+    }
+  };
+  load_a(0, A);
+  load_b(0);
+  store_b(0);
+  __syncthreads();
   for (int kc = 0; kc < nkc; ++kc) {
-    // the next chunk's loads are issued before this chunk's products
-    if (kc + 1 < nkc) load(kc + 1, An, Bn);
+    const int buf = kc & 1;
+    // the next chunk's global loads are in flight during this chunk's products
+    if (kc + 1 < nkc) {
+      load_a(kc + 1, An);
+      load_b(kc + 1);
+    }
 #pragma unroll
-    for (int m = 0; m < kRbMT; ++m) {
-      const bf16x8_rb av = __builtin_bit_cast(bf16x8_rb, A[m]);
+    for (int t = 0; t < NT; ++t) {
+      const bf16x8_rb bv =
+          __builtin_bit_cast(bf16x8_rb, *reinterpret_cast<const uint4*>(&Bs[buf][(16 * t + l16) * kRbBPitch + 8 * g]));
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
-        acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf16x8_rb, B[t]), acc[m][t],
+      for (int m = 0; m < kRbMT; ++m)
+        acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_rb, A[m]), bv, acc[m][t],
                                                             0, 0, 0);
     }
     if (kc + 1 < nkc) {
+      store_b(buf ^ 1);
 #pragma unroll
       for (int m = 0; m < kRbMT; ++m) A[m] = An[m];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) B[t] = Bn[t];
     }
+    __syncthreads();
   }
   // epilogue: lane (g, l16), element q -> pixel 16 m + 4 g + q, channel 16 t + l16
 #pragma unroll

@@ -6,7 +6,7 @@
 // kernel value w_d(u) = sum_m c_m(d, u_y) xt(u_x)^m is evaluated at the input
 // pixel u by Horner in xt, with c_m(d, u_y) = sum_b a_((m,b),d) yt(u_y)^b
 // formed once per (tap, input row) and shared by a thread's 8 pixels.
-// Output tiles of 64 x 16 pixels; the reference tile with an r-pixel halo is
+// Output tiles of 64 x 32 pixels; the reference tile with an r-pixel halo is
 // staged in LDS in FP64; accumulation in FP64. The chi2 judge's kappa2(x)
 // polynomial depends on the coefficients only: a one-workgroup kernel forms
 // it once per launch.
@@ -104,7 +104,7 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
   constexpr int RW = TX + 2 * r, RH = TY + 2 * r;
   constexpr int NQ = P + 2 * r;
   __shared__ double Rt[RH][RW + 1];
-  __shared__ double red[2];
+  __shared__ double red[kSubThreads / 64];
   const int tid = threadIdx.x;
   const int W = a.W, H = a.H;
   // the fitted coefficients are read-only for the whole launch: reading them
@@ -116,12 +116,12 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
   const bool inner = x0 >= r && x0 + RW - r <= W && y0 >= r && y0 + RH - r <= H;
   if (inner) {
     const TIO* Rb = static_cast<const TIO*>(a.R) + (int64_t)(y0 - r) * a.ld + (x0 - r);
-    for (int i = tid; i < RH * RW; i += 128) {
+    for (int i = tid; i < RH * RW; i += kSubThreads) {
       const int ly = i / RW, lx = i - (i / RW) * RW;
       Rt[ly][lx] = (double)Rb[(int64_t)ly * a.ld + lx] - a.cR;
     }
   } else {
-    for (int i = tid; i < RH * RW; i += 128) {
+    for (int i = tid; i < RH * RW; i += kSubThreads) {
       const int ly = i / RW, lx = i - (i / RW) * RW;
       int yy = y0 + ly - r, xx = x0 + lx - r;
       yy = (yy < 0) ? yy + H : yy;
@@ -261,7 +261,12 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
     chi = wave_sum(chi);
     if ((tid & 63) == 0) red[tid >> 6] = chi;
     __syncthreads();
-    if (tid == 0) a.partials[vb.y * vb.nx + vb.x] = red[0] + red[1];
+    if (tid == 0) {
+      double t = red[0];
+#pragma unroll
+      for (int w = 1; w < kSubThreads / 64; ++w) t += red[w];
+      a.partials[vb.y * vb.nx + vb.x] = t;
+    }
   }
 }
 
@@ -273,12 +278,12 @@ template <int L, int DK>
 constexpr int subtract_waves() { return (DK == 0 || (DK == 2 && L >= 7 && L <= 11)) ? 4 : 1; }
 
 template <int L, int DK, typename TIO, bool OUTPIX>
-__global__ __launch_bounds__(128, (subtract_waves<L, DK>())) void k_subtract(SubArgs a) {
+__global__ __launch_bounds__(kSubThreads, (subtract_waves<L, DK>())) void k_subtract(SubArgs a) {
   subtract_body<L, DK, TIO, OUTPIX>(a, vb_grid());
 }
 
 template <int L, int DK, typename TIO>
-__global__ __launch_bounds__(128, (subtract_waves<L, DK>())) void k_subtract_batch(const SubArgs* args, const BatchTab* tab, int n) {
+__global__ __launch_bounds__(kSubThreads, (subtract_waves<L, DK>())) void k_subtract_batch(const SubArgs* args, const BatchTab* tab, int n) {
   int item;
   VB vb;
   if (batch_locate(tab, n, item, vb)) subtract_body<L, DK, TIO>(args[item], vb);
@@ -297,11 +302,11 @@ __global__ __launch_bounds__(1024) void k_chi2_final(const double* partials, int
 template <int L, int DK>
 static hipError_t launch_sub_ldk(const SubArgs& a, bool f32, bool outpix, dim3 grid, hipStream_t st) {
   if (outpix) {
-    if (f32) hipLaunchKernelGGL((k_subtract<L, DK, float, true>), grid, dim3(128), 0, st, a);
-    else hipLaunchKernelGGL((k_subtract<L, DK, double, true>), grid, dim3(128), 0, st, a);
+    if (f32) hipLaunchKernelGGL((k_subtract<L, DK, float, true>), grid, dim3(kSubThreads), 0, st, a);
+    else hipLaunchKernelGGL((k_subtract<L, DK, double, true>), grid, dim3(kSubThreads), 0, st, a);
   } else {
-    if (f32) hipLaunchKernelGGL((k_subtract<L, DK, float, false>), grid, dim3(128), 0, st, a);
-    else hipLaunchKernelGGL((k_subtract<L, DK, double, false>), grid, dim3(128), 0, st, a);
+    if (f32) hipLaunchKernelGGL((k_subtract<L, DK, float, false>), grid, dim3(kSubThreads), 0, st, a);
+    else hipLaunchKernelGGL((k_subtract<L, DK, double, false>), grid, dim3(kSubThreads), 0, st, a);
   }
   return hipGetLastError();
 }
@@ -382,7 +387,7 @@ hipError_t launch_subtract(const sfft_desc& d, const void* R, const void* S, con
 // share the array, so calls that overlap on one device race; every call
 // rewrites all the entries it reads (one partial per output tile, the kappa2
 // coefficients), so nothing needs clearing between calls.
-constexpr int kNoAllocMaxPartials = 1 << 16;   // 64 x 16 tiles: up to 2^26 pixels
+constexpr int kNoAllocMaxPartials = 1 << 16;   // 64 x 32 tiles: up to 2^27 pixels
 constexpr int kNoAllocK2 = 128;
 constexpr int kNoAllocMaxDevices = 64;
 static __device__ __align__(256) double scratch[kNoAllocMaxPartials + kNoAllocK2];
@@ -556,9 +561,9 @@ static void sub_batch_l(const SubBatch* b, int q, hipStream_t st) {
   const dim3 grid(b->blocks[q]);
 #define SFFT_SB(DKV)                                                                                 \
   do {                                                                                               \
-    if (b->f32) hipLaunchKernelGGL((k_subtract_batch<L, DKV, float>), grid, dim3(128), 0, st,        \
+    if (b->f32) hipLaunchKernelGGL((k_subtract_batch<L, DKV, float>), grid, dim3(kSubThreads), 0, st,        \
                                    (const SubArgs*)b->dargs[q], (const BatchTab*)b->dtabs[q], n);     \
-    else hipLaunchKernelGGL((k_subtract_batch<L, DKV, double>), grid, dim3(128), 0, st,              \
+    else hipLaunchKernelGGL((k_subtract_batch<L, DKV, double>), grid, dim3(kSubThreads), 0, st,              \
                             (const SubArgs*)b->dargs[q], (const BatchTab*)b->dtabs[q], n);            \
   } while (0)
   if (b->DK == 0) SFFT_SB(0);

@@ -60,8 +60,8 @@ def test_noalloc_subtract_rejects_oversize_and_bad_args():
     lib = sf.lib()
     h = sf.Handle()
     try:
-        # 4096 x 16400: 64 x 1025 tiles > 65536 -> workspace error, nothing launched
-        big = sf.make_desc(4096, 16400, 11, 2, 2)
+        # 8192 x 16416: 128 x 513 tiles of 64 x 32 > 65536 -> workspace error, nothing launched
+        big = sf.make_desc(8192, 16416, 11, 2, 2)
         dummy = torch.zeros(16, dtype=torch.float32, device="cuda")
         coef = torch.zeros(732, dtype=torch.float64, device="cuda")
         rc = lib.sfft_subtract_noalloc(h.ptr, big, sf._dp(dummy), sf._dp(dummy), sf._dp(coef),
