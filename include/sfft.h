@@ -173,6 +173,21 @@ sfft_status sfft_solve(sfft_handle handle, const sfft_desc* desc,
                        int32_t max_refine, sfft_solve_info* info,
                        void* ws, size_t ws_bytes, void* stream);
 
+/* Size of the team of workgroups that runs sfft_solve (and the solves of
+ * sfft_difference_multi) on this handle. The paper's pipeline differences a
+ * queue of CCD pairs one after another on each GPU (Sec. 5.2); the solve of
+ * one pair is a persistent kernel whose duration is set by its diagonal
+ * Cholesky chain, and at the default (team = 0: up to half the CUs) most of
+ * those CUs wait. With several pairs in flight on separate streams (each
+ * with its own handle, workspace and buffers), a smaller team leaves CUs to
+ * the other pairs' builds and subtracts. Results are deterministic for a
+ * given team size; teams of different sizes add the solve's partial sums in
+ * different groupings, so their coefficients can differ in the last bits.
+ *   team : 0 (default) or 2..128; a team larger than the default is not
+ *          used (the default applies). Other values: SFFT_ERR_INVALID_ARG. */
+sfft_status sfft_set_solve_team(sfft_handle handle, int32_t team);
+sfft_status sfft_get_solve_team(sfft_handle handle, int32_t* team);
+
 /* D = S' - M_coef(R') with periodic boundaries, accumulated in FP64, in the
  * descriptor's kernel convention (the whole image; no mask).
  * chi2 (nullable, device double): reduced chi^2 of D over the image minus an

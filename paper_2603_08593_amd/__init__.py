@@ -96,6 +96,8 @@ _SIGS = {
     "sfft_solve": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, ctypes.c_int32, _P, _P,
                                   ctypes.c_size_t, _P]),
     "sfft_subtract": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "sfft_set_solve_team": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "sfft_get_solve_team": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "sfft_median_combine": (ctypes.c_int, [_P, ctypes.POINTER(Desc), ctypes.POINTER(_P), ctypes.c_int32,
                                            ctypes.POINTER(ctypes.c_double), ctypes.c_double, _P, _P]),
     "sfft_difference_multi": (ctypes.c_int, [_P, ctypes.POINTER(Desc), ctypes.POINTER(_P), _P, ctypes.c_int32,
@@ -267,6 +269,16 @@ def sfft_solve(handle: Handle, desc: Desc, G, h, coef, info, ws, max_refine=2, s
            "sfft_solve")
 
 
+def sfft_set_solve_team(handle: Handle, team: int):
+    _check(lib().sfft_set_solve_team(handle.ptr, int(team)), "sfft_set_solve_team")
+
+
+def sfft_get_solve_team(handle: Handle) -> int:
+    t = ctypes.c_int32(0)
+    _check(lib().sfft_get_solve_team(handle.ptr, ctypes.byref(t)), "sfft_get_solve_team")
+    return int(t.value)
+
+
 def sfft_subtract(handle: Handle, desc: Desc, ref, sci, coef, diff, chi2, ws, stream=None):
     _check(lib().sfft_subtract(handle.ptr, ctypes.byref(desc), _dp(ref), _dp(sci), _dp(coef), _dp(diff),
                                _dp(chi2), _dp(ws), ws.numel() * ws.element_size(), _stream_ptr(stream)),
@@ -321,7 +333,8 @@ class Differencer:
     """Reusable device buffers + handle for one image shape and fit."""
 
     def __init__(self, width, height, L, dk, db, *, image_dtype="float32", compute="fp64",
-                 ref_pedestal=0.0, sci_pedestal=0.0, device="cuda", stamps=None, convention="input"):
+                 ref_pedestal=0.0, sci_pedestal=0.0, device="cuda", stamps=None, convention="input",
+                 solve_team=0):
         import torch
         self.torch = torch
         self.dtype = torch.float32 if image_dtype in ("float32", torch.float32) else torch.float64
@@ -331,6 +344,8 @@ class Differencer:
                               ref_pedestal=ref_pedestal, sci_pedestal=sci_pedestal,
                               convention=SFFT_CONV_OUTPUT_PIXEL if convention == "output" else SFFT_CONV_INPUT_PIXEL)
         self.handle = Handle()
+        if solve_team:
+            sfft_set_solve_team(self.handle, solve_team)
         self.N = sfft_num_unknowns(self.desc)
         # stamps = (n_stamps, size): size the workspace for the stamp build as well
         self.stamps = stamps
@@ -403,6 +418,61 @@ class Differencer:
     def close(self):
         """Release the handle now; the torch buffers go with the object."""
         self.handle.close()
+
+
+class PairPipeline:
+    """Several CCD pairs in flight on one GPU: `depth` slots, each a
+    Differencer (its own handle, workspace and result buffers) with its own
+    HIP stream; pair k goes to slot k % depth. A slot's work is ordered on its
+    stream, so pair k + depth overwrites the results of pair k in that slot:
+    read or copy them first (wait(slot) or the slot's stream).
+
+    The solve of one pair is a persistent kernel bound by its diagonal
+    Cholesky chain; with a smaller team (`solve_team` workgroups) it leaves
+    CUs to the builds and subtracts of the other pairs in flight. Each pair's
+    results equal those of a single Differencer with the same solve_team."""
+
+    def __init__(self, width, height, L, dk, db, *, depth=3, solve_team=32, **kw):
+        import torch
+        if depth < 1:
+            raise ValueError("depth must be >= 1")
+        self.torch = torch
+        self.depth = depth
+        self.slots = [Differencer(width, height, L, dk, db, solve_team=solve_team, **kw) for _ in range(depth)]
+        self.streams = [torch.cuda.Stream() for _ in range(depth)]
+        self.count = 0
+
+    def submit(self, ref, sci, max_refine=2, mask=None, pedestals=None) -> int:
+        """Queue build + solve + subtract of one pair (pedestals: optional
+        (ref, sci) pedestals of this pair); returns its slot. The slot's
+        stream first waits for the caller's current stream (where the inputs
+        were produced)."""
+        torch = self.torch
+        k = self.count % self.depth
+        self.count += 1
+        if pedestals is not None:
+            self.slots[k].set_pedestals(*pedestals)
+        s = self.streams[k]
+        s.wait_stream(torch.cuda.current_stream())
+        for t in (ref, sci) + (() if mask is None else (mask,)):
+            t.record_stream(s)
+        self.slots[k].run(ref, sci, max_refine=max_refine, stream=s, mask=mask)
+        return k
+
+    def wait(self, slot=None):
+        """Block until the slot's queued work (or every slot's) is done."""
+        for k in (range(self.depth) if slot is None else (slot,)):
+            self.streams[k].synchronize()
+
+    def buffers(self, slot) -> Buffers:
+        return self.slots[slot].buf
+
+    def info(self, slot) -> SolveInfo:
+        return self.slots[slot].info()
+
+    def close(self):
+        for d in self.slots:
+            d.close()
 
 
 # ---------------------------------------------------------------------------

@@ -31,7 +31,7 @@ hipError_t launch_build_masked(const sfft_desc& d, const void* R, const void* S,
                                int64_t mask_ld, double* G, double* hv, unsigned char* ws, const BuildPlan& p,
                                const Prof* pf, hipStream_t st, bool reuse_sci);
 hipError_t launch_solve(const sfft_desc& d, const double* G, const double* h, double* coef,
-                        int max_refine, sfft_solve_info* info, unsigned char* ws, int num_cus,
+                        int max_refine, sfft_solve_info* info, unsigned char* ws, int num_cus, int team,
                         const Prof* pf, hipStream_t st);
 hipError_t launch_subtract(const sfft_desc& d, const void* R, const void* S, const double* coef,
                            void* D, double* chi2, unsigned char* ws, const Prof* pf,
@@ -74,6 +74,7 @@ struct sfft_handle_s {
   int num_cus = 0;
   std::map<int, sfft::Twiddles> tw;   // keyed by transform length
   sfft::Prof prof{};                  // timing events per sfft_prof_slot
+  int solve_team = 0;                 // workgroups of the single-pair solve (0: default)
   std::map<std::string, std::pair<int, int>> tuned;   // batch key -> (rows per block, solve team)
   char arch[64] = {0};
 };
@@ -291,9 +292,21 @@ sfft_status sfft_solve(sfft_handle h, const sfft_desc* d, const double* G, const
   if ((s = check_ws(ws, ws_bytes, make_layout(make_geometry(*d)).solve_end)) != SFFT_OK) return s;
   if ((s = check_device(h)) != SFFT_OK) return s;
   const hipError_t e = launch_solve(*d, G, hv, coef, max_refine, info,
-                                    static_cast<unsigned char*>(ws), h->num_cus, &h->prof,
+                                    static_cast<unsigned char*>(ws), h->num_cus, h->solve_team, &h->prof,
                                     static_cast<hipStream_t>(stream));
   return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
+}
+
+sfft_status sfft_set_solve_team(sfft_handle h, int32_t team) {
+  if (!h || team < 0 || team == 1 || team > kMaxTeam) return SFFT_ERR_INVALID_ARG;
+  h->solve_team = team;
+  return SFFT_OK;
+}
+
+sfft_status sfft_get_solve_team(sfft_handle h, int32_t* team) {
+  if (!h || !team) return SFFT_ERR_INVALID_ARG;
+  *team = h->solve_team;
+  return SFFT_OK;
 }
 
 sfft_status sfft_subtract(sfft_handle h, const sfft_desc* d, const void* ref, const void* sci,
@@ -471,7 +484,8 @@ sfft_status sfft_difference_multi(sfft_handle h, const sfft_desc* d, const void*
     if (ref_pedestals) dt.ref_pedestal = ref_pedestals[t];
     hipError_t e = launch_build(dt, refs[t], sci, G, hv, w, p, &h->prof, st, reuse && t > 0);
     if (e == hipSuccess)
-      e = launch_solve(dt, G, hv, coefs + t * N, max_refine, infos + t, w, h->num_cus, &h->prof, st);
+      e = launch_solve(dt, G, hv, coefs + t * N, max_refine, infos + t, w, h->num_cus, h->solve_team,
+                       &h->prof, st);
     if (e == hipSuccess)
       e = launch_subtract(dt, refs[t], sci, coefs + t * N, diffs[t], chi2s + t, w, &h->prof, st);
     if (e != hipSuccess) return SFFT_ERR_HIP;

@@ -902,9 +902,12 @@ static PSArgs make_solve_args(const sfft_desc& d, const double* G, const double*
 }
 
 hipError_t launch_solve(const sfft_desc& d, const double* G, const double* h, double* coef,
-                        int max_refine, sfft_solve_info* info, unsigned char* ws, int num_cus,
+                        int max_refine, sfft_solve_info* info, unsigned char* ws, int num_cus, int team,
                         const Prof* pf, hipStream_t st) {
   PSArgs a = make_solve_args(d, G, h, coef, max_refine, info, ws, 0);
+  // a caller-chosen smaller team leaves CUs to work on other streams (the
+  // diagonal chain, not the team size, bounds the solve's duration)
+  if (team >= 2 && team < a.P) a.P = team;
   // a plain launch (no cooperative-launch overhead, capturable in a graph):
   // the LDS footprint allows one solve workgroup per CU and P is at most half
   // the CUs, so every workgroup becomes resident while the others wait; the

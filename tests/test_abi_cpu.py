@@ -83,3 +83,7 @@ def test_null_arguments_rejected_before_any_device_work():
         == sf.SFFT_ERR_INVALID_ARG
     n = ctypes.c_size_t()
     assert lib.sfft_workspace_size(None, ctypes.byref(d), ctypes.byref(n)) == sf.SFFT_ERR_INVALID_ARG
+    # the solve-team setting needs a handle
+    assert lib.sfft_set_solve_team(None, 32) == sf.SFFT_ERR_INVALID_ARG
+    t = ctypes.c_int32(-1)
+    assert lib.sfft_get_solve_team(None, ctypes.byref(t)) == sf.SFFT_ERR_INVALID_ARG
