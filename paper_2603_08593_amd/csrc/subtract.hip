@@ -232,16 +232,35 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
         kk[e] = s;
       }
     }
+    // the thread's 8 pixels of S and D as two 16-byte accesses when the
+    // images are FP32, the row segment is 16-byte aligned and inside the image
+    const TIO* srow = static_cast<const TIO*>(a.S) + (int64_t)ye * a.ld + xbe;
+    TIO* drow = static_cast<TIO*>(a.D) + (int64_t)ye * a.ld + xbe;
+    constexpr bool kF32 = sizeof(TIO) == 4;
+    const bool vec = kF32 && xbe + P <= W &&
+                     ((reinterpret_cast<uintptr_t>(srow) | reinterpret_cast<uintptr_t>(drow)) & 15) == 0;
+    double sv8[P], dv8[P];
+    if (vec) {
+      const float4 s0 = reinterpret_cast<const float4*>(srow)[0];
+      const float4 s1 = reinterpret_cast<const float4*>(srow)[1];
+      sv8[0] = s0.x; sv8[1] = s0.y; sv8[2] = s0.z; sv8[3] = s0.w;
+      sv8[4] = s1.x; sv8[5] = s1.y; sv8[6] = s1.z; sv8[7] = s1.w;
+    } else {
+#pragma unroll
+      for (int p = 0; p < P; ++p) sv8[p] = (xbe + p < W) ? (double)srow[p] : 0.0;
+    }
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       const int x = xbe + p;
+      dv8[p] = 0.0;
       if (x < W) {
         const double xt = (double)x * a.sx - 1.0;
         double bgv = 0.0;
         for (int k = DB; k >= 0; --k) bgv = fma(bgv, xt, ek[k]);
-        const double sv = (double)static_cast<const TIO*>(a.S)[(int64_t)ye * a.ld + x];
+        const double sv = sv8[p];
         const double dv = (sv - a.cS) - acc[p] - bgv;
-        static_cast<TIO*>(a.D)[(int64_t)ye * a.ld + x] = (TIO)dv;
+        dv8[p] = dv;
+        if (!vec) drow[p] = (TIO)dv;
         if (a.want_chi2 && x >= r && x < W - r && ye >= r && ye < H - r) {
           double k2v = 0.0;
 #pragma unroll
@@ -255,6 +274,10 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
           chi = fma(dv * dv, iv, chi);
         }
       }
+    }
+    if (vec) {
+      reinterpret_cast<float4*>(drow)[0] = float4{(float)dv8[0], (float)dv8[1], (float)dv8[2], (float)dv8[3]};
+      reinterpret_cast<float4*>(drow)[1] = float4{(float)dv8[4], (float)dv8[5], (float)dv8[6], (float)dv8[7]};
     }
   }
   if (a.want_chi2) {
@@ -277,9 +300,19 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
 template <int L, int DK>
 constexpr int subtract_waves() { return (DK == 0 || (DK == 2 && L >= 7 && L <= 11)) ? 4 : 1; }
 
+// XCD-aware tile columns: consecutive workgroups of a launch go to the 8
+// XCDs in turn, so workgroup column bx takes tile column (bx mod 8) * per +
+// bx / 8 (per = ceil(tile columns / 8)): each XCD works through a strip of
+// per adjacent tile columns over all tile rows, and the reference halo that
+// neighbouring tiles share stays in that XCD's L2. The grid has 8 * per
+// workgroup columns; the surplus ones exit.
 template <int L, int DK, typename TIO, bool OUTPIX>
 __global__ __launch_bounds__(kSubThreads, (subtract_waves<L, DK>())) void k_subtract(SubArgs a) {
-  subtract_body<L, DK, TIO, OUTPIX>(a, vb_grid());
+  const int gx = (a.W + kSubTX - 1) / kSubTX;
+  const int per = (gx + 7) >> 3;
+  const int tx = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (tx >= gx) return;
+  subtract_body<L, DK, TIO, OUTPIX>(a, VB{tx, (int)blockIdx.y, gx, (int)gridDim.y});
 }
 
 template <int L, int DK, typename TIO>
@@ -350,7 +383,7 @@ hipError_t launch_subtract(const sfft_desc& d, const void* R, const void* S, con
                                   reinterpret_cast<double*>(ws + l.partials),
                                   reinterpret_cast<double*>(ws + l.k2));
   hipError_t e;
-  const dim3 grid((g.W + kSubTX - 1) / kSubTX, (g.H + kSubTY - 1) / kSubTY);
+  const dim3 grid(8 * (((g.W + kSubTX - 1) / kSubTX + 7) / 8), (g.H + kSubTY - 1) / kSubTY);
   const bool f32 = d.image_dtype == SFFT_F32;
   prof_begin(pf, SFFT_PROF_SUBTRACT, st);
   if (chi2) {
@@ -421,7 +454,7 @@ hipError_t launch_subtract_noalloc(int device, const sfft_desc& d, const void* R
   if (np > kNoAllocMaxPartials) return hipErrorInvalidValue;
   const SubArgs a = make_sub_args(d, R, S, coef, D, chi2 != nullptr, base, base + kNoAllocMaxPartials);
   hipError_t e;
-  const dim3 grid((g.W + kSubTX - 1) / kSubTX, (g.H + kSubTY - 1) / kSubTY);
+  const dim3 grid(8 * (((g.W + kSubTX - 1) / kSubTX + 7) / 8), (g.H + kSubTY - 1) / kSubTY);
   const bool f32 = d.image_dtype == SFFT_F32;
   if (chi2) {
     hipLaunchKernelGGL(k_kappa2, dim3(1), dim3(kK2Threads), 0, st, a);
