@@ -146,13 +146,27 @@ __device__ __forceinline__ uint4 rb_load_a(const RbConvArgs& a, const RbPix& q, 
 // per workgroup (double-buffered, one barrier per chunk) and read by the
 // four waves; rows padded to 40 bf16 against bank conflicts.
 constexpr int kRbBPitch = 40;
+constexpr size_t kRbMaxTileBytes = 48 * 1024;   // staged input rows (two workgroups per CU)
 
-template <int COUT>
+// Staged inputs (TILED): for a stride-1 layer whose copies hold a whole
+// number of workgroups (Ho Wo a multiple of kRbPix, kRbPix a multiple of Wo),
+// a workgroup's kRbPix output pixels are R = kRbPix / Wo whole rows oy0 ..
+// oy0 + R - 1 of one copy; the 3x3 taps read input rows oy0 - 1 .. oy0 + R
+// and columns -1 .. W (zero outside the image), which are copied into LDS
+// once (channel pitch cinp + 8: 16 bytes of padding per pixel against bank
+// conflicts) instead of being gathered from memory once per tap. The
+// operands, and so the products and their order, are the same.
+inline size_t rb_tile_bytes(int W, int Wo, int cinp) {
+  return sizeof(unsigned short) * (size_t)(kRbPix / Wo + 2) * (size_t)(W + 2) * (size_t)(cinp + 8);
+}
+
+template <int COUT, bool TILED>
 __global__ __launch_bounds__(kRbThreads, 2) void k_rb_conv(RbConvArgs a) {
   constexpr int NT = COUT / 16;
   constexpr int BV = COUT * 4;                         // 16-byte pieces of one chunk of weights
   constexpr int BPT = (BV + kRbThreads - 1) / kRbThreads;
   __shared__ __align__(16) unsigned short Bs[2][COUT * kRbBPitch];
+  extern __shared__ __align__(16) unsigned short Xs[];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, g = lane >> 4;
@@ -166,9 +180,43 @@ __global__ __launch_bounds__(kRbThreads, 2) void k_rb_conv(RbConvArgs a) {
   RbPix px[kRbMT];
 #pragma unroll
   for (int m = 0; m < kRbMT; ++m) px[m] = rb_pix(a, base + 16 * m + l16);
+  int t_oy0 = 0, tw = 0, cpt = 0;
+  if constexpr (TILED) {
+    const int pix0 = blockIdx.x * kRbPix;
+    const int hw = a.Ho * a.Wo;
+    const int img = pix0 / hw;
+    t_oy0 = (pix0 - img * hw) / a.Wo;
+    tw = a.W + 2;
+    cpt = a.cinp + 8;
+    const int cv8 = a.cinp / 8;
+    const int n16 = (kRbPix / a.Wo + 2) * tw * cv8;    // 16-byte pieces of the tile
+    for (int i = tid; i < n16; i += kRbThreads) {
+      const int pix = i / cv8, cv = i - pix * cv8;
+      const int ty = pix / tw, tx = pix - ty * tw;
+      const int iy = t_oy0 - 1 + ty, ix = tx - 1;
+      uint4 v = {0u, 0u, 0u, 0u};
+      if (iy >= 0 && iy < a.H && ix >= 0 && ix < a.W)
+        v = *reinterpret_cast<const uint4*>(a.x + (((int64_t)img * a.H + iy) * a.W + ix) * a.cinp + 8 * cv);
+      *reinterpret_cast<uint4*>(&Xs[pix * cpt + 8 * cv]) = v;
+    }
+    __syncthreads();
+  }
   uint4 A[kRbMT], An[kRbMT], Bg[BPT];
   auto load_a = [&](int kc, uint4 (&As)[kRbMT]) {
     const int k0 = kc * 32 + 8 * g;
+    if constexpr (TILED) {
+      if (k0 < 9 * a.cinp) {
+        const int tap = k0 / a.cinp, c0 = k0 - tap * a.cinp;
+        const int ky = tap / 3, kx = tap - ky * 3;
+#pragma unroll
+        for (int m = 0; m < kRbMT; ++m) {
+          const RbPix& q = px[m];
+          As[m] = q.img < 0 ? uint4{0u, 0u, 0u, 0u}
+                            : *reinterpret_cast<const uint4*>(&Xs[((q.oy - t_oy0 + ky) * tw + q.ox + kx) * cpt + c0]);
+        }
+        return;
+      }
+    }
 #pragma unroll
     for (int m = 0; m < kRbMT; ++m) As[m] = rb_load_a(a, px[m], k0);
   };
@@ -372,10 +420,16 @@ hipError_t launch_rb_score(const float* params, const float* stamps, int n, floa
     ca.KP = p.KP[l];
     ca.npix = (int)(copies * ca.Ho * ca.Wo);
     const dim3 grid((unsigned)((ca.npix + kRbPix - 1) / kRbPix));
-    switch (gm.co) {
-      case 32: hipLaunchKernelGGL(k_rb_conv<32>, grid, dim3(kRbThreads), 0, st, ca); break;
-      case 64: hipLaunchKernelGGL(k_rb_conv<64>, grid, dim3(kRbThreads), 0, st, ca); break;
-      case 128: hipLaunchKernelGGL(k_rb_conv<128>, grid, dim3(kRbThreads), 0, st, ca); break;
+    const bool tiled = ca.stride == 1 && (ca.Ho * ca.Wo) % kRbPix == 0 && kRbPix % ca.Wo == 0 &&
+                       rb_tile_bytes(ca.W, ca.Wo, ca.cinp) <= kRbMaxTileBytes;
+    const size_t tb = tiled ? rb_tile_bytes(ca.W, ca.Wo, ca.cinp) : 0;
+    switch (gm.co * 2 + (tiled ? 1 : 0)) {
+      case 64: hipLaunchKernelGGL((k_rb_conv<32, false>), grid, dim3(kRbThreads), 0, st, ca); break;
+      case 65: hipLaunchKernelGGL((k_rb_conv<32, true>), grid, dim3(kRbThreads), tb, st, ca); break;
+      case 128: hipLaunchKernelGGL((k_rb_conv<64, false>), grid, dim3(kRbThreads), 0, st, ca); break;
+      case 129: hipLaunchKernelGGL((k_rb_conv<64, true>), grid, dim3(kRbThreads), tb, st, ca); break;
+      case 256: hipLaunchKernelGGL((k_rb_conv<128, false>), grid, dim3(kRbThreads), 0, st, ca); break;
+      case 257: hipLaunchKernelGGL((k_rb_conv<128, true>), grid, dim3(kRbThreads), tb, st, ca); break;
       default: return hipErrorInvalidValue;
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
