@@ -201,7 +201,8 @@ sfft_status sfft_create(sfft_handle* out) {
     return SFFT_ERR_HIP;
   if (prepare_kernel_attributes() != hipSuccess) return SFFT_ERR_HIP;
   if (prepare_solve_attributes() != hipSuccess) return SFFT_ERR_HIP;
-  if (prepare_stamp_attributes() != hipSuccess || prepare_surrogate_attributes() != hipSuccess) {
+  if (prepare_stamp_attributes() != hipSuccess || prepare_surrogate_attributes() != hipSuccess ||
+      prepare_rb_attributes() != hipSuccess) {
     (void)hipGetLastError();
     return SFFT_ERR_HIP;
   }

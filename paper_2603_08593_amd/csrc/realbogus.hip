@@ -282,6 +282,152 @@ __global__ __launch_bounds__(kRbThreads, 2) void k_rb_conv(RbConvArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Stage 1 fused (stem, block-1 conv a, block-1 conv b + identity shortcut):
+// the three layers on 32 x 32 maps keep their activations in LDS, one copy
+// per workgroup, and only the block's output goes to memory. Layer by layer,
+// every 32-channel map of 4096 candidates is ~1 GB written and read back
+// (each layer then bound by memory traffic); here the copy's input (16 KB)
+// and output (64 KB) are the only traffic besides the L2-resident weights.
+// Maps are 34 x 34 pixels (a zero border of one pixel, so the 3 x 3 taps
+// need no bounds checks), bf16, 32 channels per pixel (64 bytes) with the
+// four 16-byte channel groups of pixel p stored in the order
+// cg ^ ((p >> 2) & 3): 16 consecutive pixels of one channel group then fall
+// on 16 different 16-byte bank groups. The input map holds 8 channels per
+// pixel (16 bytes, no swizzle). Products, their order (k chunks in order,
+// one v_mfma_f32_16x16x32_bf16 per chunk and output tile) and the epilogue
+// are those of k_rb_conv, so the output is the same bit for bit.
+// ---------------------------------------------------------------------------
+
+constexpr int kRbMapSide = 34;
+constexpr int kRbMapPix = kRbMapSide * kRbMapSide;
+constexpr size_t kRbMapBytes = (size_t)kRbMapPix * 64;          // 32 channels of bf16
+constexpr size_t kRbStage1Lds = 2 * kRbMapBytes;
+
+__device__ __forceinline__ int rb_map_off(int p, int cg) {      // bytes, 32-channel map
+  return p * 64 + ((cg ^ ((p >> 2) & 3)) << 4);
+}
+
+// one layer: out = relu(conv3x3(in) + bias [+ res]) on the 32 x 32 interior;
+// CIN8: the input map has 8 channels per pixel (the stem)
+template <bool CIN8, bool RES>
+__device__ __forceinline__ void rb_stage1_layer(const unsigned char* in, unsigned char* out,
+                                                const unsigned short* w, const float* bias, int KP) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, g = lane >> 4;
+  constexpr int NKC = CIN8 ? 3 : 9;            // k chunks: KP = 96 (stem), 288
+  const int cin = CIN8 ? 8 : 32;
+  // the lane's weights of every k chunk and its two biases, held in
+  // registers for the 4 passes
+  const float bias2[2] = {bias[l16], bias[16 + l16]};
+  uint4 Bw[NKC][2];
+#pragma unroll
+  for (int kc = 0; kc < NKC; ++kc)
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+      Bw[kc][t] = *reinterpret_cast<const uint4*>(w + (int64_t)(16 * t + l16) * KP + kc * 32 + 8 * g);
+  // wave w: row tiles 16 w .. 16 w + 15 of the 64 (16 pixels each), 4 per pass
+  for (int pass = 0; pass < 4; ++pass) {
+    const int mt0 = 16 * wave + 4 * pass;
+    floatx4_rb acc[4][2];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) acc[m][t] = floatx4_rb{0.f, 0.f, 0.f, 0.f};
+    auto load_a = [&](int kc, uint4 (&A)[4]) {
+      const int k0 = kc * 32 + 8 * g;
+      const int tap = k0 / cin, c0 = k0 - tap * cin;
+      const int ky = tap / 3, kx = tap - ky * 3;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int P = 16 * (mt0 + m) + l16;                      // output pixel, row-major 32 x 32
+        const int p = ((P >> 5) + ky) * kRbMapSide + (P & 31) + kx;
+        if (tap >= 9) A[m] = uint4{0u, 0u, 0u, 0u};               // k padding
+        else if (CIN8) A[m] = *reinterpret_cast<const uint4*>(in + p * 16);
+        else A[m] = *reinterpret_cast<const uint4*>(in + rb_map_off(p, c0 >> 3));
+      }
+    };
+    uint4 A[4], An[4];
+    load_a(0, A);
+#pragma unroll
+    for (int kc = 0; kc < NKC; ++kc) {
+      if (kc + 1 < NKC) load_a(kc + 1, An);
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+          acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_rb, A[m]),
+                                                              __builtin_bit_cast(bf16x8_rb, Bw[kc][t]), acc[m][t],
+                                                              0, 0, 0);
+      if (kc + 1 < NKC) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) A[m] = An[m];
+      }
+    }
+    // epilogue: lane (g, l16), element q -> pixel 16 m + 4 g + q, channel 16 t + l16
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int P = 16 * (mt0 + m) + 4 * g + q;
+        const int p = ((P >> 5) + 1) * kRbMapSide + (P & 31) + 1;
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const int co = 16 * t + l16;
+          const int off = rb_map_off(p, co >> 3) + 2 * (co & 7);
+          float v = acc[m][t][q] + bias2[t];
+          if (RES) v += bf16_to_f32(*reinterpret_cast<const unsigned short*>(out + off));
+          v = fmaxf(v, 0.0f);
+          *reinterpret_cast<unsigned short*>(out + off) = f32_to_bf16_rne(v);
+        }
+      }
+  }
+}
+
+struct RbStage1Args {
+  const unsigned short* x0;               // [copies][32][32][8]
+  const unsigned short* w[3];             // packed weights of stem, b1a, b1b
+  const float* bias[3];
+  int KP[3];
+  unsigned short* y;                      // [copies][32][32][32]: block 1 output
+  int copies;
+};
+
+__global__ __launch_bounds__(kRbThreads, 1) void k_rb_stage1(RbStage1Args a) {
+  extern __shared__ __align__(16) unsigned char rbm[];
+  unsigned char* M0 = rbm;                       // stem output, then block output (in place)
+  unsigned char* M1 = rbm + kRbMapBytes;         // input (8 channels), then conv a output
+  const int c = blockIdx.x;
+  if (c >= a.copies) return;
+  const int tid = threadIdx.x;
+  const uint4 zero = {0u, 0u, 0u, 0u};
+  // zero both maps (borders included), then the copy's input into M1
+  for (int i = tid; i < (int)(kRbStage1Lds / 16); i += kRbThreads) reinterpret_cast<uint4*>(rbm)[i] = zero;
+  __syncthreads();
+  const uint4* src = reinterpret_cast<const uint4*>(a.x0 + (int64_t)c * 32 * 32 * 8);
+  for (int i = tid; i < 32 * 32; i += kRbThreads) {
+    const int p = ((i >> 5) + 1) * kRbMapSide + (i & 31) + 1;
+    reinterpret_cast<uint4*>(M1)[p] = src[i];
+  }
+  __syncthreads();
+  rb_stage1_layer<true, false>(M1, M0, a.w[0], a.bias[0], a.KP[0]);
+  __syncthreads();
+  // M1 becomes a 32-channel map: zero it again (its border is read by conv b)
+  for (int i = tid; i < (int)(kRbMapBytes / 16); i += kRbThreads) reinterpret_cast<uint4*>(M1)[i] = zero;
+  __syncthreads();
+  rb_stage1_layer<false, false>(M0, M1, a.w[1], a.bias[1], a.KP[1]);
+  __syncthreads();
+  rb_stage1_layer<false, true>(M1, M0, a.w[2], a.bias[2], a.KP[2]);
+  __syncthreads();
+  // the block output, un-swizzled, 16 bytes per store
+  uint4* dst = reinterpret_cast<uint4*>(a.y + (int64_t)c * 32 * 32 * 32);
+  for (int i = tid; i < 32 * 32 * 4; i += kRbThreads) {
+    const int P = i >> 2, cg = i & 3;
+    const int p = ((P >> 5) + 1) * kRbMapSide + (P & 31) + 1;
+    dst[i] = *reinterpret_cast<const uint4*>(M0 + rb_map_off(p, cg));
+  }
+}
+
+// ---------------------------------------------------------------------------
 // head: mean over the 8 x 8 pixels and the 4 copies, linear 128 -> 64, ReLU,
 // linear 64 -> 1, sigmoid. One workgroup of 128 threads per candidate, FP32,
 // fixed order.
@@ -403,7 +549,21 @@ hipError_t launch_rb_score(const float* params, const float* stamps, int n, floa
       {B1, 16, nullptr, 0, nullptr, B0},       // block 3 conv a  -> t8 (B0)
       {B0, 8, B1, 16, nullptr, B2},            // block 3 conv b + proj(a3) -> a4 (B2)
   };
-  for (int l = 0; l < kRbGemms; ++l) {
+  {
+    RbStage1Args sa{};
+    sa.x0 = x0;
+    for (int l = 0; l < 3; ++l) {
+      sa.w[l] = reinterpret_cast<const unsigned short*>(ws + p.w[l]);
+      sa.bias[l] = reinterpret_cast<const float*>(ws + p.bias[l]);
+      sa.KP[l] = p.KP[l];
+    }
+    sa.y = steps[2].y;
+    sa.copies = (int)copies;
+    if (sa.KP[0] != 96 || sa.KP[1] != 288 || sa.KP[2] != 288) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_rb_stage1, dim3((unsigned)copies), dim3(kRbThreads), kRbStage1Lds, st, sa);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  for (int l = 3; l < kRbGemms; ++l) {
     const RbGemm& gm = kRbGemm[l];
     const Step& s = steps[l];
     RbConvArgs ca{};
@@ -437,6 +597,11 @@ hipError_t launch_rb_score(const float* params, const float* stamps, int n, floa
   hipLaunchKernelGGL(k_rb_head, dim3(n), dim3(128), 0, st, B2, params + kRbFc1W, params + kRbFc1B,
                      params + kRbFc2W, params + kRbFc2B, n, logits, probs);
   return hipGetLastError();
+}
+
+hipError_t prepare_rb_attributes() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rb_stage1),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRbStage1Lds);
 }
 
 hipError_t launch_rb_extract(const RbExtractArgs& a, bool f32, hipStream_t st) {

@@ -84,5 +84,6 @@ struct RbExtractArgs {
 hipError_t launch_rb_score(const float* params, const float* stamps, int n, float* logits, float* probs,
                            unsigned char* ws, hipStream_t st);
 hipError_t launch_rb_extract(const RbExtractArgs& a, bool f32, hipStream_t st);
+hipError_t prepare_rb_attributes();   // dynamic LDS limit of the fused stage-1 kernel
 
 }  // namespace sfft
