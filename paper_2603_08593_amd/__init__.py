@@ -566,7 +566,7 @@ class MultiDifferencer:
     zero-point-normalised median combine, in caller-owned torch buffers."""
 
     def __init__(self, width, height, L, dk, db, n_templates, *, image_dtype="float32", compute="fp64",
-                 sci_pedestal=0.0, device="cuda"):
+                 sci_pedestal=0.0, device="cuda", solve_team=0):
         import torch
         self.torch = torch
         self.dtype = torch.float32 if image_dtype in ("float32", torch.float32) else torch.float64
@@ -578,6 +578,8 @@ class MultiDifferencer:
         if st != SFFT_OK:
             raise SfftError(st, "sfft_validate")
         self.handle = Handle()
+        if solve_team:
+            sfft_set_solve_team(self.handle, solve_team)
         self.n = int(n_templates)
         self.N = N = sfft_num_unknowns(self.desc)
         dev = torch.device(device)

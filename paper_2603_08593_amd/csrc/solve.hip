@@ -120,9 +120,9 @@ __device__ __forceinline__ bool failed_by(const PSArgs& a, int k) {
 
 // Progress flags of the factorisation, one monotonic word per workgroup.
 // Workgroup 0 (diagonal chain): 2k + 1 once L_kk and U_k of step k are
-// stored, 2k + 2 once the panel tile L_(k+1),k is. Workgroups 1 .. P-1:
-// 2k + 1 after their panel tiles of step k, 2k + 2 after their trailing
-// updates of step k. All stores of the workgroup precede the flag (barrier,
+// stored. Workgroups 1 .. P-1: 2k + 2 after their bulk work of step k; in
+// the two-phase bulk of the batched solve also 2k + 1 after their panel
+// tiles of step k. All stores of the workgroup precede the flag (barrier,
 // then a release fence by the storing thread).
 __device__ __forceinline__ void publish(const PSArgs& a, int bid, unsigned val) {
   __syncthreads();
@@ -640,6 +640,90 @@ __device__ __forceinline__ void bulk_step(const PSArgs& a, int k, int q, int nb,
   }
 }
 
+// The bulk work of step k in two phases (the batched solve, which is bound
+// by the bulk's throughput rather than by the diagonal chain). Panels: the
+// tiles X_rk = A_rk U_k of the matrix rows k + 1 <= r < nt, written over
+// A_rk (read by nothing after step k), and of the v row and the identity
+// rows of blocks i <= k, written to Z (their final results); each computed
+// once, by one workgroup. Updates, after every bulk workgroup has finished
+// its panels: A_rJ -= X_rk X_Jk^T over the same task list as bulk_step,
+// with both panel tiles loaded instead of computed (one tile product per
+// task instead of up to three).
+__device__ __forceinline__ void bulk_panels(const PSArgs& a, int k, int q, int nb, double (*TU)[kLD],
+                                            double (*TX)[kLD]) {
+  const int nt = a.nt, Np = a.Np;
+  const int m = nt - k - 1;
+  const int ntot = m + k + 2;                   // matrix rows, the v row, identity rows 0..k
+  const int tb = (int)((int64_t)ntot * q / nb), te = (int)((int64_t)ntot * (q + 1) / nb);
+  bool have_u = false;
+  for (int t = tb; t < te; ++t) {
+    const int rt = (t < m) ? k + 1 + t : nt + (t - m);
+    const int rows = (rt == nt) ? 1 : kTile;
+    const int64_t r0 = row_off(rt, nt, Np);
+    {
+      double vu[kPerThread], vx[kPerThread];
+      if (!have_u) tile_gather(vu, a.Ud + (int64_t)k * kTile * kTile, kTile, 0, 0);
+      tile_gather(vx, a.A, Np, r0, (int64_t)k * kTile, rows);
+      if (!have_u) tile_scatter(TU, vu);
+      tile_scatter(TX, vx);
+    }
+    have_u = true;
+    __syncthreads();
+    tile_mul_inplace(TX, TU);                   // X_rk
+    if (rt < nt) tile_out(TX, a.A, Np, r0, (int64_t)k * kTile, rows);
+    else tile_out(TX, a.Z, Np, r0 - Np, (int64_t)k * kTile, rows);
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void bulk_updates(const PSArgs& a, int k, int q, int nb, double (*TX)[kLD],
+                                             double (*TL)[kLD], double (*TC)[kLD]) {
+  const int nt = a.nt, Np = a.Np;
+  const int m = nt - k - 1;
+  if (m == 0) return;
+  const int ntri = m * (m + 1) / 2;
+  const int nrow = k + 2;
+  const int ntot = ntri + nrow * m;
+  const int tb = 1 + (int)((int64_t)(ntot - 1) * q / nb);
+  const int te = 1 + (int)((int64_t)(ntot - 1) * (q + 1) / nb);
+  int xrow = -1;
+  for (int t = tb; t < te; ++t) {
+    int rt, J;
+    if (t < ntri) {
+      int ti, tj;
+      tri_decode(t, ti, tj);
+      rt = k + 1 + ti;
+      J = k + 1 + tj;
+    } else {
+      const int u = t - ntri;
+      rt = nt + u / m;
+      J = k + 1 + u % m;
+    }
+    const int rows = (rt == nt) ? 1 : kTile;
+    const int64_t r0 = row_off(rt, nt, Np);
+    const bool diag = (J == rt);
+    const bool new_x = (rt != xrow);
+    {
+      double vx[kPerThread], vc[kPerThread], vl[kPerThread];
+      if (new_x) {
+        if (rt < nt) tile_gather(vx, a.A, Np, r0, (int64_t)k * kTile, rows);
+        else tile_gather(vx, a.Z, Np, r0 - Np, (int64_t)k * kTile, rows);
+      }
+      tile_gather(vc, a.A, Np, r0, (int64_t)J * kTile, rows);
+      if (!diag) tile_gather(vl, a.A, Np, (int64_t)J * kTile, (int64_t)k * kTile);
+      if (new_x) tile_scatter(TX, vx);
+      tile_scatter(TC, vc);
+      if (!diag) tile_scatter(TL, vl);
+    }
+    xrow = rt;
+    __syncthreads();
+    tile_sub_abt(TC, TX, diag ? TX : TL);
+    store_tile_r(TC, a.A, Np, r0, J, rows);
+    __syncthreads();
+  }
+}
+
+template <bool TWO_PHASE>
 __device__ __forceinline__ void solve_body(const PSArgs& a, const int bid) {
   extern __shared__ __align__(16) double smem[];
   double (*T0)[kLD] = reinterpret_cast<double (*)[kLD]>(smem);
@@ -765,7 +849,17 @@ __device__ __forceinline__ void solve_body(const PSArgs& a, const int bid) {
       // U_k stored; the bulk work of step k - 1 complete
       if (P > 1) wait_progress(a, 2 * k + 1, 2 * k);
       if (failed_by(a, k)) break;
-      bulk_step(a, k, q, nb, T0, T1, T2, T3);
+      if constexpr (TWO_PHASE) {
+        bulk_panels(a, k, q, nb, T0, T1);
+        // every panel tile of step k written before any update reads it
+        if (P > 1) {
+          publish(a, bid, 2 * k + 1);
+          wait_progress(a, 2 * k + 1, 2 * k + 1);
+        }
+        bulk_updates(a, k, q, nb, T1, T2, T3);
+      } else {
+        bulk_step(a, k, q, nb, T0, T1, T2, T3);
+      }
       if (P > 1) publish(a, bid, 2 * k + 2);
     }
   }
@@ -839,14 +933,14 @@ __device__ __forceinline__ void solve_body(const PSArgs& a, const int bid) {
   }
 }
 
-__global__ __launch_bounds__(kPT) void k_solve_persistent(PSArgs a) { solve_body(a, blockIdx.x); }
+__global__ __launch_bounds__(kPT) void k_solve_persistent(PSArgs a) { solve_body<false>(a, blockIdx.x); }
 
 // T teams of P co-resident workgroups; team t solves items t, t + T, ...
 // (a static work queue over items ordered by decreasing size, every item
 // planned with the same P)
 __global__ __launch_bounds__(kPT) void k_solve_batch(const PSArgs* args, const int* order, int n, int P, int T) {
   const int team = blockIdx.x / P, bid = blockIdx.x % P;
-  for (int q = team; q < n; q += T) solve_body(args[order[q]], bid);
+  for (int q = team; q < n; q += T) solve_body<true>(args[order[q]], bid);
 }
 
 // clears the arrival / release / progress flags and the time stamps
