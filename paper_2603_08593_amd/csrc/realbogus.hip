@@ -428,6 +428,142 @@ __global__ __launch_bounds__(kRbThreads, 1) void k_rb_stage1(RbStage1Args a) {
 }
 
 // ---------------------------------------------------------------------------
+// Stage 2 fused (block 2: stride-2 conv a 32 -> 64, conv b 64 -> 64 with the
+// 1x1 stride-2 projection of the block input appended to its k range), one
+// copy per workgroup. LDS: the block input as a 34 x 34 map of 32 channels
+// (as in stage 1) and conv a's output as an 18 x 18 map of 64 channels (a
+// zero border, 128 bytes per pixel, channel group cg of pixel p stored at
+// cg ^ ((p >> 1) & 7)); conv b's output goes to memory. Wave w computes
+// the output channels 32 (w & 1) .. + 31 of half the pixels, with that
+// half's weights in registers. Same products and order as k_rb_conv.
+// ---------------------------------------------------------------------------
+
+constexpr int kRbMap16Side = 18;
+constexpr size_t kRbMap16Bytes = (size_t)kRbMap16Side * kRbMap16Side * 128;   // 64 channels of bf16
+constexpr size_t kRbStage2Lds = kRbMapBytes + kRbMap16Bytes;
+
+__device__ __forceinline__ int rb_map16_off(int p, int cg) {    // bytes, 64-channel map
+  return p * 128 + ((cg ^ ((p >> 1) & 7)) << 4);
+}
+
+// one GEMM of stage 2: 256 output pixels (16 x 16) x 64 channels; wave w:
+// channel half h = w & 1, pixels 128 (w >> 1) .. + 127 in two passes of 64.
+// CONV_A: input the 34 x 34 block-input map (stride 2); else the 18 x 18 map
+// (stride 1) plus the projection chunk from the block-input map.
+template <bool CONV_A, int NKC>
+__device__ __forceinline__ void rb_stage2_gemm(const unsigned char* in32, const unsigned char* in64,
+                                               unsigned char* out64, unsigned short* gout,
+                                               const unsigned short* w, const float* bias, int KP) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, g = lane >> 4;
+  const int h = wave & 1;
+  const float bias2[2] = {bias[32 * h + l16], bias[32 * h + 16 + l16]};
+  uint4 Bw[NKC][2];
+#pragma unroll
+  for (int kc = 0; kc < NKC; ++kc)
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+      Bw[kc][t] = *reinterpret_cast<const uint4*>(w + (int64_t)(32 * h + 16 * t + l16) * KP + kc * 32 + 8 * g);
+  for (int pass = 0; pass < 2; ++pass) {
+    const int mt0 = 8 * (wave >> 1) + 4 * pass;
+    floatx4_rb acc[4][2];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) acc[m][t] = floatx4_rb{0.f, 0.f, 0.f, 0.f};
+    auto load_a = [&](int kc, uint4 (&A)[4]) {
+      const int k0 = kc * 32 + 8 * g;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int P = 16 * (mt0 + m) + l16;                     // output pixel, row-major 16 x 16
+        const int oy = P >> 4, ox = P & 15;
+        if (CONV_A) {                                          // 3 x 3, stride 2, 32 input channels
+          const int tap = k0 >> 5, c0 = k0 & 31;
+          const int ky = tap / 3, kx = tap - ky * 3;
+          const int p = (2 * oy + ky) * kRbMapSide + 2 * ox + kx;
+          A[m] = *reinterpret_cast<const uint4*>(in32 + rb_map_off(p, c0 >> 3));
+        } else if (k0 < 9 * 64) {                              // 3 x 3, stride 1, 64 channels
+          const int tap = k0 >> 6, c0 = k0 & 63;
+          const int ky = tap / 3, kx = tap - ky * 3;
+          const int p = (oy + ky) * kRbMap16Side + ox + kx;
+          A[m] = *reinterpret_cast<const uint4*>(in64 + rb_map16_off(p, c0 >> 3));
+        } else {                                               // projection: block input at (2 oy, 2 ox)
+          const int c0 = k0 - 9 * 64;
+          const int p = (2 * oy + 1) * kRbMapSide + 2 * ox + 1;
+          A[m] = *reinterpret_cast<const uint4*>(in32 + rb_map_off(p, c0 >> 3));
+        }
+      }
+    };
+    uint4 A[4], An[4];
+    load_a(0, A);
+#pragma unroll
+    for (int kc = 0; kc < NKC; ++kc) {
+      if (kc + 1 < NKC) load_a(kc + 1, An);
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+          acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_rb, A[m]),
+                                                              __builtin_bit_cast(bf16x8_rb, Bw[kc][t]), acc[m][t],
+                                                              0, 0, 0);
+      if (kc + 1 < NKC) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) A[m] = An[m];
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int P = 16 * (mt0 + m) + 4 * g + q;
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const int co = 32 * h + 16 * t + l16;
+          const float v = fmaxf(acc[m][t][q] + bias2[t], 0.0f);
+          const unsigned short b = f32_to_bf16_rne(v);
+          if (CONV_A) {
+            const int p = ((P >> 4) + 1) * kRbMap16Side + (P & 15) + 1;
+            *reinterpret_cast<unsigned short*>(out64 + rb_map16_off(p, co >> 3) + 2 * (co & 7)) = b;
+          } else {
+            gout[(int64_t)P * 64 + co] = b;
+          }
+        }
+      }
+  }
+}
+
+struct RbStage2Args {
+  const unsigned short* x;                // [copies][32][32][32]: block 1 output
+  const unsigned short* w[2];             // packed weights of block 2 conv a, conv b (+ projection)
+  const float* bias[2];
+  int KP[2];
+  unsigned short* y;                      // [copies][16][16][64]: block 2 output
+  int copies;
+};
+
+__global__ __launch_bounds__(kRbThreads, 1) void k_rb_stage2(RbStage2Args a) {
+  extern __shared__ __align__(16) unsigned char rbm[];
+  unsigned char* M32 = rbm;                      // block input, 34 x 34 x 32
+  unsigned char* M64 = rbm + kRbMapBytes;        // conv a output, 18 x 18 x 64
+  const int c = blockIdx.x;
+  if (c >= a.copies) return;
+  const int tid = threadIdx.x;
+  const uint4 zero = {0u, 0u, 0u, 0u};
+  for (int i = tid; i < (int)(kRbStage2Lds / 16); i += kRbThreads) reinterpret_cast<uint4*>(rbm)[i] = zero;
+  __syncthreads();
+  const uint4* src = reinterpret_cast<const uint4*>(a.x + (int64_t)c * 32 * 32 * 32);
+  for (int i = tid; i < 32 * 32 * 4; i += kRbThreads) {
+    const int P = i >> 2, cg = i & 3;
+    const int p = ((P >> 5) + 1) * kRbMapSide + (P & 31) + 1;
+    *reinterpret_cast<uint4*>(M32 + rb_map_off(p, cg)) = src[i];
+  }
+  __syncthreads();
+  rb_stage2_gemm<true, 9>(M32, nullptr, M64, nullptr, a.w[0], a.bias[0], a.KP[0]);
+  __syncthreads();
+  rb_stage2_gemm<false, 19>(M32, M64, nullptr, a.y + (int64_t)c * 16 * 16 * 64, a.w[1], a.bias[1], a.KP[1]);
+}
+
+// ---------------------------------------------------------------------------
 // head: mean over the 8 x 8 pixels and the 4 copies, linear 128 -> 64, ReLU,
 // linear 64 -> 1, sigmoid. One workgroup of 128 threads per candidate, FP32,
 // fixed order.
@@ -563,7 +699,21 @@ hipError_t launch_rb_score(const float* params, const float* stamps, int n, floa
     hipLaunchKernelGGL(k_rb_stage1, dim3((unsigned)copies), dim3(kRbThreads), kRbStage1Lds, st, sa);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  for (int l = 3; l < kRbGemms; ++l) {
+  {
+    RbStage2Args sa{};
+    sa.x = steps[3].x;
+    for (int l = 0; l < 2; ++l) {
+      sa.w[l] = reinterpret_cast<const unsigned short*>(ws + p.w[3 + l]);
+      sa.bias[l] = reinterpret_cast<const float*>(ws + p.bias[3 + l]);
+      sa.KP[l] = p.KP[3 + l];
+    }
+    sa.y = steps[4].y;
+    sa.copies = (int)copies;
+    if (sa.KP[0] != 288 || sa.KP[1] != 608) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_rb_stage2, dim3((unsigned)copies), dim3(kRbThreads), kRbStage2Lds, st, sa);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  for (int l = 5; l < kRbGemms; ++l) {
     const RbGemm& gm = kRbGemm[l];
     const Step& s = steps[l];
     RbConvArgs ca{};
@@ -600,8 +750,11 @@ hipError_t launch_rb_score(const float* params, const float* stamps, int n, floa
 }
 
 hipError_t prepare_rb_attributes() {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rb_stage1),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRbStage1Lds);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rb_stage1),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRbStage1Lds);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rb_stage2),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRbStage2Lds);
 }
 
 hipError_t launch_rb_extract(const RbExtractArgs& a, bool f32, hipStream_t st) {
