@@ -298,6 +298,7 @@ __global__ __launch_bounds__(kRbThreads, 2) void k_rb_conv(RbConvArgs a) {
 // are those of k_rb_conv, so the output is the same bit for bit.
 // ---------------------------------------------------------------------------
 
+constexpr int kRbFusedThreads = 512;   // fused stages: 8 waves, two per SIMD
 constexpr int kRbMapSide = 34;
 constexpr int kRbMapPix = kRbMapSide * kRbMapSide;
 constexpr size_t kRbMapBytes = (size_t)kRbMapPix * 64;          // 32 channels of bf16
@@ -325,9 +326,9 @@ __device__ __forceinline__ void rb_stage1_layer(const unsigned char* in, unsigne
 #pragma unroll
     for (int t = 0; t < 2; ++t)
       Bw[kc][t] = *reinterpret_cast<const uint4*>(w + (int64_t)(16 * t + l16) * KP + kc * 32 + 8 * g);
-  // wave w: row tiles 16 w .. 16 w + 15 of the 64 (16 pixels each), 4 per pass
-  for (int pass = 0; pass < 4; ++pass) {
-    const int mt0 = 16 * wave + 4 * pass;
+  // wave w: row tiles 8 w .. 8 w + 7 of the 64 (16 pixels each), 4 per pass
+  for (int pass = 0; pass < 2; ++pass) {
+    const int mt0 = 8 * wave + 4 * pass;
     floatx4_rb acc[4][2];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
@@ -392,7 +393,7 @@ struct RbStage1Args {
   int copies;
 };
 
-__global__ __launch_bounds__(kRbThreads, 1) void k_rb_stage1(RbStage1Args a) {
+__global__ __launch_bounds__(kRbFusedThreads, 1) void k_rb_stage1(RbStage1Args a) {
   extern __shared__ __align__(16) unsigned char rbm[];
   unsigned char* M0 = rbm;                       // stem output, then block output (in place)
   unsigned char* M1 = rbm + kRbMapBytes;         // input (8 channels), then conv a output
@@ -401,10 +402,10 @@ __global__ __launch_bounds__(kRbThreads, 1) void k_rb_stage1(RbStage1Args a) {
   const int tid = threadIdx.x;
   const uint4 zero = {0u, 0u, 0u, 0u};
   // zero both maps (borders included), then the copy's input into M1
-  for (int i = tid; i < (int)(kRbStage1Lds / 16); i += kRbThreads) reinterpret_cast<uint4*>(rbm)[i] = zero;
+  for (int i = tid; i < (int)(kRbStage1Lds / 16); i += kRbFusedThreads) reinterpret_cast<uint4*>(rbm)[i] = zero;
   __syncthreads();
   const uint4* src = reinterpret_cast<const uint4*>(a.x0 + (int64_t)c * 32 * 32 * 8);
-  for (int i = tid; i < 32 * 32; i += kRbThreads) {
+  for (int i = tid; i < 32 * 32; i += kRbFusedThreads) {
     const int p = ((i >> 5) + 1) * kRbMapSide + (i & 31) + 1;
     reinterpret_cast<uint4*>(M1)[p] = src[i];
   }
@@ -412,7 +413,7 @@ __global__ __launch_bounds__(kRbThreads, 1) void k_rb_stage1(RbStage1Args a) {
   rb_stage1_layer<true, false>(M1, M0, a.w[0], a.bias[0], a.KP[0]);
   __syncthreads();
   // M1 becomes a 32-channel map: zero it again (its border is read by conv b)
-  for (int i = tid; i < (int)(kRbMapBytes / 16); i += kRbThreads) reinterpret_cast<uint4*>(M1)[i] = zero;
+  for (int i = tid; i < (int)(kRbMapBytes / 16); i += kRbFusedThreads) reinterpret_cast<uint4*>(M1)[i] = zero;
   __syncthreads();
   rb_stage1_layer<false, false>(M0, M1, a.w[1], a.bias[1], a.KP[1]);
   __syncthreads();
@@ -420,7 +421,7 @@ __global__ __launch_bounds__(kRbThreads, 1) void k_rb_stage1(RbStage1Args a) {
   __syncthreads();
   // the block output, un-swizzled, 16 bytes per store
   uint4* dst = reinterpret_cast<uint4*>(a.y + (int64_t)c * 32 * 32 * 32);
-  for (int i = tid; i < 32 * 32 * 4; i += kRbThreads) {
+  for (int i = tid; i < 32 * 32 * 4; i += kRbFusedThreads) {
     const int P = i >> 2, cg = i & 3;
     const int p = ((P >> 5) + 1) * kRbMapSide + (P & 31) + 1;
     dst[i] = *reinterpret_cast<const uint4*>(M0 + rb_map_off(p, cg));
@@ -447,7 +448,7 @@ __device__ __forceinline__ int rb_map16_off(int p, int cg) {    // bytes, 64-cha
 }
 
 // one GEMM of stage 2: 256 output pixels (16 x 16) x 64 channels; wave w:
-// channel half h = w & 1, pixels 128 (w >> 1) .. + 127 in two passes of 64.
+// channel half h = w & 1, pixels 64 (w >> 1) .. + 63.
 // CONV_A: input the 34 x 34 block-input map (stride 2); else the 18 x 18 map
 // (stride 1) plus the projection chunk from the block-input map.
 template <bool CONV_A, int NKC>
@@ -464,8 +465,8 @@ __device__ __forceinline__ void rb_stage2_gemm(const unsigned char* in32, const 
 #pragma unroll
     for (int t = 0; t < 2; ++t)
       Bw[kc][t] = *reinterpret_cast<const uint4*>(w + (int64_t)(32 * h + 16 * t + l16) * KP + kc * 32 + 8 * g);
-  for (int pass = 0; pass < 2; ++pass) {
-    const int mt0 = 8 * (wave >> 1) + 4 * pass;
+  {
+    const int mt0 = 4 * (wave >> 1);
     floatx4_rb acc[4][2];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
@@ -541,7 +542,7 @@ struct RbStage2Args {
   int copies;
 };
 
-__global__ __launch_bounds__(kRbThreads, 1) void k_rb_stage2(RbStage2Args a) {
+__global__ __launch_bounds__(kRbFusedThreads, 1) void k_rb_stage2(RbStage2Args a) {
   extern __shared__ __align__(16) unsigned char rbm[];
   unsigned char* M32 = rbm;                      // block input, 34 x 34 x 32
   unsigned char* M64 = rbm + kRbMapBytes;        // conv a output, 18 x 18 x 64
@@ -549,10 +550,10 @@ __global__ __launch_bounds__(kRbThreads, 1) void k_rb_stage2(RbStage2Args a) {
   if (c >= a.copies) return;
   const int tid = threadIdx.x;
   const uint4 zero = {0u, 0u, 0u, 0u};
-  for (int i = tid; i < (int)(kRbStage2Lds / 16); i += kRbThreads) reinterpret_cast<uint4*>(rbm)[i] = zero;
+  for (int i = tid; i < (int)(kRbStage2Lds / 16); i += kRbFusedThreads) reinterpret_cast<uint4*>(rbm)[i] = zero;
   __syncthreads();
   const uint4* src = reinterpret_cast<const uint4*>(a.x + (int64_t)c * 32 * 32 * 32);
-  for (int i = tid; i < 32 * 32 * 4; i += kRbThreads) {
+  for (int i = tid; i < 32 * 32 * 4; i += kRbFusedThreads) {
     const int P = i >> 2, cg = i & 3;
     const int p = ((P >> 5) + 1) * kRbMapSide + (P & 31) + 1;
     *reinterpret_cast<uint4*>(M32 + rb_map_off(p, cg)) = src[i];
@@ -696,7 +697,7 @@ hipError_t launch_rb_score(const float* params, const float* stamps, int n, floa
     sa.y = steps[2].y;
     sa.copies = (int)copies;
     if (sa.KP[0] != 96 || sa.KP[1] != 288 || sa.KP[2] != 288) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_rb_stage1, dim3((unsigned)copies), dim3(kRbThreads), kRbStage1Lds, st, sa);
+    hipLaunchKernelGGL(k_rb_stage1, dim3((unsigned)copies), dim3(kRbFusedThreads), kRbStage1Lds, st, sa);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   {
@@ -710,7 +711,7 @@ hipError_t launch_rb_score(const float* params, const float* stamps, int n, floa
     sa.y = steps[4].y;
     sa.copies = (int)copies;
     if (sa.KP[0] != 288 || sa.KP[1] != 608) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_rb_stage2, dim3((unsigned)copies), dim3(kRbThreads), kRbStage2Lds, st, sa);
+    hipLaunchKernelGGL(k_rb_stage2, dim3((unsigned)copies), dim3(kRbFusedThreads), kRbStage2Lds, st, sa);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   for (int l = 5; l < kRbGemms; ++l) {
