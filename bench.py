@@ -352,6 +352,7 @@ def run_batch(steps, warmup):
         del pr
     torch.cuda.synchronize()
     rpb, team = b.tune()
+    knobs = b.knobs()
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         for _ in range(warmup):
@@ -384,7 +385,7 @@ def run_batch(steps, warmup):
     t_step = (t1 - t0) / steps
     return dict(value=round(ccd_equiv / t_step, 3) if ok else 0.0, ms=t_step * 1e3, items=len(shapes),
                 ccd_equiv=ccd_equiv, items_per_s=len(shapes) / t_step, max_chi2=float(chis.max()),
-                rpb=rpb, team=team, phase=phase, steps=steps)
+                rpb=rpb, team=team, knobs=knobs, phase=phase, steps=steps)
 
 
 def run_stamps(pair, R, S, steps, warmup):
@@ -723,7 +724,7 @@ def batch_line(args, r):
                                "spectra with FP64-mean pedestals, FP64 solve, one launch per phase, HIP graph",
                    "form": "batched", "parallelism": "single GPU", "items": r["items"],
                    "ccd_equivalents": round(r["ccd_equiv"], 2), "tuned_rows_per_workgroup": r["rpb"],
-                   "tuned_solve_team": r["team"]},
+                   "tuned_solve_team": r["team"], "tuned_knobs": r["knobs"]},
         "items_per_s": round(r["items_per_s"], 2), "max_chi2_nu": round(r["max_chi2"], 5),
         "phase_us_eager": {k: round(v, 1) for k, v in r["phase"].items()},
     }

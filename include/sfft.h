@@ -188,6 +188,18 @@ sfft_status sfft_solve(sfft_handle handle, const sfft_desc* desc,
 sfft_status sfft_set_solve_team(sfft_handle handle, int32_t team);
 sfft_status sfft_get_solve_team(sfft_handle handle, int32_t* team);
 
+/* Stage order of the row pass's FFTs along x (the transforms of the FFT
+ * form of the least-squares build, paper Sec. 1) on this handle. Every plan
+ * is a mixed-radix Stockham transform of length W = 2^a 3^b 5^c with stages
+ * of radix 8 (as many as fit), then one of 4 or 2, then 3s, then 5s:
+ *   order 0 (default): that sequence; order 1: the same stages reversed.
+ * Both compute the same DFT; the sums are grouped differently, so spectra
+ * (and everything fitted from them) can differ in the last bits. The
+ * batched form has its own setting (sfft_batch_knobs).
+ * Other values: SFFT_ERR_INVALID_ARG. */
+sfft_status sfft_set_radix_order(sfft_handle handle, int32_t order);
+sfft_status sfft_get_radix_order(sfft_handle handle, int32_t* order);
+
 /* D = S' - M_coef(R') with periodic boundaries, accumulated in FP64, in the
  * descriptor's kernel convention (the whole image; no mask).
  * chi2 (nullable, device double): reduced chi^2 of D over the image minus an
@@ -220,8 +232,9 @@ sfft_status sfft_subtract_noalloc(sfft_handle handle, const sfft_desc* desc,
  * the solve runs teams of co-resident workgroups over a queue of the items,
  * largest first; the subtract
  * is one launch per distinct L), and the whole sequence can be captured in
- * one HIP graph. The row-pass rows per workgroup and the solve team size
- * come from an autotuner (sfft_batch_tune), remembered per batch
+ * one HIP graph. The launch configuration (sfft_batch_knobs: row-pass rows
+ * per workgroup, row FFT radix order, subtract tile height, solve team
+ * size) comes from an autotuner (sfft_batch_tune), remembered per batch
  * composition and device in the handle and, when the environment variable
  * SFFT_TUNE_CACHE names a file, across processes.
  * Restrictions: compute SFFT_COMPUTE_FP32, image_dtype SFFT_F32, width <=
@@ -252,13 +265,46 @@ sfft_status sfft_batch_run(sfft_batch batch, void* stream);
 /* The same, captured into a HIP graph on the first call and replayed
  * (stream must not be the null stream). */
 sfft_status sfft_batch_run_graph(sfft_batch batch, void* stream);
-/* Times each candidate configuration on the stream (runs the batch several
- * times; results of the last run are valid), keeps the fastest. Either out
- * pointer may be NULL. */
+/* Launch configuration of a batch (the autotuner's search space):
+ *   rows_per_block : row-pass image rows per workgroup, 1..64
+ *   radix_order    : stage order of the row FFTs, 0 or 1 (as in
+ *                    sfft_set_radix_order)
+ *   tile_rows      : subtract output tile height, 16, 32 or 64 (tiles are
+ *                    64 pixels wide; one workgroup of 8 * tile_rows threads
+ *                    per tile)
+ *   team           : solve workgroups per team, 1..128, or 0 for one team
+ *                    per item (CUs / n, at most 64)
+ * The column pass (4 spectrum columns per 512-thread workgroup, the
+ * 128-point y-correlation's thread mapping) and the Cholesky tile (64, the
+ * FP64 matrix-core tile) are fixed by their kernels' designs.
+ * rows_per_block and tile_rows change no bit of the coefficients or the
+ * difference image (chi2 adds one partial sum per subtract tile, so
+ * tile_rows can change its last bits); team (as in sfft_set_solve_team)
+ * and radix_order group sums differently and can change the last bits of
+ * the coefficients. */
+typedef struct {
+  int32_t rows_per_block;
+  int32_t radix_order;
+  int32_t tile_rows;
+  int32_t team;
+} sfft_batch_knobs;
+
+/* Times candidate configurations on the stream and keeps the fastest: the
+ * row-pass rows per workgroup with the radix order, then the solve team,
+ * then the subtract tile height (the phases run one after another, so each
+ * group is timed with the others fixed). Runs the batch several times;
+ * results of the last run are valid. Either out pointer may be NULL; the
+ * whole choice is read back with sfft_batch_get_knobs. */
 sfft_status sfft_batch_tune(sfft_batch batch, void* stream, int32_t* rows_per_block, int32_t* team);
-/* Sets the configuration without timing: row-pass rows per workgroup 1..64,
- * solve team size 1..128 workgroups, or 0 for one team per item (CUs / n,
- * at most 64).
+/* Sets (without timing) or reads the whole configuration. Out-of-range
+ * values: SFFT_ERR_INVALID_ARG, the batch unchanged. Setting is blocking
+ * (re-uploads the tables; not inside a stream capture); a captured graph is
+ * discarded and captured again on the next sfft_batch_run_graph. */
+sfft_status sfft_batch_set_knobs(sfft_batch batch, const sfft_batch_knobs* knobs);
+sfft_status sfft_batch_get_knobs(sfft_batch batch, sfft_batch_knobs* knobs);
+/* Sets two knobs without timing (the others keep their values): row-pass
+ * rows per workgroup 1..64, solve team size 1..128 workgroups, or 0 for one
+ * team per item (CUs / n, at most 64).
  * Out-of-range values: SFFT_ERR_INVALID_ARG, the batch unchanged. Blocking
  * (re-uploads the tables; not inside a stream capture); a captured graph is
  * discarded and captured again on the next sfft_batch_run_graph. */

@@ -66,6 +66,15 @@ class SolveInfo(ctypes.Structure):
 SOLVE_INFO_BYTES = ctypes.sizeof(SolveInfo)
 
 
+class BatchKnobs(ctypes.Structure):
+    """sfft_batch_knobs: the batched form's launch configuration."""
+    _fields_ = [("rows_per_block", ctypes.c_int32), ("radix_order", ctypes.c_int32),
+                ("tile_rows", ctypes.c_int32), ("team", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
 class BatchItem(ctypes.Structure):
     _fields_ = [
         ("desc", Desc),
@@ -98,6 +107,8 @@ _SIGS = {
     "sfft_subtract": (ctypes.c_int, [_P, ctypes.POINTER(Desc), _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "sfft_set_solve_team": (ctypes.c_int, [_P, ctypes.c_int32]),
     "sfft_get_solve_team": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
+    "sfft_set_radix_order": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "sfft_get_radix_order": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "sfft_median_combine": (ctypes.c_int, [_P, ctypes.POINTER(Desc), ctypes.POINTER(_P), ctypes.c_int32,
                                            ctypes.POINTER(ctypes.c_double), ctypes.c_double, _P, _P]),
     "sfft_difference_multi": (ctypes.c_int, [_P, ctypes.POINTER(Desc), ctypes.POINTER(_P), _P, ctypes.c_int32,
@@ -129,6 +140,8 @@ _SIGS = {
     "sfft_batch_run_graph": (ctypes.c_int, [_P, _P]),
     "sfft_batch_tune": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "sfft_batch_plan": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
+    "sfft_batch_set_knobs": (ctypes.c_int, [_P, ctypes.POINTER(BatchKnobs)]),
+    "sfft_batch_get_knobs": (ctypes.c_int, [_P, ctypes.POINTER(BatchKnobs)]),
     "sfft_batch_set_pedestals": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                                 ctypes.POINTER(ctypes.c_double)]),
     "sfft_batch_destroy": (ctypes.c_int, [_P]),
@@ -279,6 +292,16 @@ def sfft_get_solve_team(handle: Handle) -> int:
     return int(t.value)
 
 
+def sfft_set_radix_order(handle: Handle, order: int):
+    _check(lib().sfft_set_radix_order(handle.ptr, int(order)), "sfft_set_radix_order")
+
+
+def sfft_get_radix_order(handle: Handle) -> int:
+    o = ctypes.c_int32(0)
+    _check(lib().sfft_get_radix_order(handle.ptr, ctypes.byref(o)), "sfft_get_radix_order")
+    return int(o.value)
+
+
 def sfft_subtract(handle: Handle, desc: Desc, ref, sci, coef, diff, chi2, ws, stream=None):
     _check(lib().sfft_subtract(handle.ptr, ctypes.byref(desc), _dp(ref), _dp(sci), _dp(coef), _dp(diff),
                                _dp(chi2), _dp(ws), ws.numel() * ws.element_size(), _stream_ptr(stream)),
@@ -334,7 +357,7 @@ class Differencer:
 
     def __init__(self, width, height, L, dk, db, *, image_dtype="float32", compute="fp64",
                  ref_pedestal=0.0, sci_pedestal=0.0, device="cuda", stamps=None, convention="input",
-                 solve_team=0):
+                 solve_team=0, radix_order=0):
         import torch
         self.torch = torch
         self.dtype = torch.float32 if image_dtype in ("float32", torch.float32) else torch.float64
@@ -346,6 +369,8 @@ class Differencer:
         self.handle = Handle()
         if solve_team:
             sfft_set_solve_team(self.handle, solve_team)
+        if radix_order:
+            sfft_set_radix_order(self.handle, radix_order)
         self.N = sfft_num_unknowns(self.desc)
         # stamps = (n_stamps, size): size the workspace for the stamp build as well
         self.stamps = stamps
@@ -800,8 +825,20 @@ class Batch:
         return int(rpb.value), int(team.value)
 
     def plan(self, rows_per_block, team):
-        """Fixed configuration (team 0: one solve team per item)."""
+        """Fixed rows per workgroup and solve team (team 0: one solve team per
+        item); the other knobs keep their values."""
         _check(lib().sfft_batch_plan(self._b, int(rows_per_block), int(team)), "sfft_batch_plan")
+
+    def knobs(self) -> dict:
+        """The whole launch configuration in use (team resolved)."""
+        k = BatchKnobs()
+        _check(lib().sfft_batch_get_knobs(self._b, ctypes.byref(k)), "sfft_batch_get_knobs")
+        return k.as_dict()
+
+    def set_knobs(self, rows_per_block=4, radix_order=0, tile_rows=32, team=0):
+        self._sync()
+        k = BatchKnobs(int(rows_per_block), int(radix_order), int(tile_rows), int(team))
+        _check(lib().sfft_batch_set_knobs(self._b, ctypes.byref(k)), "sfft_batch_set_knobs")
 
     def info(self, k) -> SolveInfo:
         return read_info(self.bufs[k].info)

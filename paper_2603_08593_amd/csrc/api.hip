@@ -75,7 +75,8 @@ struct sfft_handle_s {
   std::map<int, sfft::Twiddles> tw;   // keyed by transform length
   sfft::Prof prof{};                  // timing events per sfft_prof_slot
   int solve_team = 0;                 // workgroups of the single-pair solve (0: default)
-  std::map<std::string, std::pair<int, int>> tuned;   // batch key -> (rows per block, solve team)
+  int radix_order = 0;                // stage order of the single-pair row FFTs
+  std::map<std::string, sfft_batch_knobs> tuned;   // batch key -> tuned configuration
   char arch[64] = {0};
 };
 
@@ -83,7 +84,7 @@ struct sfft_batch_s {
   sfft_handle handle = nullptr;
   std::vector<sfft_batch_item> items;
   int max_refine = 2;
-  int rows_per_block = 4, team = 0;
+  sfft_batch_knobs knobs{4, 0, sfft::kSubTY, 0};   // team: the value in use (0 resolved)
   std::string key;
   sfft::BuildBatch* build = nullptr;
   sfft::SolveBatch* solve = nullptr;
@@ -258,7 +259,7 @@ sfft_status sfft_build_system(sfft_handle h, const sfft_desc* d, const void* ref
   if (get_twiddles(h, d->width, tw) != hipSuccess) return SFFT_ERR_HIP;
   if (get_twiddles(h, kTP, t128) != hipSuccess) return SFFT_ERR_HIP;
   const bool f32 = d->compute == SFFT_COMPUTE_FP32;
-  BuildPlan p{f32 ? tw.w32 : tw.w64, tw.w64, f32 ? t128.w32 : t128.w64, h->num_cus};
+  BuildPlan p{f32 ? tw.w32 : tw.w64, tw.w64, f32 ? t128.w32 : t128.w64, h->num_cus, h->radix_order};
   const hipError_t e = launch_build(*d, ref, sci, G, hv, static_cast<unsigned char*>(ws), p,
                                     &h->prof, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
@@ -277,7 +278,7 @@ sfft_status sfft_build_system_masked(sfft_handle h, const sfft_desc* d, const vo
   if (get_twiddles(h, d->width, tw) != hipSuccess) return SFFT_ERR_HIP;
   if (get_twiddles(h, kTP, t128) != hipSuccess) return SFFT_ERR_HIP;
   const bool f32 = d->compute == SFFT_COMPUTE_FP32;
-  BuildPlan p{f32 ? tw.w32 : tw.w64, tw.w64, f32 ? t128.w32 : t128.w64, h->num_cus};
+  BuildPlan p{f32 ? tw.w32 : tw.w64, tw.w64, f32 ? t128.w32 : t128.w64, h->num_cus, h->radix_order};
   const hipError_t e = launch_build_masked(*d, ref, sci, mask, mask_ld, G, hv, static_cast<unsigned char*>(ws), p,
                                            &h->prof, static_cast<hipStream_t>(stream), false);
   return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
@@ -307,6 +308,18 @@ sfft_status sfft_set_solve_team(sfft_handle h, int32_t team) {
 sfft_status sfft_get_solve_team(sfft_handle h, int32_t* team) {
   if (!h || !team) return SFFT_ERR_INVALID_ARG;
   *team = h->solve_team;
+  return SFFT_OK;
+}
+
+sfft_status sfft_set_radix_order(sfft_handle h, int32_t order) {
+  if (!h || order < 0 || order > 1) return SFFT_ERR_INVALID_ARG;
+  h->radix_order = order;
+  return SFFT_OK;
+}
+
+sfft_status sfft_get_radix_order(sfft_handle h, int32_t* order) {
+  if (!h || !order) return SFFT_ERR_INVALID_ARG;
+  *order = h->radix_order;
   return SFFT_OK;
 }
 
@@ -398,7 +411,7 @@ sfft_status sfft_refit_background(sfft_handle h, const sfft_desc* d, const void*
   if (d->convention != SFFT_CONV_INPUT_PIXEL) return SFFT_ERR_UNSUPPORTED;
   if ((s = check_ws(ws, ws_bytes, make_layout(make_geometry(*d)).build_end)) != SFFT_OK) return s;
   if ((s = check_device(h)) != SFFT_OK) return s;
-  BuildPlan p{nullptr, nullptr, nullptr, h->num_cus};
+  BuildPlan p{nullptr, nullptr, nullptr, h->num_cus, 0};
   const hipError_t e = launch_bg_refit(*d, ref, sci, coef, G, hv, static_cast<unsigned char*>(ws), p,
                                        static_cast<hipStream_t>(stream));
   return e == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
@@ -473,7 +486,7 @@ sfft_status sfft_difference_multi(sfft_handle h, const sfft_desc* d, const void*
   if (get_twiddles(h, d->width, tw) != hipSuccess) return SFFT_ERR_HIP;
   if (get_twiddles(h, kTP, t128) != hipSuccess) return SFFT_ERR_HIP;
   const bool f32 = d->compute == SFFT_COMPUTE_FP32;
-  const BuildPlan p{f32 ? tw.w32 : tw.w64, tw.w64, f32 ? t128.w32 : t128.w64, h->num_cus};
+  const BuildPlan p{f32 ? tw.w32 : tw.w64, tw.w64, f32 ? t128.w32 : t128.w64, h->num_cus, h->radix_order};
   hipStream_t st = static_cast<hipStream_t>(stream);
   unsigned char* w = static_cast<unsigned char*>(ws);
   const int64_t N = sfft_num_unknowns(d);
@@ -667,8 +680,13 @@ static void batch_release(sfft_batch b) {
   b->dev_bytes = 0;
 }
 
-// (re)build the per-phase tables for the given tunables and upload them
-static sfft_status batch_plan(sfft_batch b, int rows_per_block, int team) {
+static bool knobs_valid(const sfft_batch_knobs& k) {
+  return k.rows_per_block >= 1 && k.rows_per_block <= 64 && k.radix_order >= 0 && k.radix_order <= 1 &&
+         (k.tile_rows == 16 || k.tile_rows == 32 || k.tile_rows == 64) && k.team >= 0 && k.team <= kMaxTeam;
+}
+
+// (re)build the per-phase tables for the given configuration and upload them
+static sfft_status batch_plan(sfft_batch b, const sfft_batch_knobs& kn) {
   batch_release(b);
   const int n = (int)b->items.size();
   std::vector<BuildItem> bi(n);
@@ -680,18 +698,18 @@ static sfft_status batch_plan(sfft_batch b, int rows_per_block, int team) {
     Twiddles tw, t128;
     if (get_twiddles(b->handle, it.desc.width, tw) != hipSuccess) return SFFT_ERR_HIP;
     if (get_twiddles(b->handle, kTP, t128) != hipSuccess) return SFFT_ERR_HIP;
-    plans[k] = BuildPlan{tw.w32, tw.w64, t128.w32, b->handle->num_cus};
+    plans[k] = BuildPlan{tw.w32, tw.w64, t128.w32, b->handle->num_cus, kn.radix_order};
     unsigned char* ws = static_cast<unsigned char*>(it.ws);
     bi[k] = BuildItem{it.desc, it.ref, it.sci, it.G, it.h, ws};
     si[k] = SolveItem{it.desc, it.G, it.h, it.coef, it.info, ws};
     ui[k] = SubItem{it.desc, it.ref, it.sci, it.coef, it.diff, it.chi2, ws};
   }
   hipError_t e;
-  b->build = build_batch_create(bi.data(), n, plans.data(), rows_per_block, &e);
+  b->build = build_batch_create(bi.data(), n, plans.data(), kn.rows_per_block, &e);
   if (!b->build) return e == hipErrorInvalidValue ? SFFT_ERR_UNSUPPORTED : SFFT_ERR_HIP;
-  b->solve = solve_batch_create(si.data(), n, b->max_refine, team, b->handle->num_cus, &e);
+  b->solve = solve_batch_create(si.data(), n, b->max_refine, kn.team, b->handle->num_cus, &e);
   if (!b->solve) return e == hipErrorInvalidValue ? SFFT_ERR_UNSUPPORTED : SFFT_ERR_HIP;
-  b->sub = sub_batch_create(ui.data(), n, &e);
+  b->sub = sub_batch_create(ui.data(), n, kn.tile_rows, &e);
   if (!b->sub) return e == hipErrorInvalidValue ? SFFT_ERR_UNSUPPORTED : SFFT_ERR_HIP;
   const size_t o1 = align256(build_batch_dev_bytes(b->build));
   const size_t o2 = o1 + align256(solve_batch_dev_bytes(b->solve));
@@ -701,8 +719,8 @@ static sfft_status batch_plan(sfft_batch b, int rows_per_block, int team) {
   if (build_batch_upload(b->build, d) != hipSuccess || solve_batch_upload(b->solve, d + o1) != hipSuccess ||
       sub_batch_upload(b->sub, d + o2) != hipSuccess)
     return SFFT_ERR_HIP;
-  b->rows_per_block = rows_per_block;
-  b->team = solve_batch_team(b->solve);
+  b->knobs = kn;
+  b->knobs.team = solve_batch_team(b->solve);
   return SFFT_OK;
 }
 
@@ -723,9 +741,12 @@ static std::string batch_key(sfft_handle h, const std::vector<sfft_batch_item>& 
 
 static const char* tune_cache_path() { return std::getenv("SFFT_TUNE_CACHE"); }
 
-static bool tune_cache_lookup(sfft_handle h, const std::string& key, int& rpb, int& team) {
+// cache lines: "<key> <rows per block> <team> <radix order> <tile rows>";
+// lines with only the first two values (an older cache) take the defaults
+// of the others
+static bool tune_cache_lookup(sfft_handle h, const std::string& key, sfft_batch_knobs& kn) {
   auto it = h->tuned.find(key);
-  if (it != h->tuned.end()) { rpb = it->second.first; team = it->second.second; return true; }
+  if (it != h->tuned.end()) { kn = it->second; return true; }
   const char* path = tune_cache_path();
   if (!path) return false;
   FILE* f = std::fopen(path, "r");
@@ -734,21 +755,26 @@ static bool tune_cache_lookup(sfft_handle h, const std::string& key, int& rpb, i
   bool found = false;
   while (std::fgets(line, sizeof line, f)) {
     char k[3900];
-    int a = 0, b = 0;
-    if (std::sscanf(line, "%3899s %d %d", k, &a, &b) == 3 && key == k) { rpb = a; team = b; found = true; }
+    sfft_batch_knobs c{4, 0, kSubTY, 0};
+    const int got = std::sscanf(line, "%3899s %d %d %d %d", k, &c.rows_per_block, &c.team, &c.radix_order,
+                                &c.tile_rows);
+    if (got >= 3 && key == k) {
+      if (got < 5) { c.radix_order = 0; c.tile_rows = kSubTY; }
+      if (knobs_valid(c)) { kn = c; found = true; }
+    }
   }
   std::fclose(f);
-  if (found) h->tuned[key] = {rpb, team};
+  if (found) h->tuned[key] = kn;
   return found;
 }
 
-static void tune_cache_store(sfft_handle h, const std::string& key, int rpb, int team) {
-  h->tuned[key] = {rpb, team};
+static void tune_cache_store(sfft_handle h, const std::string& key, const sfft_batch_knobs& kn) {
+  h->tuned[key] = kn;
   const char* path = tune_cache_path();
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s %d %d\n", key.c_str(), rpb, team);
+  std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), kn.rows_per_block, kn.team, kn.radix_order, kn.tile_rows);
   std::fclose(f);
 }
 
@@ -775,9 +801,9 @@ sfft_status sfft_batch_create(sfft_handle h, const sfft_batch_item* items, int32
   b->items.assign(items, items + n);
   b->max_refine = max_refine;
   b->key = batch_key(h, b->items);
-  int rpb = 4, team = 0;
-  (void)tune_cache_lookup(h, b->key, rpb, team);
-  if ((s = batch_plan(b, rpb, team)) != SFFT_OK) {
+  sfft_batch_knobs kn{4, 0, kSubTY, 0};
+  (void)tune_cache_lookup(h, b->key, kn);
+  if ((s = batch_plan(b, kn)) != SFFT_OK) {
     batch_release(b);
     delete b;
     return s;
@@ -823,9 +849,13 @@ sfft_status sfft_batch_run_graph(sfft_batch b, void* stream) {
   return hipGraphLaunch(b->exec, st) == hipSuccess ? SFFT_OK : SFFT_ERR_HIP;
 }
 
-// Autotuner: times the whole batch for each candidate (row-pass rows per
-// workgroup x solve team size) with events on the stream, keeps the fastest,
-// and records it in the handle (and in $SFFT_TUNE_CACHE when set).
+// Autotuner. The three phases run one after another and each knob acts on
+// one phase only (rows per workgroup and radix order: the build; team: the
+// solve; tile rows: the subtract), so the knobs are searched group by group
+// with the others held: build knobs first, then the team, then the tile.
+// Each candidate runs the whole batch twice on the stream, timed by events
+// on the second run; the fastest is kept and recorded in the handle (and in
+// $SFFT_TUNE_CACHE when set).
 sfft_status sfft_batch_tune(sfft_batch b, void* stream, int32_t* rows_per_block, int32_t* team) {
   if (!b) return SFFT_ERR_INVALID_ARG;
   sfft_status s;
@@ -840,39 +870,77 @@ sfft_status sfft_batch_tune(sfft_batch b, void* stream, int32_t* rows_per_block,
   teams.push_back(one_each);
   for (int t : {4, 8, 16, 32, 64})
     if (t > one_each && t <= cus) teams.push_back(t);
-  const int rpbs[] = {2, 4, 8, 16};
   hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return SFFT_ERR_HIP;
-  float best = 1e30f;
-  int brpb = 4, bteam = teams.empty() ? 1 : teams.back();
-  for (int rpb : rpbs)
-    for (int t : teams) {
-      if ((s = batch_plan(b, rpb, t)) != SFFT_OK) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return s; }
-      float ms = 0.f;
-      for (int rep = 0; rep < 2; ++rep) {
-        (void)hipEventRecord(e0, st);
-        if ((s = batch_launch(b, st, nullptr)) != SFFT_OK) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return s; }
-        (void)hipEventRecord(e1, st);
-        if (hipEventSynchronize(e1) != hipSuccess) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return SFFT_ERR_HIP; }
-        (void)hipEventElapsedTime(&ms, e0, e1);
-      }
-      if (ms < best) { best = ms; brpb = rpb; bteam = t; }
+  if (hipEventCreate(&e0) != hipSuccess) return SFFT_ERR_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return SFFT_ERR_HIP; }
+  auto time_knobs = [&](const sfft_batch_knobs& kn, float& ms) -> sfft_status {
+    sfft_status r;
+    if ((r = batch_plan(b, kn)) != SFFT_OK) return r;
+    for (int rep = 0; rep < 2; ++rep) {
+      if (hipEventRecord(e0, st) != hipSuccess) return SFFT_ERR_HIP;
+      if ((r = batch_launch(b, st, nullptr)) != SFFT_OK) return r;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return SFFT_ERR_HIP;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return SFFT_ERR_HIP;
     }
+    return SFFT_OK;
+  };
+  sfft_batch_knobs best{4, 0, kSubTY, teams.back()};
+  float best_ms = 1e30f;
+  auto consider = [&](const sfft_batch_knobs& kn) -> sfft_status {
+    float ms = 0.f;
+    const sfft_status r = time_knobs(kn, ms);
+    if (r == SFFT_OK && ms < best_ms) { best_ms = ms; best = kn; }
+    return r;
+  };
+  const sfft_batch_knobs start = best;
+  for (int rpb : {2, 4, 8, 16})
+    for (int ro : {0, 1}) {
+      sfft_batch_knobs kn = start;
+      kn.rows_per_block = rpb;
+      kn.radix_order = ro;
+      if (s == SFFT_OK) s = consider(kn);
+    }
+  for (size_t i = 0; s == SFFT_OK && i < teams.size(); ++i) {
+    sfft_batch_knobs kn = best;
+    kn.team = teams[i];
+    s = consider(kn);
+  }
+  for (int tr : {16, 32, 64}) {
+    if (s != SFFT_OK) break;
+    sfft_batch_knobs kn = best;
+    kn.tile_rows = tr;
+    s = consider(kn);
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if ((s = batch_plan(b, brpb, bteam)) != SFFT_OK) return s;
-  tune_cache_store(b->handle, b->key, brpb, bteam);
-  if (rows_per_block) *rows_per_block = brpb;
-  if (team) *team = bteam;
+  if (s != SFFT_OK) return s;
+  if ((s = batch_plan(b, best)) != SFFT_OK) return s;
+  tune_cache_store(b->handle, b->key, b->knobs);
+  if (rows_per_block) *rows_per_block = b->knobs.rows_per_block;
+  if (team) *team = b->knobs.team;
   return SFFT_OK;
 }
 
 sfft_status sfft_batch_plan(sfft_batch b, int32_t rows_per_block, int32_t team) {
-  if (!b || rows_per_block < 1 || rows_per_block > 64 || team < 0 || team > kMaxTeam) return SFFT_ERR_INVALID_ARG;
+  if (!b) return SFFT_ERR_INVALID_ARG;
+  sfft_batch_knobs kn = b->knobs;
+  kn.rows_per_block = rows_per_block;
+  kn.team = team;
+  return sfft_batch_set_knobs(b, &kn);
+}
+
+sfft_status sfft_batch_set_knobs(sfft_batch b, const sfft_batch_knobs* knobs) {
+  if (!b || !knobs || !knobs_valid(*knobs)) return SFFT_ERR_INVALID_ARG;
   sfft_status s;
   if ((s = check_device(b->handle)) != SFFT_OK) return s;
   if (hipDeviceSynchronize() != hipSuccess) return SFFT_ERR_HIP;   // tables in use by queued work
-  return batch_plan(b, rows_per_block, team);
+  return batch_plan(b, *knobs);
+}
+
+sfft_status sfft_batch_get_knobs(sfft_batch b, sfft_batch_knobs* knobs) {
+  if (!b || !knobs) return SFFT_ERR_INVALID_ARG;
+  *knobs = b->knobs;
+  return SFFT_OK;
 }
 
 sfft_status sfft_batch_set_pedestals(sfft_batch b, const double* ref_pedestals, const double* sci_pedestals) {
@@ -887,7 +955,7 @@ sfft_status sfft_batch_set_pedestals(sfft_batch b, const double* ref_pedestals, 
     b->items[k].desc.ref_pedestal = ref_pedestals[k];
     b->items[k].desc.sci_pedestal = sci_pedestals[k];
   }
-  return batch_plan(b, b->rows_per_block, b->team);
+  return batch_plan(b, b->knobs);
 }
 
 sfft_status sfft_batch_destroy(sfft_batch b) {

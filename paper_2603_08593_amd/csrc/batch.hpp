@@ -55,7 +55,7 @@ struct SubItem {
 };
 
 struct SubBatch;
-SubBatch* sub_batch_create(const SubItem* items, int n, hipError_t* err);
+SubBatch* sub_batch_create(const SubItem* items, int n, int tile_rows, hipError_t* err);
 size_t sub_batch_dev_bytes(const SubBatch* b);
 hipError_t sub_batch_upload(SubBatch* b, unsigned char* dev);
 hipError_t sub_batch_launch(const SubBatch* b, const Prof* pf, hipStream_t st);

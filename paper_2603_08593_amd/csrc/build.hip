@@ -121,8 +121,11 @@ __device__ void fft_lds(cx<T>* buf, const cx<T>* twl, const cx<T>* twh, int N, c
   }
 }
 
-// radix plan: as many 8s as possible, then 4 or 2, then 3s and 5s
-inline FftPlan make_fft_plan(int n) {
+// radix plan: as many 8s as possible, then 4 or 2, then 3s and 5s (order
+// 0), or those stages reversed (order 1). A Stockham pass takes any radix at
+// any position, so both orders give the DFT; they group its sums
+// differently and touch LDS with different strides per stage.
+inline FftPlan make_fft_plan(int n, int order = 0) {
   FftPlan p{};
   int twos = 0, threes = 0, fives = 0;
   while (n % 2 == 0) { n /= 2; ++twos; }
@@ -133,6 +136,12 @@ inline FftPlan make_fft_plan(int n) {
   if (twos == 1) p.radix[p.nstages++] = 2;
   for (int i = 0; i < threes; ++i) p.radix[p.nstages++] = 3;
   for (int i = 0; i < fives; ++i) p.radix[p.nstages++] = 5;
+  if (order == 1)
+    for (int i = 0, j = p.nstages - 1; i < j; ++i, --j) {
+      const int t = p.radix[i];
+      p.radix[i] = p.radix[j];
+      p.radix[j] = t;
+    }
   return p;
 }
 
@@ -1202,7 +1211,7 @@ static RowArgs make_row_args(const Geometry& g, const sfft_desc& d, const void* 
                              unsigned char* ws, const Layout& l, const BuildPlan& p) {
   RowArgs a{};
   a.R = R; a.S = S; a.ld = d.ld; a.W = g.W; a.H = g.H; a.DK = g.DK; a.DB = g.DB; a.r = g.r;
-  a.plan = make_fft_plan(g.W);
+  a.plan = make_fft_plan(g.W, p.radix_order);
   a.cR = d.ref_pedestal; a.cS = d.sci_pedestal;
   a.sx = g.W > 1 ? 2.0 / (double)(g.W - 1) : 0.0;
   a.F = ws + l.F; a.pitchK = g.pitchK; a.planeK = g.planeK;

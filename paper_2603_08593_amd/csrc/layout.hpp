@@ -14,7 +14,8 @@ constexpr int kColsPerWG = 4;   // k_x columns per column-pass workgroup
 constexpr int kColThreads = 512;
 constexpr int kRowThreads = 256;
 constexpr int kTile = 64;       // Cholesky tile
-constexpr int kSubTX = 64, kSubTY = 32;   // subtract output tile
+constexpr int kSubTX = 64, kSubTY = 32;   // subtract output tile (single-pair launch)
+constexpr int kSubTYMin = 16;             // smallest tile height a batch may choose
 constexpr int kSubThreads = kSubTX * kSubTY / 8;   // 8 pixels of a row per thread
 constexpr int kMaxW = 4096;
 // solve synchronisation words: [0, 256) barrier flags, [256, 512) progress
@@ -56,6 +57,7 @@ struct BuildPlan {
   const void* twW64;    // same table in FP64
   const void* tw128;    // exp(-2 pi i m / 128) in the build precision
   int num_cus;
+  int radix_order;      // row FFT stage order: 0 largest radix first, 1 reversed
 };
 
 // caller-provided timing events per sfft_prof_slot
@@ -83,7 +85,7 @@ struct Layout {
   size_t total;
   int nmom;           // doubles in the moment block
   int nt;             // Cholesky tiles per side
-  int npartials;
+  int npartials;      // subtract tiles of the single-pair launch
 };
 
 // moment block (doubles): M2[(DK+DB+1)^2], E[2r*(DK+DB+1)], MSy[(DB+1)^2],
@@ -93,8 +95,8 @@ inline int moment_count(const Geometry& g) {
   return nm * nm + 2 * g.r * nm + (g.DB + 1) * (g.DB + 1) + 2 * (2 * g.DB + 1);
 }
 
-inline int subtract_blocks(const Geometry& g) {
-  return ((g.W + kSubTX - 1) / kSubTX) * ((g.H + kSubTY - 1) / kSubTY);
+inline int subtract_blocks(const Geometry& g, int tile_rows = kSubTY) {
+  return ((g.W + kSubTX - 1) / kSubTX) * ((g.H + tile_rows - 1) / tile_rows);
 }
 
 inline Layout make_layout(const Geometry& g) {
@@ -137,8 +139,9 @@ inline Layout make_layout(const Geometry& g) {
   l.solve_end = o;
   // subtract region
   o = base;
+  // chi2 partials, one per subtract tile: room for the smallest tile height
   l.npartials = subtract_blocks(g);
-  l.partials = o; o = align256(o + sizeof(double) * l.npartials);
+  l.partials = o; o = align256(o + sizeof(double) * subtract_blocks(g, kSubTYMin));
   // coefficients of the chi2 judge's kappa2 polynomial, (2 DK + 1)^2
   l.k2 = o; o = align256(o + sizeof(double) * 81);
   l.sub_end = o;

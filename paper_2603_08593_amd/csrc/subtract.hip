@@ -96,15 +96,19 @@ __global__ __launch_bounds__(kK2Threads) void k_kappa2_batch(const SubArgs* args
 // OUTPIX: the kernel polynomial is evaluated at the output pixel x (the
 // output-pixel convention) instead of the input pixel x - d: the Horner
 // coordinates are those of the output row and pixel.
-template <int L, int DK, typename TIO, bool OUTPIX = false>
+//
+// TY: output tile height (the tile is kSubTX = 64 pixels wide, one thread per
+// 8 pixels of a row, so the workgroup has 8 * TY threads).
+template <int L, int DK, typename TIO, bool OUTPIX = false, int TY = kSubTY>
 __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
   constexpr int r = (L - 1) / 2;
   constexpr int NK = (DK + 1) * (DK + 2) / 2;
-  constexpr int TX = kSubTX, TY = kSubTY, P = 8;
+  constexpr int TX = kSubTX, P = 8;
+  constexpr int NT = TX * TY / P;
   constexpr int RW = TX + 2 * r, RH = TY + 2 * r;
   constexpr int NQ = P + 2 * r;
   __shared__ double Rt[RH][RW + 1];
-  __shared__ double red[kSubThreads / 64];
+  __shared__ double red[NT / 64];
   const int tid = threadIdx.x;
   const int W = a.W, H = a.H;
   // the fitted coefficients are read-only for the whole launch: reading them
@@ -116,12 +120,12 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
   const bool inner = x0 >= r && x0 + RW - r <= W && y0 >= r && y0 + RH - r <= H;
   if (inner) {
     const TIO* Rb = static_cast<const TIO*>(a.R) + (int64_t)(y0 - r) * a.ld + (x0 - r);
-    for (int i = tid; i < RH * RW; i += kSubThreads) {
+    for (int i = tid; i < RH * RW; i += NT) {
       const int ly = i / RW, lx = i - (i / RW) * RW;
       Rt[ly][lx] = (double)Rb[(int64_t)ly * a.ld + lx] - a.cR;
     }
   } else {
-    for (int i = tid; i < RH * RW; i += kSubThreads) {
+    for (int i = tid; i < RH * RW; i += NT) {
       const int ly = i / RW, lx = i - (i / RW) * RW;
       int yy = y0 + ly - r, xx = x0 + lx - r;
       yy = (yy < 0) ? yy + H : yy;
@@ -287,7 +291,7 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
     if (tid == 0) {
       double t = red[0];
 #pragma unroll
-      for (int w = 1; w < kSubThreads / 64; ++w) t += red[w];
+      for (int w = 1; w < NT / 64; ++w) t += red[w];
       a.partials[vb.y * vb.nx + vb.x] = t;
     }
   }
@@ -315,11 +319,12 @@ __global__ __launch_bounds__(kSubThreads, (subtract_waves<L, DK>())) void k_subt
   subtract_body<L, DK, TIO, OUTPIX>(a, VB{tx, (int)blockIdx.y, gx, (int)gridDim.y});
 }
 
-template <int L, int DK, typename TIO>
-__global__ __launch_bounds__(kSubThreads, (subtract_waves<L, DK>())) void k_subtract_batch(const SubArgs* args, const BatchTab* tab, int n) {
+// batched items (FP32 images), tiles of 64 x TY pixels
+template <int L, int DK, int TY>
+__global__ __launch_bounds__(kSubTX * TY / 8, (subtract_waves<L, DK>())) void k_subtract_batch(const SubArgs* args, const BatchTab* tab, int n) {
   int item;
   VB vb;
-  if (batch_locate(tab, n, item, vb)) subtract_body<L, DK, TIO>(args[item], vb);
+  if (batch_locate(tab, n, item, vb)) subtract_body<L, DK, float, false, TY>(args[item], vb);
 }
 
 __global__ __launch_bounds__(1024) void k_chi2_final(const double* partials, int n, double dof,
@@ -501,7 +506,7 @@ __global__ __launch_bounds__(1024) void k_chi2_final_batch(const Chi2Item* items
 
 struct SubBatch {
   int n = 0, DK = 0;
-  bool f32 = true;
+  int tile_rows = kSubTY;                    // output tile height: 16, 32 or 64
   std::vector<int> Ls;                       // distinct kernel sizes
   std::vector<std::vector<SubArgs>> args;    // per size
   std::vector<std::vector<BatchTab>> tabs;   // per size
@@ -512,21 +517,24 @@ struct SubBatch {
   Chi2Item* dchi = nullptr;
 };
 
-SubBatch* sub_batch_create(const SubItem* items, int n, hipError_t* err) {
+SubBatch* sub_batch_create(const SubItem* items, int n, int tile_rows, hipError_t* err) {
+  if (tile_rows != 16 && tile_rows != 32 && tile_rows != 64) {
+    *err = hipErrorInvalidValue;
+    return nullptr;
+  }
   SubBatch* b = new (std::nothrow) SubBatch();
   if (!b) { *err = hipErrorOutOfMemory; return nullptr; }
   b->n = n;
+  b->tile_rows = tile_rows;
   for (int k = 0; k < n; ++k) {
     const SubItem& it = items[k];
     const Geometry g = make_geometry(it.d);
-    const bool f32 = it.d.image_dtype == SFFT_F32;
-    if ((k > 0 && (g.DK != b->DK || f32 != b->f32)) || !it.chi2) {
+    if ((k > 0 && g.DK != b->DK) || it.d.image_dtype != SFFT_F32 || !it.chi2) {
       delete b;
       *err = hipErrorInvalidValue;
       return nullptr;
     }
     b->DK = g.DK;
-    b->f32 = f32;
     int slot = -1;
     for (size_t q = 0; q < b->Ls.size(); ++q)
       if (b->Ls[q] == g.L) slot = (int)q;
@@ -544,14 +552,14 @@ SubBatch* sub_batch_create(const SubItem* items, int n, hipError_t* err) {
     BatchTab t{};
     t.start = b->blocks[slot];
     t.nx = (g.W + kSubTX - 1) / kSubTX;
-    t.ny = (g.H + kSubTY - 1) / kSubTY;
+    t.ny = (g.H + tile_rows - 1) / tile_rows;
     b->tabs[slot].push_back(t);
     b->blocks[slot] += t.nx * t.ny;
     Chi2Item c{};
     c.partials = reinterpret_cast<const double*>(it.ws + l.partials);
     c.out = it.chi2;
     c.dof = chi2_dof(g);
-    c.n = l.npartials;
+    c.n = subtract_blocks(g, tile_rows);   // within the workspace's room (tile_rows >= kSubTYMin)
     b->chi.push_back(c);
   }
   *err = hipSuccess;
@@ -588,21 +596,22 @@ hipError_t sub_batch_upload(SubBatch* b, unsigned char* dev) {
   return hipMemcpy(dev, blob.data(), blob.size(), hipMemcpyHostToDevice);
 }
 
+template <int L, int TY>
+static void sub_batch_lt(const SubBatch* b, int q, hipStream_t st) {
+  const int n = (int)b->args[q].size();
+  const dim3 grid(b->blocks[q]), block(kSubTX * TY / 8);
+  const SubArgs* args = b->dargs[q];
+  const BatchTab* tab = b->dtabs[q];
+  if (b->DK == 0) hipLaunchKernelGGL((k_subtract_batch<L, 0, TY>), grid, block, 0, st, args, tab, n);
+  else if (b->DK == 1) hipLaunchKernelGGL((k_subtract_batch<L, 1, TY>), grid, block, 0, st, args, tab, n);
+  else hipLaunchKernelGGL((k_subtract_batch<L, 2, TY>), grid, block, 0, st, args, tab, n);
+}
+
 template <int L>
 static void sub_batch_l(const SubBatch* b, int q, hipStream_t st) {
-  const int n = (int)b->args[q].size();
-  const dim3 grid(b->blocks[q]);
-#define SFFT_SB(DKV)                                                                                 \
-  do {                                                                                               \
-    if (b->f32) hipLaunchKernelGGL((k_subtract_batch<L, DKV, float>), grid, dim3(kSubThreads), 0, st,        \
-                                   (const SubArgs*)b->dargs[q], (const BatchTab*)b->dtabs[q], n);     \
-    else hipLaunchKernelGGL((k_subtract_batch<L, DKV, double>), grid, dim3(kSubThreads), 0, st,              \
-                            (const SubArgs*)b->dargs[q], (const BatchTab*)b->dtabs[q], n);            \
-  } while (0)
-  if (b->DK == 0) SFFT_SB(0);
-  else if (b->DK == 1) SFFT_SB(1);
-  else SFFT_SB(2);
-#undef SFFT_SB
+  if (b->tile_rows == 16) sub_batch_lt<L, 16>(b, q, st);
+  else if (b->tile_rows == 64) sub_batch_lt<L, 64>(b, q, st);
+  else sub_batch_lt<L, 32>(b, q, st);
 }
 
 hipError_t sub_batch_launch(const SubBatch* b, const Prof* pf, hipStream_t st) {

@@ -87,3 +87,9 @@ def test_null_arguments_rejected_before_any_device_work():
     assert lib.sfft_set_solve_team(None, 32) == sf.SFFT_ERR_INVALID_ARG
     t = ctypes.c_int32(-1)
     assert lib.sfft_get_solve_team(None, ctypes.byref(t)) == sf.SFFT_ERR_INVALID_ARG
+    # so do the radix-order setting and the batch configuration
+    assert lib.sfft_set_radix_order(None, 1) == sf.SFFT_ERR_INVALID_ARG
+    assert lib.sfft_get_radix_order(None, ctypes.byref(t)) == sf.SFFT_ERR_INVALID_ARG
+    k = sf.BatchKnobs(4, 0, 32, 0)
+    assert lib.sfft_batch_set_knobs(None, ctypes.byref(k)) == sf.SFFT_ERR_INVALID_ARG
+    assert lib.sfft_batch_get_knobs(None, ctypes.byref(k)) == sf.SFFT_ERR_INVALID_ARG

@@ -7,8 +7,10 @@ again when replayed from a captured HIP graph (several replays, with eager
 work and synchronisations between them) and after autotuning.
 
 Bounds: the batched kernels run the same per-item arithmetic as the
-single-pair ones, so coefficients must agree to 1e-12 relative (observed:
-bit-identical) and chi2 to 1e-12."""
+single-pair ones with the same row FFT radix order, so coefficients must
+agree to 1e-12 relative (observed: bit-identical) and chi2 to 1e-12, for
+every launch configuration the autotuner can choose (rows per workgroup,
+radix order, subtract tile height, solve team)."""
 import numpy as np
 import pytest
 
@@ -40,10 +42,10 @@ def _pairs():
     return out
 
 
-def _single(p, torch, sf, peds):
+def _single(p, torch, sf, peds, radix_order=0):
     H, W = p.R.shape
     d = sf.Differencer(W, H, p.L, 2, 2, image_dtype="float32", compute="fp32",
-                       ref_pedestal=peds[0], sci_pedestal=peds[1])
+                       ref_pedestal=peds[0], sci_pedestal=peds[1], radix_order=radix_order)
     d.run(torch.from_numpy(p.R).cuda(), torch.from_numpy(p.S).cuda(), max_refine=1)
     torch.cuda.synchronize()
     return d.buf.coef.cpu().numpy(), float(d.buf.chi2.item()), d.buf.diff.cpu().numpy()
@@ -86,10 +88,45 @@ def test_batch_matches_single_pairs_eager_graph_and_tuned():
         _check(b, refs, f"graph replay {rep}")
     rpb, team = b.tune()
     torch.cuda.synchronize()
-    print(f"  tuned: rows per workgroup {rpb}, solve team {team}", flush=True)
+    kn = b.knobs()
+    print(f"  tuned: {kn}", flush=True)
+    assert (kn["rows_per_block"], kn["team"]) == (rpb, team)
+    if kn["radix_order"] != 0:     # singles with the same row FFT plans
+        refs = [_single(p, torch, sf, b.peds[k], radix_order=kn["radix_order"]) for k, p in enumerate(pairs)]
     b.run()
     torch.cuda.synchronize()
     _check(b, refs, "tuned")
+    b.close()
+
+
+def test_batch_knob_grid():
+    """Every radix order and subtract tile height, with several row blockings
+    and teams: each item equals the single-pair result with the same radix
+    order; invalid knobs are rejected and leave the batch as it was."""
+    torch, sf = _torch(), _sf()
+    pairs = _pairs()
+    b = sf.Batch(SHAPES, dk=2, db=2, max_refine=1)
+    for k, p in enumerate(pairs):
+        b.load(k, torch.from_numpy(p.R).cuda(), torch.from_numpy(p.S).cuda())
+    refs = {ro: [_single(p, torch, sf, b.peds[k], radix_order=ro) for k, p in enumerate(pairs)]
+            for ro in (0, 1)}
+    grid = [(2, 0, 16, 8), (4, 1, 16, 0), (8, 0, 64, 16), (16, 1, 64, 4), (4, 1, 32, 32), (1, 0, 32, 3)]
+    for rpb, ro, tr, team in grid:
+        b.set_knobs(rows_per_block=rpb, radix_order=ro, tile_rows=tr, team=team)
+        kn = b.knobs()
+        assert (kn["rows_per_block"], kn["radix_order"], kn["tile_rows"]) == (rpb, ro, tr)
+        for k in range(len(SHAPES)):
+            b.bufs[k].coef.zero_()
+            b.bufs[k].chi2.zero_()
+        b.run()
+        torch.cuda.synchronize()
+        _check(b, refs[ro], f"knobs {kn}")
+    before = b.knobs()
+    for bad in (dict(tile_rows=24), dict(radix_order=2), dict(rows_per_block=0), dict(team=129)):
+        with pytest.raises(sf.SfftError) as e:
+            b.set_knobs(**bad)
+        assert e.value.status == sf.SFFT_ERR_INVALID_ARG
+    assert b.knobs() == before
     b.close()
 
 

@@ -36,13 +36,13 @@ def _sigma_sky(D, r):
     return 1.4826 * float(np.median(np.abs(Dm - np.median(Dm))))
 
 
-def _run_gpu(p, compute="fp64", peds=(0.0, 0.0), refine=2):
+def _run_gpu(p, compute="fp64", peds=(0.0, 0.0), refine=2, radix_order=0):
     torch = _torch()
     sf = _sf()
     H, W = p.R.shape
     dt = "float32" if p.R.dtype == np.float32 else "float64"
     d = sf.Differencer(W, H, p.L, p.DK, p.DB, image_dtype=dt, compute=compute,
-                       ref_pedestal=peds[0], sci_pedestal=peds[1])
+                       ref_pedestal=peds[0], sci_pedestal=peds[1], radix_order=radix_order)
     R = torch.from_numpy(p.R).cuda()
     S = torch.from_numpy(p.S).cuda()
     d.run(R, S, max_refine=refine)
@@ -97,6 +97,28 @@ def test_small_shapes(W, H, L, DK, DB, dtype):
                         psf="moffat", fwhm=3.5, fwhm_end=5.0, flux=(1e2, 1e6), dtype=dtype)
     _say(f"shape {W}x{H} L={L} DK={DK} DB={DB} {np.dtype(dtype).name}")
     _compare(p, _run_gpu(p))
+
+
+@pytest.mark.parametrize("W,H,L,DK,DB,dtype", [
+    (2048, 64, 7, 2, 2, np.float32),      # CCD width: stages 4, 8, 8, 8
+    (1500, 40, 3, 1, 1, np.float32),      # 2^2 3 5^3: stages 5, 5, 5, 3, 4
+    (96, 80, 5, 1, 1, np.float64),        # stages 3, 4, 8
+    (160, 120, 7, 2, 2, np.float32),      # stages 5, 4, 8
+])
+def test_reversed_radix_order(W, H, L, DK, DB, dtype):
+    """Row FFTs with their stages in reversed order (sfft_set_radix_order 1):
+    the same oracle bounds as the default order, and G within rounding of
+    the default order's G."""
+    p = synth.make_pair(W, H, L, DK, DB, seed=2000 + W + H + L, nstars=max(8, W * H // 2000),
+                        psf="moffat", fwhm=3.5, fwhm_end=5.0, flux=(1e2, 1e6), dtype=dtype)
+    _say(f"reversed radix order: {W}x{H} L={L} DK={DK} DB={DB} {np.dtype(dtype).name}")
+    g1 = _run_gpu(p, radix_order=1)
+    assert g1["d"].handle is not None
+    _compare(p, g1)
+    g0 = _run_gpu(p)
+    dg = np.max(np.abs(g1["G"] - g0["G"])) / np.max(np.abs(g0["G"]))
+    _say(f"  G order 1 vs order 0: {dg:.1e} of max")
+    assert dg <= 1e-13
 
 
 def test_pedestals_fp64():
