@@ -330,13 +330,61 @@ constexpr int col_spec_stride() {
   return (2 * NK + 1) * 136 + ((4 - (((2 * NK + 1) * 136) % 16)) + 16) % 16;
 }
 
+// FP64 spectra: the staged rows go from global memory straight into LDS
+// (16-byte elements, one per lane; each wave's 64 elements of one base are
+// contiguous), with no registers in between, issued as soon as the previous
+// block's rows have been read, so the loads overlap the rest of the block.
+// The compiler keeps such a load in flight across other LDS accesses only
+// when it can tell them apart, so this form keeps every LDS array static.
+// (FP32 elements are 8 bytes, a size the direct loads do not have: the FP32
+// form stages through registers.)
+template <typename T>
+constexpr bool col_direct() { return sizeof(T) == 8; }
+
 template <typename T, int NK>
 constexpr size_t col_pass_shmem() {
-  // spectra, twiddles, staged rows, then the row weight table:
-  // [window (U, V)][power 0..DK][row] of T
+  // dynamic LDS of the register-staged form: spectra, twiddles, staged
+  // rows, then the row weight table: [window (U, V)][power 0..DK][row] of T
+  if constexpr (col_direct<T>()) return 0;
   return sizeof(cx<T>) * ((size_t)kColsPerWG * col_spec_stride<NK>() + kTP +
                           (size_t)BaseCount<NK>::value * kTP * kColsPerWG) +
          sizeof(T) * 2 * (BaseCount<NK>::value - 1) * kTP;
+}
+
+// LDS arrays of the column pass: static for the direct-staged form, carved
+// from the dynamic allocation otherwise
+template <typename T, int NK>
+__device__ __forceinline__ void col_lds(cx<T>*& spec, cx<T>*& tw, cx<T>*& raw, T*& wtab) {
+  constexpr int NBASE = BaseCount<NK>::value;
+  constexpr int CS = col_spec_stride<NK>();
+  if constexpr (col_direct<T>()) {
+    __shared__ __align__(16) cx<T> s_spec[kColsPerWG * CS];
+    __shared__ __align__(16) cx<T> s_tw[kTP];
+    __shared__ __align__(16) cx<T> s_raw[NBASE * kTP * kColsPerWG];
+    __shared__ __align__(16) T s_wtab[2 * (NBASE - 1) * kTP];
+    spec = s_spec; tw = s_tw; raw = s_raw; wtab = s_wtab;
+  } else {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    spec = reinterpret_cast<cx<T>*>(smem_raw);
+    tw = spec + kColsPerWG * CS;
+    raw = tw + kTP;
+    wtab = reinterpret_cast<T*>(raw + NBASE * kTP * kColsPerWG);
+  }
+}
+
+__device__ __forceinline__ void wait_vm_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }   // vmcnt(0)
+
+// Workgroup barrier for the LDS data that ds instructions wrote: the wave
+// waits for its own LDS accesses (lgkmcnt(0)), not for its direct global ->
+// LDS loads, which stay in flight across it (a memory fence would wait for
+// them, as they write LDS; their data is waited for explicitly before a full
+// barrier). The signal fences keep the compiler from moving memory accesses
+// across the barrier.
+__device__ __forceinline__ void col_lds_barrier() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vmcnt and expcnt not waited
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
 template <typename T, int NK>
@@ -347,12 +395,13 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const VB vb) {
   constexpr int NBASE = BaseCount<NK>::value;
   constexpr int SPAD = 136;
   constexpr int CS = col_spec_stride<NK>();
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<T>* spec = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* tw = spec + kColsPerWG * CS;
-  cx<T>* raw = tw + kTP;                     // staged rows: [base][m][column]
+  constexpr bool DIRECT = col_direct<T>();
+  cx<T>* spec;
+  cx<T>* tw;
+  cx<T>* raw;                                // staged rows: [base][m][column]
+  T* wtab;
+  col_lds<T, NK>(spec, tw, raw, wtab);
   constexpr int NPOW = NBASE - 1;            // powers yt^0 .. yt^DK
-  T* wtab = reinterpret_cast<T*>(raw + NBASE * kTP * kColsPerWG);
   const cx<T>* twg = static_cast<const cx<T>*>(a.tw128);
   const int tid = threadIdx.x;
   if (tid < kTP) tw[tid] = twg[tid];
@@ -382,21 +431,44 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const VB vb) {
   };
 
   // staged rows: element (base u, window row m = tid >> 2, column c = tid & 3)
+  // at raw[(u * kTP + m) * kColsPerWG + c] = raw[u * kTP * kColsPerWG + tid]
   const int fm = tid >> 2, fc = tid & 3;
-  cx<T> pre[NBASE];
+  cx<T> pre[DIRECT ? 1 : NBASE];
   auto fetch = [&](int yb) {
     const int o = (fm < kTP - h) ? fm : fm - kTP;
     int y = yb + o;
     y = (y < 0) ? y + H : ((y >= H) ? y - H : y);
     const int kx = kx0 + fc;
+    if constexpr (DIRECT) {
+      // lane l of the wave writes LDS at the wave's base + 16 l; lanes past
+      // the last column load nothing and keep their zeros
+      if (kx < kxend) {
+        const cx<T>* src = F + (int64_t)y * a.pitchK + kx;
+        cx<T>* dst = raw + (tid & ~63);
 #pragma unroll
-    for (int u = 0; u < NBASE; ++u)
-      pre[u] = (kx < kxend) ? F[(int64_t)u * a.planeK + (int64_t)y * a.pitchK + kx] : cx<T>{(T)0, (T)0};
+        for (int u = 0; u < NBASE; ++u)
+          __builtin_amdgcn_global_load_lds(static_cast<const void*>(src + (int64_t)u * a.planeK),
+                                           (__attribute__((address_space(3))) void*)(dst + u * kTP * kColsPerWG),
+                                           16, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < NBASE; ++u)
+        pre[u] = (kx < kxend) ? F[(int64_t)u * a.planeK + (int64_t)y * a.pitchK + kx] : cx<T>{(T)0, (T)0};
+    }
   };
   auto commit = [&]() {
+    if constexpr (!DIRECT) {
 #pragma unroll
-    for (int u = 0; u < NBASE; ++u) raw[(u * kTP + fm) * kColsPerWG + fc] = pre[u];
+      for (int u = 0; u < NBASE; ++u) raw[(u * kTP + fm) * kColsPerWG + fc] = pre[u];
+    }
   };
+  if constexpr (DIRECT) {
+    if (kx0 + fc >= kxend) {
+#pragma unroll
+      for (int u = 0; u < NBASE; ++u) raw[u * kTP * kColsPerWG + tid] = cx<T>{(T)0, (T)0};
+    }
+  }
 
   // weight of window row m for the block starting at yb: yt(y)^b inside the
   // window (kernel side: the T rows of the block; science side: the block
@@ -425,6 +497,7 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const VB vb) {
   fetch(0);
   commit();
   fill_weights(0);
+  if constexpr (DIRECT) wait_vm_all();
   __syncthreads();
 
   for (int yb = 0; yb < H; yb += a.T) {
@@ -453,8 +526,13 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const VB vb) {
       for (int r = 0; r < 16; ++r) dst[pad16(16 * j + r)] = v[r];
     }
     const bool more = yb + a.T < H;
-    if (more) fetch(yb + a.T);             // in flight during stage 2 and the products
+    if constexpr (!DIRECT) {
+      if (more) fetch(yb + a.T);           // in flight during stage 2
+    }
     __syncthreads();
+    if constexpr (DIRECT) {
+      if (more) fetch(yb + a.T);           // raw is read: in flight during stage 2 and the products
+    }
     // ---- stage 2: radix-8, Ns = 16 (twiddle exp(-2 pi i r j / 128)).
     // As the last Stockham stage it reads and writes the same 8 slots
     // (j + 16 r), so each butterfly is updated in place.
@@ -476,7 +554,8 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const VB vb) {
 #pragma unroll
         for (int r = 0; r < 8; ++r) p[pad16(j + 16 * r)] = v[r];
       }
-      __syncthreads();
+      if constexpr (DIRECT) col_lds_barrier();   // the next rows stay in flight
+      else __syncthreads();
     }
     // ---- products: thread (column, k_y)
     {
@@ -499,6 +578,7 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const VB vb) {
       commit();
       fill_weights(yb + a.T);
     }
+    if constexpr (DIRECT) wait_vm_all();
     __syncthreads();
   }
 
@@ -1190,9 +1270,7 @@ hipError_t prepare_kernel_attributes() {
     set_row_attrs<double, float, true>(set);
     set_row_attrs<float, double, true>(set);
     set_row_attrs<float, float, true>(set);
-    set(reinterpret_cast<const void*>(&k_col_pass<double, 1>));
-    set(reinterpret_cast<const void*>(&k_col_pass<double, 3>));
-    set(reinterpret_cast<const void*>(&k_col_pass<double, 6>));
+    // (the FP64 column pass has only static LDS, see col_direct)
     set(reinterpret_cast<const void*>(&k_col_pass<float, 1>));
     set(reinterpret_cast<const void*>(&k_col_pass<float, 3>));
     set(reinterpret_cast<const void*>(&k_col_pass<float, 6>));
