@@ -107,7 +107,13 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
   constexpr int NT = TX * TY / P;
   constexpr int RW = TX + 2 * r, RH = TY + 2 * r;
   constexpr int NQ = P + 2 * r;
-  __shared__ double Rt[RH][RW + 1];
+  // LDS tile with each run of 8 columns skewed by one slot (column lx at
+  // lx + lx / 8) and a row pitch of 8 mod 16 doubles: the threads of a wave
+  // read their windows (8 pixels apart, 8 rows) from distinct banks
+  constexpr int RWP = ((RW - 1 + (RW - 1) / 8 + 1 + 7) / 16) * 16 + 8;
+  __shared__ double Rt[RH][RWP];
+  auto col = [](int lx) { return lx + (lx >> 3); };
+  static_assert(P == 8, "the skewed window offsets assume 8 pixels per thread");
   __shared__ double red[NT / 64];
   const int tid = threadIdx.x;
   const int W = a.W, H = a.H;
@@ -122,7 +128,7 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
     const TIO* Rb = static_cast<const TIO*>(a.R) + (int64_t)(y0 - r) * a.ld + (x0 - r);
     for (int i = tid; i < RH * RW; i += NT) {
       const int ly = i / RW, lx = i - (i / RW) * RW;
-      Rt[ly][lx] = (double)Rb[(int64_t)ly * a.ld + lx] - a.cR;
+      Rt[ly][col(lx)] = (double)Rb[(int64_t)ly * a.ld + lx] - a.cR;
     }
   } else {
     for (int i = tid; i < RH * RW; i += NT) {
@@ -134,7 +140,7 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
       xx = (xx < 0) ? xx + W : xx;
       xx = (xx >= W) ? xx - W : xx;
       xx = (xx >= W) ? xx - W : xx;
-      Rt[ly][lx] = (double)static_cast<const TIO*>(a.R)[(int64_t)yy * a.ld + xx] - a.cR;
+      Rt[ly][col(lx)] = (double)static_cast<const TIO*>(a.R)[(int64_t)yy * a.ld + xx] - a.cR;
     }
   }
   __syncthreads();
@@ -170,7 +176,7 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
     const double yt = OUTPIX ? (double)y * a.sy - 1.0 : (double)uy * a.sy - 1.0;
     double win[NQ];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) win[q] = Rt[lr][P * tx + q];
+    for (int q = 0; q < NQ; ++q) win[q] = Rt[lr][9 * tx + q + (q >> 3)];   // col(8 tx + q)
 #pragma unroll
     for (int dxi = 0; dxi < L; ++dxi) {
       const int tap = dyi * L + dxi;
@@ -269,7 +275,7 @@ __device__ __forceinline__ void subtract_body(const SubArgs& a, const VB vb) {
           double k2v = 0.0;
 #pragma unroll
           for (int e = 2 * DK; e >= 0; --e) k2v = fma(k2v, xt, kk[e]);
-          const double rv = Rt[te_y + r][P * te_x + p + r] + a.cR;
+          const double rv = Rt[te_y + r][9 * te_x + (p + r) + ((p + r) >> 3)] + a.cR;   // col(8 te_x + p + r)
           const double var = fmax(sv, 1.0) + k2v * fmax(rv, 1.0);
           // 1 / var: hardware estimate and two Newton steps (var >= 1)
           double iv = __builtin_amdgcn_rcp(var);
