@@ -13,9 +13,9 @@
 // consecutive k values are one 16-byte load of one pixel; a block's 1x1
 // projection shortcut is appended to the same k range (one accumulator), an
 // identity shortcut is added in the epilogue. FP32 accumulation; bias,
-// shortcut, ReLU and the rounding to bf16 in the epilogue. Each wave computes
-// 64 output pixels x all output channels, so a weight load serves four
-// matrix-core tiles and an activation load COUT / 16 of them.
+// shortcut, ReLU and the rounding to bf16 in the epilogue. The network runs
+// as three fused stages (stem and block 1, block 2, block 3), one stamp copy
+// per workgroup with the activations of the stage in LDS.
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -104,184 +104,6 @@ __global__ __launch_bounds__(256) void k_rb_input(const float* stamps, int n, un
 }
 
 // ---------------------------------------------------------------------------
-// implicit-GEMM convolution
-// ---------------------------------------------------------------------------
-
-constexpr int kRbThreads = 256;
-constexpr int kRbMT = 4;                   // 16-pixel row tiles per wave
-constexpr int kRbPix = 64 * kRbMT;         // output pixels per workgroup (4 waves x 64)
-
-// an output pixel's copy index and coordinates (or img = -1 past the end)
-struct RbPix {
-  int img, oy, ox;
-};
-
-__device__ __forceinline__ RbPix rb_pix(const RbConvArgs& a, int P) {
-  if (P >= a.npix) return RbPix{-1, 0, 0};
-  const int hw = a.Ho * a.Wo;
-  const int img = P / hw, rem = P - img * hw;
-  const int oy = rem / a.Wo;
-  return RbPix{img, oy, rem - oy * a.Wo};
-}
-
-// 8 bf16 of k-chunk lane group g for output pixel q: the 3x3 part from x,
-// the projection part from x2, zeros past either (and for padding taps)
-__device__ __forceinline__ uint4 rb_load_a(const RbConvArgs& a, const RbPix& q, int k0) {
-  const uint4 zero = {0u, 0u, 0u, 0u};
-  if (q.img < 0) return zero;
-  if (k0 < 9 * a.cinp) {
-    const int tap = k0 / a.cinp, c0 = k0 - tap * a.cinp;
-    const int ky = tap / 3, kx = tap - ky * 3;
-    const int iy = q.oy * a.stride + ky - 1, ix = q.ox * a.stride + kx - 1;
-    if (iy < 0 || iy >= a.H || ix < 0 || ix >= a.W) return zero;
-    return *reinterpret_cast<const uint4*>(a.x + (((int64_t)q.img * a.H + iy) * a.W + ix) * a.cinp + c0);
-  }
-  const int c0 = k0 - 9 * a.cinp;
-  if (!a.x2 || c0 >= a.cinp2) return zero;
-  const int iy = q.oy * a.stride2, ix = q.ox * a.stride2;
-  return *reinterpret_cast<const uint4*>(a.x2 + (((int64_t)q.img * a.H2 + iy) * a.W2 + ix) * a.cinp2 + c0);
-}
-
-// The weights of a 32-wide k chunk (COUT x 32 bf16) are staged in LDS once
-// per workgroup (double-buffered, one barrier per chunk) and read by the
-// four waves; rows padded to 40 bf16 against bank conflicts.
-constexpr int kRbBPitch = 40;
-constexpr size_t kRbMaxTileBytes = 48 * 1024;   // staged input rows (two workgroups per CU)
-
-// Staged inputs (TILED): for a stride-1 layer whose copies hold a whole
-// number of workgroups (Ho Wo a multiple of kRbPix, kRbPix a multiple of Wo),
-// a workgroup's kRbPix output pixels are R = kRbPix / Wo whole rows oy0 ..
-// oy0 + R - 1 of one copy; the 3x3 taps read input rows oy0 - 1 .. oy0 + R
-// and columns -1 .. W (zero outside the image), which are copied into LDS
-// once (channel pitch cinp + 8: 16 bytes of padding per pixel against bank
-// conflicts) instead of being gathered from memory once per tap. The
-// operands, and so the products and their order, are the same.
-inline size_t rb_tile_bytes(int W, int Wo, int cinp) {
-  return sizeof(unsigned short) * (size_t)(kRbPix / Wo + 2) * (size_t)(W + 2) * (size_t)(cinp + 8);
-}
-
-template <int COUT, bool TILED>
-__global__ __launch_bounds__(kRbThreads, 2) void k_rb_conv(RbConvArgs a) {
-  constexpr int NT = COUT / 16;
-  constexpr int BV = COUT * 4;                         // 16-byte pieces of one chunk of weights
-  constexpr int BPT = (BV + kRbThreads - 1) / kRbThreads;
-  __shared__ __align__(16) unsigned short Bs[2][COUT * kRbBPitch];
-  extern __shared__ __align__(16) unsigned short Xs[];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int l16 = lane & 15, g = lane >> 4;
-  const int base = blockIdx.x * kRbPix + wave * 64;
-  floatx4_rb acc[kRbMT][NT];
-#pragma unroll
-  for (int m = 0; m < kRbMT; ++m)
-#pragma unroll
-    for (int t = 0; t < NT; ++t) acc[m][t] = floatx4_rb{0.f, 0.f, 0.f, 0.f};
-  const int nkc = a.KP / 32;
-  RbPix px[kRbMT];
-#pragma unroll
-  for (int m = 0; m < kRbMT; ++m) px[m] = rb_pix(a, base + 16 * m + l16);
-  int t_oy0 = 0, tw = 0, cpt = 0;
-  if constexpr (TILED) {
-    const int pix0 = blockIdx.x * kRbPix;
-    const int hw = a.Ho * a.Wo;
-    const int img = pix0 / hw;
-    t_oy0 = (pix0 - img * hw) / a.Wo;
-    tw = a.W + 2;
-    cpt = a.cinp + 8;
-    const int cv8 = a.cinp / 8;
-    const int n16 = (kRbPix / a.Wo + 2) * tw * cv8;    // 16-byte pieces of the tile
-    for (int i = tid; i < n16; i += kRbThreads) {
-      const int pix = i / cv8, cv = i - pix * cv8;
-      const int ty = pix / tw, tx = pix - ty * tw;
-      const int iy = t_oy0 - 1 + ty, ix = tx - 1;
-      uint4 v = {0u, 0u, 0u, 0u};
-      if (iy >= 0 && iy < a.H && ix >= 0 && ix < a.W)
-        v = *reinterpret_cast<const uint4*>(a.x + (((int64_t)img * a.H + iy) * a.W + ix) * a.cinp + 8 * cv);
-      *reinterpret_cast<uint4*>(&Xs[pix * cpt + 8 * cv]) = v;
-    }
-    __syncthreads();
-  }
-  uint4 A[kRbMT], An[kRbMT], Bg[BPT];
-  auto load_a = [&](int kc, uint4 (&As)[kRbMT]) {
-    const int k0 = kc * 32 + 8 * g;
-    if constexpr (TILED) {
-      if (k0 < 9 * a.cinp) {
-        const int tap = k0 / a.cinp, c0 = k0 - tap * a.cinp;
-        const int ky = tap / 3, kx = tap - ky * 3;
-#pragma unroll
-        for (int m = 0; m < kRbMT; ++m) {
-          const RbPix& q = px[m];
-          As[m] = q.img < 0 ? uint4{0u, 0u, 0u, 0u}
-                            : *reinterpret_cast<const uint4*>(&Xs[((q.oy - t_oy0 + ky) * tw + q.ox + kx) * cpt + c0]);
-        }
-        return;
-      }
-    }
-#pragma unroll
-    for (int m = 0; m < kRbMT; ++m) As[m] = rb_load_a(a, px[m], k0);
-  };
-  // piece i of a chunk: output channel i / 4, k offset 8 (i % 4)
-  auto load_b = [&](int kc) {
-#pragma unroll
-    for (int u = 0; u < BPT; ++u) {
-      const int i = tid + u * kRbThreads;
-      if (i < BV)
-        Bg[u] = *reinterpret_cast<const uint4*>(a.w + (int64_t)(i >> 2) * a.KP + kc * 32 + 8 * (i & 3));
-    }
-  };
-  auto store_b = [&](int buf) {
-#pragma unroll
-    for (int u = 0; u < BPT; ++u) {
-      const int i = tid + u * kRbThreads;
-      if (i < BV) *reinterpret_cast<uint4*>(&Bs[buf][(i >> 2) * kRbBPitch + 8 * (i & 3)]) = Bg[u];
-    }
-  };
-  load_a(0, A);
-  load_b(0);
-  store_b(0);
-  __syncthreads();
-  for (int kc = 0; kc < nkc; ++kc) {
-    const int buf = kc & 1;
-    // the next chunk's global loads are in flight during this chunk's products
-    if (kc + 1 < nkc) {
-      load_a(kc + 1, An);
-      load_b(kc + 1);
-    }
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const bf16x8_rb bv =
-          __builtin_bit_cast(bf16x8_rb, *reinterpret_cast<const uint4*>(&Bs[buf][(16 * t + l16) * kRbBPitch + 8 * g]));
-#pragma unroll
-      for (int m = 0; m < kRbMT; ++m)
-        acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_rb, A[m]), bv, acc[m][t],
-                                                            0, 0, 0);
-    }
-    if (kc + 1 < nkc) {
-      store_b(buf ^ 1);
-#pragma unroll
-      for (int m = 0; m < kRbMT; ++m) A[m] = An[m];
-    }
-    __syncthreads();
-  }
-  // epilogue: lane (g, l16), element q -> pixel 16 m + 4 g + q, channel 16 t + l16
-#pragma unroll
-  for (int m = 0; m < kRbMT; ++m)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int P = base + 16 * m + 4 * g + q;
-      if (P >= a.npix) continue;
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const int co = 16 * t + l16;
-        float v = acc[m][t][q] + a.bias[co];
-        if (a.res) v += bf16_to_f32(a.res[(int64_t)P * COUT + co]);
-        v = fmaxf(v, 0.0f);
-        a.y[(int64_t)P * COUT + co] = f32_to_bf16_rne(v);
-      }
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Stage 1 fused (stem, block-1 conv a, block-1 conv b + identity shortcut):
 // the three layers on 32 x 32 maps keep their activations in LDS, one copy
 // per workgroup, and only the block's output goes to memory. Layer by layer,
@@ -293,9 +115,10 @@ __global__ __launch_bounds__(kRbThreads, 2) void k_rb_conv(RbConvArgs a) {
 // four 16-byte channel groups of pixel p stored in the order
 // cg ^ ((p >> 2) & 3): 16 consecutive pixels of one channel group then fall
 // on 16 different 16-byte bank groups. The input map holds 8 channels per
-// pixel (16 bytes, no swizzle). Products, their order (k chunks in order,
-// one v_mfma_f32_16x16x32_bf16 per chunk and output tile) and the epilogue
-// are those of k_rb_conv, so the output is the same bit for bit.
+// pixel (16 bytes, no swizzle). Every output is the sum of its k chunks in
+// order, one v_mfma_f32_16x16x32_bf16 per chunk and output tile, then the
+// epilogue (bias, shortcut, ReLU, rounding to bf16) in FP32: the rounding
+// points the FP64 oracle reproduces.
 // ---------------------------------------------------------------------------
 
 constexpr int kRbFusedThreads = 512;   // fused stages: 8 waves, two per SIMD
@@ -436,7 +259,7 @@ __global__ __launch_bounds__(kRbFusedThreads, 1) void k_rb_stage1(RbStage1Args a
 // zero border, 128 bytes per pixel, channel group cg of pixel p stored at
 // cg ^ ((p >> 1) & 7)); conv b's output goes to memory. Wave w computes
 // the output channels 32 (w & 1) .. + 31 of half the pixels, with that
-// half's weights in registers. Same products and order as k_rb_conv.
+// half's weights in registers. Same products and order as the other stages.
 // ---------------------------------------------------------------------------
 
 constexpr int kRbMap16Side = 18;
@@ -562,6 +385,127 @@ __global__ __launch_bounds__(kRbFusedThreads, 1) void k_rb_stage2(RbStage2Args a
   rb_stage2_gemm<true, 9>(M32, nullptr, M64, nullptr, a.w[0], a.bias[0], a.KP[0]);
   __syncthreads();
   rb_stage2_gemm<false, 19>(M32, M64, nullptr, a.y + (int64_t)c * 16 * 16 * 64, a.w[1], a.bias[1], a.KP[1]);
+}
+
+// ---------------------------------------------------------------------------
+// Stage 3: block 3 (conv a: 3 x 3 stride 2, 64 -> 128; conv b: 3 x 3, 128 ->
+// 128 plus the 1 x 1 stride-2 projection of the block input) for one stamp
+// copy per workgroup: the block input (18 x 18 x 64, zero border) and the
+// conv a output (10 x 10 x 128, zero border) stay in LDS, and the block
+// output goes to global memory for the head. Wave w owns output channels
+// 16 w .. 16 w + 15 for all 64 output pixels (four matrix-core tiles), with
+// its k-chunks of weights in registers.
+// ---------------------------------------------------------------------------
+
+constexpr int kRbMap8Side = 10;
+constexpr size_t kRbMap8Bytes = (size_t)kRbMap8Side * kRbMap8Side * 256;   // 128 channels of bf16
+constexpr size_t kRbStage3Lds = kRbMap16Bytes + kRbMap8Bytes;
+
+// 128-channel map: 16 groups of 8 channels (16 bytes) per pixel; the group
+// slot is cg ^ ((x + 8 (y & 1)) mod 16), so the 16 pixels that a
+// quarter-wave reads (two rows of 8) take distinct banks
+__device__ __forceinline__ int rb_map8_off(int y, int x, int cg) {
+  return (y * kRbMap8Side + x) * 256 + ((cg ^ ((x + 8 * (y & 1)) & 15)) << 4);
+}
+
+// one GEMM of stage 3: 64 output pixels (8 x 8) x 128 channels.
+// CONV_A: input the 18 x 18 block-input map (stride 2); else the 10 x 10
+// map (stride 1) plus the projection chunk from the block-input map.
+template <bool CONV_A, int NKC>
+__device__ __forceinline__ void rb_stage3_gemm(const unsigned char* in64, const unsigned char* in128,
+                                               unsigned char* out128, unsigned short* gout,
+                                               const unsigned short* w, const float* bias, int KP) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, g = lane >> 4;
+  const int co = 16 * wave + l16;           // weight row of this lane, output channel of its column
+  const float bias1 = bias[co];
+  uint4 Bw[NKC];
+#pragma unroll
+  for (int kc = 0; kc < NKC; ++kc)
+    Bw[kc] = *reinterpret_cast<const uint4*>(w + (int64_t)co * KP + kc * 32 + 8 * g);
+  floatx4_rb acc[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) acc[m] = floatx4_rb{0.f, 0.f, 0.f, 0.f};
+  auto load_a = [&](int kc, uint4 (&A)[4]) {
+    const int k0 = kc * 32 + 8 * g;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int P = 16 * m + l16;                              // output pixel, row-major 8 x 8
+      const int oy = P >> 3, ox = P & 7;
+      if (CONV_A) {                                          // 3 x 3, stride 2, 64 input channels
+        const int tap = k0 >> 6, c0 = k0 & 63;
+        const int ky = tap / 3, kx = tap - ky * 3;
+        const int p = (2 * oy + ky) * kRbMap16Side + 2 * ox + kx;
+        A[m] = *reinterpret_cast<const uint4*>(in64 + rb_map16_off(p, c0 >> 3));
+      } else if (k0 < 9 * 128) {                             // 3 x 3, stride 1, 128 channels
+        const int tap = k0 >> 7, c0 = k0 & 127;
+        const int ky = tap / 3, kx = tap - ky * 3;
+        A[m] = *reinterpret_cast<const uint4*>(in128 + rb_map8_off(oy + ky, ox + kx, c0 >> 3));
+      } else {                                               // projection: block input at (2 oy, 2 ox)
+        const int c0 = k0 - 9 * 128;
+        const int p = (2 * oy + 1) * kRbMap16Side + 2 * ox + 1;
+        A[m] = *reinterpret_cast<const uint4*>(in64 + rb_map16_off(p, c0 >> 3));
+      }
+    }
+  };
+  uint4 A[4], An[4];
+  load_a(0, A);
+#pragma unroll
+  for (int kc = 0; kc < NKC; ++kc) {
+    if (kc + 1 < NKC) load_a(kc + 1, An);
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_rb, A[m]),
+                                                       __builtin_bit_cast(bf16x8_rb, Bw[kc]), acc[m], 0, 0, 0);
+    if (kc + 1 < NKC) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) A[m] = An[m];
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int P = 16 * m + 4 * g + q;
+      const float v = fmaxf(acc[m][q] + bias1, 0.0f);
+      const unsigned short b = f32_to_bf16_rne(v);
+      if (CONV_A)
+        *reinterpret_cast<unsigned short*>(out128 + rb_map8_off((P >> 3) + 1, (P & 7) + 1, co >> 3) +
+                                           2 * (co & 7)) = b;
+      else
+        gout[(int64_t)P * 128 + co] = b;
+    }
+}
+
+struct RbStage3Args {
+  const unsigned short* x;                // [copies][16][16][64]: block 2 output
+  const unsigned short* w[2];             // packed weights of block 3 conv a, conv b (+ projection)
+  const float* bias[2];
+  int KP[2];
+  unsigned short* y;                      // [copies][8][8][128]: block 3 output
+  int copies;
+};
+
+__global__ __launch_bounds__(kRbFusedThreads, 1) void k_rb_stage3(RbStage3Args a) {
+  extern __shared__ __align__(16) unsigned char rbm[];
+  unsigned char* M64 = rbm;                      // block input, 18 x 18 x 64
+  unsigned char* M128 = rbm + kRbMap16Bytes;     // conv a output, 10 x 10 x 128
+  const int c = blockIdx.x;
+  if (c >= a.copies) return;
+  const int tid = threadIdx.x;
+  const uint4 zero = {0u, 0u, 0u, 0u};
+  for (int i = tid; i < (int)(kRbStage3Lds / 16); i += kRbFusedThreads) reinterpret_cast<uint4*>(rbm)[i] = zero;
+  __syncthreads();
+  const uint4* src = reinterpret_cast<const uint4*>(a.x + (int64_t)c * 16 * 16 * 64);
+  for (int i = tid; i < 16 * 16 * 8; i += kRbFusedThreads) {
+    const int P = i >> 3, cg = i & 7;
+    const int p = ((P >> 4) + 1) * kRbMap16Side + (P & 15) + 1;
+    *reinterpret_cast<uint4*>(M64 + rb_map16_off(p, cg)) = src[i];
+  }
+  __syncthreads();
+  rb_stage3_gemm<true, 18>(M64, nullptr, M128, nullptr, a.w[0], a.bias[0], a.KP[0]);
+  __syncthreads();
+  rb_stage3_gemm<false, 38>(M64, M128, nullptr, a.y + (int64_t)c * 8 * 8 * 128, a.w[1], a.bias[1], a.KP[1]);
 }
 
 // ---------------------------------------------------------------------------
@@ -714,35 +658,18 @@ hipError_t launch_rb_score(const float* params, const float* stamps, int n, floa
     hipLaunchKernelGGL(k_rb_stage2, dim3((unsigned)copies), dim3(kRbFusedThreads), kRbStage2Lds, st, sa);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  for (int l = 5; l < kRbGemms; ++l) {
-    const RbGemm& gm = kRbGemm[l];
-    const Step& s = steps[l];
-    RbConvArgs ca{};
-    ca.x = s.x; ca.x2 = s.x2; ca.res = s.res; ca.y = s.y;
-    ca.w = reinterpret_cast<const unsigned short*>(ws + p.w[l]);
-    ca.bias = reinterpret_cast<const float*>(ws + p.bias[l]);
-    ca.H = ca.W = s.H;
-    ca.cinp = gm.cinp;
-    ca.stride = gm.stride;
-    ca.Ho = ca.Wo = s.H / gm.stride;
-    ca.H2 = ca.W2 = s.H2;
-    ca.cinp2 = gm.cipp;
-    ca.stride2 = 2;
-    ca.KP = p.KP[l];
-    ca.npix = (int)(copies * ca.Ho * ca.Wo);
-    const dim3 grid((unsigned)((ca.npix + kRbPix - 1) / kRbPix));
-    const bool tiled = ca.stride == 1 && (ca.Ho * ca.Wo) % kRbPix == 0 && kRbPix % ca.Wo == 0 &&
-                       rb_tile_bytes(ca.W, ca.Wo, ca.cinp) <= kRbMaxTileBytes;
-    const size_t tb = tiled ? rb_tile_bytes(ca.W, ca.Wo, ca.cinp) : 0;
-    switch (gm.co * 2 + (tiled ? 1 : 0)) {
-      case 64: hipLaunchKernelGGL((k_rb_conv<32, false>), grid, dim3(kRbThreads), 0, st, ca); break;
-      case 65: hipLaunchKernelGGL((k_rb_conv<32, true>), grid, dim3(kRbThreads), tb, st, ca); break;
-      case 128: hipLaunchKernelGGL((k_rb_conv<64, false>), grid, dim3(kRbThreads), 0, st, ca); break;
-      case 129: hipLaunchKernelGGL((k_rb_conv<64, true>), grid, dim3(kRbThreads), tb, st, ca); break;
-      case 256: hipLaunchKernelGGL((k_rb_conv<128, false>), grid, dim3(kRbThreads), 0, st, ca); break;
-      case 257: hipLaunchKernelGGL((k_rb_conv<128, true>), grid, dim3(kRbThreads), tb, st, ca); break;
-      default: return hipErrorInvalidValue;
+  {
+    RbStage3Args sa{};
+    sa.x = steps[5].x;
+    for (int l = 0; l < 2; ++l) {
+      sa.w[l] = reinterpret_cast<const unsigned short*>(ws + p.w[5 + l]);
+      sa.bias[l] = reinterpret_cast<const float*>(ws + p.bias[5 + l]);
+      sa.KP[l] = p.KP[5 + l];
     }
+    sa.y = steps[6].y;
+    sa.copies = (int)copies;
+    if (sa.KP[0] != 576 || sa.KP[1] != 1216) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_rb_stage3, dim3((unsigned)copies), dim3(kRbFusedThreads), kRbStage3Lds, st, sa);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_rb_head, dim3(n), dim3(128), 0, st, B2, params + kRbFc1W, params + kRbFc1B,
@@ -754,8 +681,11 @@ hipError_t prepare_rb_attributes() {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rb_stage1),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRbStage1Lds);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rb_stage2),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRbStage2Lds);
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rb_stage2), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)kRbStage2Lds);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rb_stage3),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRbStage3Lds);
 }
 
 hipError_t launch_rb_extract(const RbExtractArgs& a, bool f32, hipStream_t st) {

@@ -59,18 +59,6 @@ struct RbPlan {
 };
 RbPlan rb_plan(int n);
 
-struct RbConvArgs {
-  const unsigned short* x;      // input, bf16 NHWC [copies][H][W][cinp]
-  const unsigned short* x2;     // projection input [copies][H2][W2][cinp2] or null
-  const unsigned short* res;    // identity shortcut [copies][Ho][Wo][COUT] or null
-  unsigned short* y;            // output [copies][Ho][Wo][COUT]
-  const unsigned short* w;      // packed weights [COUT][KP]
-  const float* bias;            // [COUT] (projection bias included)
-  int H, W, cinp, stride, Ho, Wo;
-  int H2, W2, cinp2, stride2;
-  int KP, npix;
-};
-
 struct RbExtractArgs {
   const void* img[3];           // science, template, difference
   int64_t ld;
