@@ -266,27 +266,25 @@ __global__ __launch_bounds__(kStThreads, 1) void k_stamp_gram(StampArgs a) {
   const int s_begin = (int)((int64_t)group * a.nst / a.ngroups);
   const int s_end = (int)((int64_t)(group + 1) * a.nst / a.ngroups);
   for (int s = s_begin; s < s_end; ++s) {
-    // ---- copy the used planes of this stamp into LDS (4 x 16 B per thread in flight)
+    // ---- copy the used planes of this stamp into LDS: direct global -> LDS
+    // loads (16 bytes per lane; lane l of a wave writes its wave's LDS base
+    // + 16 l), all of the stamp's issued before one wait, so the copy costs
+    // about one memory latency instead of one per 16 KB
     const unsigned* src = a.planes + (int64_t)s * g.stamp_dw;
     for (int c = 0; c < ncopy; ++c) {
       const int p = copy_plane[c];
       const uint4* s4 = reinterpret_cast<const uint4*>(src + stamp_plane_offset(g, p));
       uint4* d4 = reinterpret_cast<uint4*>(lds + slot_off[p]);
       const int n4 = (p < g.nK ? g.halo_dw : g.comp_dw) / 4;
-      for (int i = tid; i < n4; i += 4 * kStThreads) {
-        uint4 v[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int idx = i + k * kStThreads;
-          if (idx < n4) v[k] = s4[idx];
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int idx = i + k * kStThreads;
-          if (idx < n4) d4[idx] = v[k];
-        }
+      for (int i0 = 0; i0 < n4; i0 += kStThreads) {
+        const int idx = i0 + tid;
+        if (idx < n4)
+          __builtin_amdgcn_global_load_lds(static_cast<const void*>(s4 + idx),
+                                           (__attribute__((address_space(3))) void*)(d4 + i0 + (tid & ~63)), 16, 0,
+                                           0);
       }
     }
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's copies have landed
     __syncthreads();
 
     // ---- Gram over this stamp's 32-pixel chunks (every 4th chunk per wave)
