@@ -70,40 +70,6 @@ __global__ __launch_bounds__(256) void k_rb_pack(RbPackArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// input: stamps FP32 [n][3][32][32] -> bf16 NHWC [4n][32][32][8], copy
-// 4k + rot = the stamp rotated by rot quarter turns (numpy's rot90 on the
-// two image axes: out[i][j] = s[j][31 - i] for one turn)
-// ---------------------------------------------------------------------------
-
-__global__ __launch_bounds__(256) void k_rb_input(const float* stamps, int n, unsigned short* x0) {
-  const int64_t total = (int64_t)n * 4 * kRbStamp * kRbStamp;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= total) return;
-  const int j = (int)(i % kRbStamp);
-  const int r = (int)((i / kRbStamp) % kRbStamp);
-  const int copy = (int)(i / (kRbStamp * kRbStamp));
-  const int k = copy >> 2, rot = copy & 3;
-  constexpr int e = kRbStamp - 1;
-  int sy, sx;
-  switch (rot) {
-    case 0: sy = r; sx = j; break;
-    case 1: sy = j; sx = e - r; break;
-    case 2: sy = e - r; sx = e - j; break;
-    default: sy = e - j; sx = r; break;
-  }
-  unsigned short v[8];
-#pragma unroll
-  for (int c = 0; c < 8; ++c)
-    v[c] = c < 3 ? f32_to_bf16_rne(stamps[(((int64_t)k * 3 + c) * kRbStamp + sy) * kRbStamp + sx]) : 0;
-  uint4 pk;
-  pk.x = v[0] | ((unsigned)v[1] << 16);
-  pk.y = v[2] | ((unsigned)v[3] << 16);
-  pk.z = v[4] | ((unsigned)v[5] << 16);
-  pk.w = v[6] | ((unsigned)v[7] << 16);
-  reinterpret_cast<uint4*>(x0)[i] = pk;
-}
-
-// ---------------------------------------------------------------------------
 // Stage 1 fused (stem, block-1 conv a, block-1 conv b + identity shortcut):
 // the three layers on 32 x 32 maps keep their activations in LDS, one copy
 // per workgroup, and only the block's output goes to memory. Layer by layer,
@@ -208,7 +174,7 @@ __device__ __forceinline__ void rb_stage1_layer(const unsigned char* in, unsigne
 }
 
 struct RbStage1Args {
-  const unsigned short* x0;               // [copies][32][32][8]
+  const float* stamps;                    // [n][3][32][32]: science, template, difference
   const unsigned short* w[3];             // packed weights of stem, b1a, b1b
   const float* bias[3];
   int KP[3];
@@ -227,10 +193,32 @@ __global__ __launch_bounds__(kRbFusedThreads, 1) void k_rb_stage1(RbStage1Args a
   // zero both maps (borders included), then the copy's input into M1
   for (int i = tid; i < (int)(kRbStage1Lds / 16); i += kRbFusedThreads) reinterpret_cast<uint4*>(rbm)[i] = zero;
   __syncthreads();
-  const uint4* src = reinterpret_cast<const uint4*>(a.x0 + (int64_t)c * 32 * 32 * 8);
-  for (int i = tid; i < 32 * 32; i += kRbFusedThreads) {
-    const int p = ((i >> 5) + 1) * kRbMapSide + (i & 31) + 1;
-    reinterpret_cast<uint4*>(M1)[p] = src[i];
+  // the copy's input: copy c is candidate c / 4 turned by (c mod 4) quarter
+  // turns (numpy's rot90 on the two image axes: one turn maps
+  // out[i][j] = s[j][31 - i]), so that a quarter turn of a stamp only
+  // permutes its copies; pixel (r, j) of the copy holds the three stamp
+  // channels in bf16 and five zero channels (16 bytes)
+  {
+    const int rot = c & 3;
+    const float* stp = a.stamps + (int64_t)(c >> 2) * 3 * kRbStamp * kRbStamp;
+    constexpr int e = kRbStamp - 1;
+    for (int i = tid; i < kRbStamp * kRbStamp; i += kRbFusedThreads) {
+      const int r = i / kRbStamp, j = i % kRbStamp;
+      int sy, sx;
+      switch (rot) {
+        case 0: sy = r; sx = j; break;
+        case 1: sy = j; sx = e - r; break;
+        case 2: sy = e - r; sx = e - j; break;
+        default: sy = e - j; sx = r; break;
+      }
+      const int o = sy * kRbStamp + sx;
+      uint4 pk;
+      pk.x = f32_to_bf16_rne(stp[o]) | ((unsigned)f32_to_bf16_rne(stp[kRbStamp * kRbStamp + o]) << 16);
+      pk.y = f32_to_bf16_rne(stp[2 * kRbStamp * kRbStamp + o]);
+      pk.z = 0u;
+      pk.w = 0u;
+      reinterpret_cast<uint4*>(M1)[(r + 1) * kRbMapSide + j + 1] = pk;
+    }
   }
   __syncthreads();
   rb_stage1_layer<true, false>(M1, M0, a.w[0], a.bias[0], a.KP[0]);
@@ -582,8 +570,8 @@ RbPlan rb_plan(int n) {
     p.w[l] = take((size_t)gm.co * kp * 2);
     p.bias[l] = take((size_t)gm.co * 4);
   }
-  p.x0 = take((size_t)copies * 32 * 32 * 8 * 2);
-  for (int b = 0; b < 3; ++b) p.act[b] = take((size_t)copies * 32 * 32 * 32 * 2);
+  p.act[0] = take((size_t)copies * 32 * 32 * 32 * 2);   // stage 1 output, then stage 3 output
+  p.act[1] = take((size_t)copies * 16 * 16 * 64 * 2);   // stage 2 output
   p.total = o;
   return p;
 }
@@ -609,36 +597,18 @@ hipError_t launch_rb_score(const float* params, const float* stamps, int n, floa
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   const int64_t copies = 4 * (int64_t)n;
-  unsigned short* x0 = reinterpret_cast<unsigned short*>(ws + p.x0);
-  {
-    const int64_t total = copies * 32 * 32;
-    hipLaunchKernelGGL(k_rb_input, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, stamps, n, x0);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
-  unsigned short* B0 = reinterpret_cast<unsigned short*>(ws + p.act[0]);
-  unsigned short* B1 = reinterpret_cast<unsigned short*>(ws + p.act[1]);
-  unsigned short* B2 = reinterpret_cast<unsigned short*>(ws + p.act[2]);
-  // (input, H, projection input, H2, residual, output) per GEMM
-  struct Step { const unsigned short* x; int H; const unsigned short* x2; int H2; const unsigned short* res;
-                unsigned short* y; };
-  const Step steps[kRbGemms] = {
-      {x0, 32, nullptr, 0, nullptr, B0},       // stem            -> a1 (B0)
-      {B0, 32, nullptr, 0, nullptr, B1},       // block 1 conv a  -> t  (B1)
-      {B1, 32, nullptr, 0, B0, B2},            // block 1 conv b + a1 -> a2 (B2)
-      {B2, 32, nullptr, 0, nullptr, B0},       // block 2 conv a  -> t16 (B0)
-      {B0, 16, B2, 32, nullptr, B1},           // block 2 conv b + proj(a2) -> a3 (B1)
-      {B1, 16, nullptr, 0, nullptr, B0},       // block 3 conv a  -> t8 (B0)
-      {B0, 8, B1, 16, nullptr, B2},            // block 3 conv b + proj(a3) -> a4 (B2)
-  };
+  unsigned short* A1 = reinterpret_cast<unsigned short*>(ws + p.act[0]);   // stage 1 out: [copies][32][32][32]
+  unsigned short* A2 = reinterpret_cast<unsigned short*>(ws + p.act[1]);   // stage 2 out: [copies][16][16][64]
+  unsigned short* A3 = A1;                                                 // stage 3 out: [copies][8][8][128]
   {
     RbStage1Args sa{};
-    sa.x0 = x0;
+    sa.stamps = stamps;
     for (int l = 0; l < 3; ++l) {
       sa.w[l] = reinterpret_cast<const unsigned short*>(ws + p.w[l]);
       sa.bias[l] = reinterpret_cast<const float*>(ws + p.bias[l]);
       sa.KP[l] = p.KP[l];
     }
-    sa.y = steps[2].y;
+    sa.y = A1;
     sa.copies = (int)copies;
     if (sa.KP[0] != 96 || sa.KP[1] != 288 || sa.KP[2] != 288) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_rb_stage1, dim3((unsigned)copies), dim3(kRbFusedThreads), kRbStage1Lds, st, sa);
@@ -646,13 +616,13 @@ hipError_t launch_rb_score(const float* params, const float* stamps, int n, floa
   }
   {
     RbStage2Args sa{};
-    sa.x = steps[3].x;
+    sa.x = A1;
     for (int l = 0; l < 2; ++l) {
       sa.w[l] = reinterpret_cast<const unsigned short*>(ws + p.w[3 + l]);
       sa.bias[l] = reinterpret_cast<const float*>(ws + p.bias[3 + l]);
       sa.KP[l] = p.KP[3 + l];
     }
-    sa.y = steps[4].y;
+    sa.y = A2;
     sa.copies = (int)copies;
     if (sa.KP[0] != 288 || sa.KP[1] != 608) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_rb_stage2, dim3((unsigned)copies), dim3(kRbFusedThreads), kRbStage2Lds, st, sa);
@@ -660,19 +630,19 @@ hipError_t launch_rb_score(const float* params, const float* stamps, int n, floa
   }
   {
     RbStage3Args sa{};
-    sa.x = steps[5].x;
+    sa.x = A2;
     for (int l = 0; l < 2; ++l) {
       sa.w[l] = reinterpret_cast<const unsigned short*>(ws + p.w[5 + l]);
       sa.bias[l] = reinterpret_cast<const float*>(ws + p.bias[5 + l]);
       sa.KP[l] = p.KP[5 + l];
     }
-    sa.y = steps[6].y;
+    sa.y = A3;
     sa.copies = (int)copies;
     if (sa.KP[0] != 576 || sa.KP[1] != 1216) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_rb_stage3, dim3((unsigned)copies), dim3(kRbFusedThreads), kRbStage3Lds, st, sa);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_rb_head, dim3(n), dim3(128), 0, st, B2, params + kRbFc1W, params + kRbFc1B,
+  hipLaunchKernelGGL(k_rb_head, dim3(n), dim3(128), 0, st, A3, params + kRbFc1W, params + kRbFc1B,
                      params + kRbFc2W, params + kRbFc2B, n, logits, probs);
   return hipGetLastError();
 }

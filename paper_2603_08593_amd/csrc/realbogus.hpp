@@ -54,7 +54,7 @@ struct RbPlan {
   int n;
   int KP[kRbGemms];             // padded k length of each GEMM (multiple of 32)
   size_t w[kRbGemms], bias[kRbGemms];
-  size_t x0, act[3];            // input copies (bf16 NHWC, 8 channels) and three activation buffers
+  size_t act[2];                // stage outputs (bf16 NHWC): stage 1 then stage 3, stage 2
   size_t total;
 };
 RbPlan rb_plan(int n);
