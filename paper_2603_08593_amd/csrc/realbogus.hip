@@ -401,7 +401,7 @@ __device__ __forceinline__ int rb_map8_off(int y, int x, int cg) {
 // map (stride 1) plus the projection chunk from the block-input map.
 template <bool CONV_A, int NKC>
 __device__ __forceinline__ void rb_stage3_gemm(const unsigned char* in64, const unsigned char* in128,
-                                               unsigned char* out128, unsigned short* gout,
+                                               unsigned char* out128, unsigned short* yout,
                                                const unsigned short* w, const float* bias, int KP) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, g = lane >> 4;
@@ -450,6 +450,9 @@ __device__ __forceinline__ void rb_stage3_gemm(const unsigned char* in64, const 
       for (int m = 0; m < 4; ++m) A[m] = An[m];
     }
   }
+  // conv b: its output overwrites LDS that the other waves may still read,
+  // so it waits for them
+  if (!CONV_A) __syncthreads();
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -461,7 +464,7 @@ __device__ __forceinline__ void rb_stage3_gemm(const unsigned char* in64, const 
         *reinterpret_cast<unsigned short*>(out128 + rb_map8_off((P >> 3) + 1, (P & 7) + 1, co >> 3) +
                                            2 * (co & 7)) = b;
       else
-        gout[(int64_t)P * 128 + co] = b;
+        yout[P * 128 + co] = b;
     }
 }
 
@@ -470,7 +473,7 @@ struct RbStage3Args {
   const unsigned short* w[2];             // packed weights of block 3 conv a, conv b (+ projection)
   const float* bias[2];
   int KP[2];
-  unsigned short* y;                      // [copies][8][8][128]: block 3 output
+  float* feat;                            // [copies][128]: per-channel sums of the block output
   int copies;
 };
 
@@ -493,29 +496,35 @@ __global__ __launch_bounds__(kRbFusedThreads, 1) void k_rb_stage3(RbStage3Args a
   __syncthreads();
   rb_stage3_gemm<true, 18>(M64, nullptr, M128, nullptr, a.w[0], a.bias[0], a.KP[0]);
   __syncthreads();
-  rb_stage3_gemm<false, 38>(M64, M128, nullptr, a.y + (int64_t)c * 8 * 8 * 128, a.w[1], a.bias[1], a.KP[1]);
+  // the block output (bf16, [pixel][channel]) goes over the block-input map
+  // (free once conv b is done); then each channel's 64 pixels are summed in
+  // pixel order in FP32, the first step of the head's average pooling
+  unsigned short* Y = reinterpret_cast<unsigned short*>(M64);
+  rb_stage3_gemm<false, 38>(M64, M128, nullptr, Y, a.w[1], a.bias[1], a.KP[1]);
+  __syncthreads();
+  if (tid < 128) {
+    float sr = 0.0f;
+    for (int px = 0; px < 64; ++px) sr += bf16_to_f32(Y[px * 128 + tid]);
+    a.feat[(int64_t)c * 128 + tid] = sr;
+  }
 }
 
 // ---------------------------------------------------------------------------
-// head: mean over the 8 x 8 pixels and the 4 copies, linear 128 -> 64, ReLU,
-// linear 64 -> 1, sigmoid. One workgroup of 128 threads per candidate, FP32,
-// fixed order.
+// head: mean over the 8 x 8 pixels (from the per-copy channel sums of
+// stage 3) and the 4 copies, linear 128 -> 64, ReLU, linear 64 -> 1, sigmoid.
+// One workgroup of 128 threads per candidate, FP32, fixed order.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(128) void k_rb_head(const unsigned short* a4, const float* w1, const float* b1,
+__global__ __launch_bounds__(128) void k_rb_head(const float* feat, const float* w1, const float* b1,
                                                  const float* w2, const float* b2, int n, float* logits,
                                                  float* probs) {
   __shared__ float f[128];
   __shared__ float hbuf[64];
   const int k = blockIdx.x, c = threadIdx.x;
   if (k >= n) return;
+  // feat: each copy's per-channel sum over its 8 x 8 pixels (stage 3)
   float s = 0.0f;
-  for (int rot = 0; rot < 4; ++rot) {
-    const unsigned short* p = a4 + ((int64_t)(4 * k + rot) * 64) * 128 + c;
-    float sr = 0.0f;
-    for (int px = 0; px < 64; ++px) sr += bf16_to_f32(p[(int64_t)px * 128]);
-    s += sr * (1.0f / 64.0f);
-  }
+  for (int rot = 0; rot < 4; ++rot) s += feat[(int64_t)(4 * k + rot) * 128 + c] * (1.0f / 64.0f);
   f[c] = s * 0.25f;
   __syncthreads();
   if (c < 64) {
@@ -570,7 +579,7 @@ RbPlan rb_plan(int n) {
     p.w[l] = take((size_t)gm.co * kp * 2);
     p.bias[l] = take((size_t)gm.co * 4);
   }
-  p.act[0] = take((size_t)copies * 32 * 32 * 32 * 2);   // stage 1 output, then stage 3 output
+  p.act[0] = take((size_t)copies * 32 * 32 * 32 * 2);   // stage 1 output, then stage 3's channel sums
   p.act[1] = take((size_t)copies * 16 * 16 * 64 * 2);   // stage 2 output
   p.total = o;
   return p;
@@ -599,7 +608,7 @@ hipError_t launch_rb_score(const float* params, const float* stamps, int n, floa
   const int64_t copies = 4 * (int64_t)n;
   unsigned short* A1 = reinterpret_cast<unsigned short*>(ws + p.act[0]);   // stage 1 out: [copies][32][32][32]
   unsigned short* A2 = reinterpret_cast<unsigned short*>(ws + p.act[1]);   // stage 2 out: [copies][16][16][64]
-  unsigned short* A3 = A1;                                                 // stage 3 out: [copies][8][8][128]
+  float* feat = reinterpret_cast<float*>(ws + p.act[0]);                    // stage 3 out: [copies][128]
   {
     RbStage1Args sa{};
     sa.stamps = stamps;
@@ -636,13 +645,13 @@ hipError_t launch_rb_score(const float* params, const float* stamps, int n, floa
       sa.bias[l] = reinterpret_cast<const float*>(ws + p.bias[5 + l]);
       sa.KP[l] = p.KP[5 + l];
     }
-    sa.y = A3;
+    sa.feat = feat;
     sa.copies = (int)copies;
     if (sa.KP[0] != 576 || sa.KP[1] != 1216) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_rb_stage3, dim3((unsigned)copies), dim3(kRbFusedThreads), kRbStage3Lds, st, sa);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_rb_head, dim3(n), dim3(128), 0, st, A3, params + kRbFc1W, params + kRbFc1B,
+  hipLaunchKernelGGL(k_rb_head, dim3(n), dim3(128), 0, st, feat, params + kRbFc1W, params + kRbFc1B,
                      params + kRbFc2W, params + kRbFc2B, n, logits, probs);
   return hipGetLastError();
 }
