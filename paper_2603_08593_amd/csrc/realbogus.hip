@@ -14,8 +14,8 @@
 // projection shortcut is appended to the same k range (one accumulator), an
 // identity shortcut is added in the epilogue. FP32 accumulation; bias,
 // shortcut, ReLU and the rounding to bf16 in the epilogue. The network runs
-// as three fused stages (stem and block 1, block 2, block 3), one stamp copy
-// per workgroup with the activations of the stage in LDS.
+// as two fused kernels (stem and blocks 1 and 2; block 3 and the first
+// pooling step), one stamp copy per workgroup with the activations in LDS.
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -70,12 +70,13 @@ __global__ __launch_bounds__(256) void k_rb_pack(RbPackArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Stage 1 fused (stem, block-1 conv a, block-1 conv b + identity shortcut):
-// the three layers on 32 x 32 maps keep their activations in LDS, one copy
-// per workgroup, and only the block's output goes to memory. Layer by layer,
-// every 32-channel map of 4096 candidates is ~1 GB written and read back
-// (each layer then bound by memory traffic); here the copy's input (16 KB)
-// and output (64 KB) are the only traffic besides the L2-resident weights.
+// Stage 1 fused (stem, block-1 conv a, block-1 conv b + identity shortcut,
+// then block 2 below): the layers keep their activations in LDS, one copy
+// per workgroup, and only block 2's output goes to memory. Layer by layer,
+// every 32-channel 32 x 32 map of 4096 candidates is ~1 GB written and read
+// back (each layer then bound by memory traffic); here the stamp (12 KB)
+// and block 2's output (32 KB) are the only traffic besides the
+// L2-resident weights.
 // Maps are 34 x 34 pixels (a zero border of one pixel, so the 3 x 3 taps
 // need no bounds checks), bf16, 32 channels per pixel (64 bytes) with the
 // four 16-byte channel groups of pixel p stored in the order
@@ -173,92 +174,26 @@ __device__ __forceinline__ void rb_stage1_layer(const unsigned char* in, unsigne
   }
 }
 
-struct RbStage1Args {
-  const float* stamps;                    // [n][3][32][32]: science, template, difference
-  const unsigned short* w[3];             // packed weights of stem, b1a, b1b
-  const float* bias[3];
-  int KP[3];
-  unsigned short* y;                      // [copies][32][32][32]: block 1 output
-  int copies;
-};
-
-__global__ __launch_bounds__(kRbFusedThreads, 1) void k_rb_stage1(RbStage1Args a) {
-  extern __shared__ __align__(16) unsigned char rbm[];
-  unsigned char* M0 = rbm;                       // stem output, then block output (in place)
-  unsigned char* M1 = rbm + kRbMapBytes;         // input (8 channels), then conv a output
-  const int c = blockIdx.x;
-  if (c >= a.copies) return;
-  const int tid = threadIdx.x;
-  const uint4 zero = {0u, 0u, 0u, 0u};
-  // zero both maps (borders included), then the copy's input into M1
-  for (int i = tid; i < (int)(kRbStage1Lds / 16); i += kRbFusedThreads) reinterpret_cast<uint4*>(rbm)[i] = zero;
-  __syncthreads();
-  // the copy's input: copy c is candidate c / 4 turned by (c mod 4) quarter
-  // turns (numpy's rot90 on the two image axes: one turn maps
-  // out[i][j] = s[j][31 - i]), so that a quarter turn of a stamp only
-  // permutes its copies; pixel (r, j) of the copy holds the three stamp
-  // channels in bf16 and five zero channels (16 bytes)
-  {
-    const int rot = c & 3;
-    const float* stp = a.stamps + (int64_t)(c >> 2) * 3 * kRbStamp * kRbStamp;
-    constexpr int e = kRbStamp - 1;
-    for (int i = tid; i < kRbStamp * kRbStamp; i += kRbFusedThreads) {
-      const int r = i / kRbStamp, j = i % kRbStamp;
-      int sy, sx;
-      switch (rot) {
-        case 0: sy = r; sx = j; break;
-        case 1: sy = j; sx = e - r; break;
-        case 2: sy = e - r; sx = e - j; break;
-        default: sy = e - j; sx = r; break;
-      }
-      const int o = sy * kRbStamp + sx;
-      uint4 pk;
-      pk.x = f32_to_bf16_rne(stp[o]) | ((unsigned)f32_to_bf16_rne(stp[kRbStamp * kRbStamp + o]) << 16);
-      pk.y = f32_to_bf16_rne(stp[2 * kRbStamp * kRbStamp + o]);
-      pk.z = 0u;
-      pk.w = 0u;
-      reinterpret_cast<uint4*>(M1)[(r + 1) * kRbMapSide + j + 1] = pk;
-    }
-  }
-  __syncthreads();
-  rb_stage1_layer<true, false>(M1, M0, a.w[0], a.bias[0], a.KP[0]);
-  __syncthreads();
-  // M1 becomes a 32-channel map: zero it again (its border is read by conv b)
-  for (int i = tid; i < (int)(kRbMapBytes / 16); i += kRbFusedThreads) reinterpret_cast<uint4*>(M1)[i] = zero;
-  __syncthreads();
-  rb_stage1_layer<false, false>(M0, M1, a.w[1], a.bias[1], a.KP[1]);
-  __syncthreads();
-  rb_stage1_layer<false, true>(M1, M0, a.w[2], a.bias[2], a.KP[2]);
-  __syncthreads();
-  // the block output, un-swizzled, 16 bytes per store
-  uint4* dst = reinterpret_cast<uint4*>(a.y + (int64_t)c * 32 * 32 * 32);
-  for (int i = tid; i < 32 * 32 * 4; i += kRbFusedThreads) {
-    const int P = i >> 2, cg = i & 3;
-    const int p = ((P >> 5) + 1) * kRbMapSide + (P & 31) + 1;
-    dst[i] = *reinterpret_cast<const uint4*>(M0 + rb_map_off(p, cg));
-  }
-}
-
 // ---------------------------------------------------------------------------
-// Stage 2 fused (block 2: stride-2 conv a 32 -> 64, conv b 64 -> 64 with the
-// 1x1 stride-2 projection of the block input appended to its k range), one
-// copy per workgroup. LDS: the block input as a 34 x 34 map of 32 channels
-// (as in stage 1) and conv a's output as an 18 x 18 map of 64 channels (a
-// zero border, 128 bytes per pixel, channel group cg of pixel p stored at
-// cg ^ ((p >> 1) & 7)); conv b's output goes to memory. Wave w computes
-// the output channels 32 (w & 1) .. + 31 of half the pixels, with that
-// half's weights in registers. Same products and order as the other stages.
+// Block 2 (stride-2 conv a 32 -> 64, conv b 64 -> 64 with the 1x1 stride-2
+// projection of the block input appended to its k range), run by the first
+// fused kernel after block 1 on the same copy. LDS: the block input is block
+// 1's output map (34 x 34 x 32), conv a's output an 18 x 18 map of 64
+// channels over the other map's space (a zero border, 128 bytes per pixel,
+// channel group cg of pixel p stored at cg ^ ((p >> 1) & 7)); conv b's
+// output goes to memory. Wave w computes the output channels 32 (w & 1) ..
+// + 31 of half the pixels, with that half's weights in registers.
 // ---------------------------------------------------------------------------
 
 constexpr int kRbMap16Side = 18;
 constexpr size_t kRbMap16Bytes = (size_t)kRbMap16Side * kRbMap16Side * 128;   // 64 channels of bf16
-constexpr size_t kRbStage2Lds = kRbMapBytes + kRbMap16Bytes;
+static_assert(kRbMap16Bytes <= kRbMapBytes, "block 2's conv a map fits over block 1's second map");
 
 __device__ __forceinline__ int rb_map16_off(int p, int cg) {    // bytes, 64-channel map
   return p * 128 + ((cg ^ ((p >> 1) & 7)) << 4);
 }
 
-// one GEMM of stage 2: 256 output pixels (16 x 16) x 64 channels; wave w:
+// one GEMM of block 2: 256 output pixels (16 x 16) x 64 channels; wave w:
 // channel half h = w & 1, pixels 64 (w >> 1) .. + 63.
 // CONV_A: input the 34 x 34 block-input map (stride 2); else the 18 x 18 map
 // (stride 1) plus the projection chunk from the block-input map.
@@ -344,35 +279,70 @@ __device__ __forceinline__ void rb_stage2_gemm(const unsigned char* in32, const 
   }
 }
 
-struct RbStage2Args {
-  const unsigned short* x;                // [copies][32][32][32]: block 1 output
-  const unsigned short* w[2];             // packed weights of block 2 conv a, conv b (+ projection)
-  const float* bias[2];
-  int KP[2];
+struct RbStage1Args {
+  const float* stamps;                    // [n][3][32][32]: science, template, difference
+  const unsigned short* w[5];             // packed weights of stem, b1a, b1b, b2a, b2b (+ projection)
+  const float* bias[5];
+  int KP[5];
   unsigned short* y;                      // [copies][16][16][64]: block 2 output
   int copies;
 };
 
-__global__ __launch_bounds__(kRbFusedThreads, 1) void k_rb_stage2(RbStage2Args a) {
+__global__ __launch_bounds__(kRbFusedThreads, 1) void k_rb_stage1(RbStage1Args a) {
   extern __shared__ __align__(16) unsigned char rbm[];
-  unsigned char* M32 = rbm;                      // block input, 34 x 34 x 32
-  unsigned char* M64 = rbm + kRbMapBytes;        // conv a output, 18 x 18 x 64
+  unsigned char* M0 = rbm;                       // stem output, then block output (in place)
+  unsigned char* M1 = rbm + kRbMapBytes;         // input (8 channels), then conv a output
   const int c = blockIdx.x;
   if (c >= a.copies) return;
   const int tid = threadIdx.x;
   const uint4 zero = {0u, 0u, 0u, 0u};
-  for (int i = tid; i < (int)(kRbStage2Lds / 16); i += kRbFusedThreads) reinterpret_cast<uint4*>(rbm)[i] = zero;
+  // zero both maps (borders included), then the copy's input into M1
+  for (int i = tid; i < (int)(kRbStage1Lds / 16); i += kRbFusedThreads) reinterpret_cast<uint4*>(rbm)[i] = zero;
   __syncthreads();
-  const uint4* src = reinterpret_cast<const uint4*>(a.x + (int64_t)c * 32 * 32 * 32);
-  for (int i = tid; i < 32 * 32 * 4; i += kRbFusedThreads) {
-    const int P = i >> 2, cg = i & 3;
-    const int p = ((P >> 5) + 1) * kRbMapSide + (P & 31) + 1;
-    *reinterpret_cast<uint4*>(M32 + rb_map_off(p, cg)) = src[i];
+  // the copy's input: copy c is candidate c / 4 turned by (c mod 4) quarter
+  // turns (numpy's rot90 on the two image axes: one turn maps
+  // out[i][j] = s[j][31 - i]), so that a quarter turn of a stamp only
+  // permutes its copies; pixel (r, j) of the copy holds the three stamp
+  // channels in bf16 and five zero channels (16 bytes)
+  {
+    const int rot = c & 3;
+    const float* stp = a.stamps + (int64_t)(c >> 2) * 3 * kRbStamp * kRbStamp;
+    constexpr int e = kRbStamp - 1;
+    for (int i = tid; i < kRbStamp * kRbStamp; i += kRbFusedThreads) {
+      const int r = i / kRbStamp, j = i % kRbStamp;
+      int sy, sx;
+      switch (rot) {
+        case 0: sy = r; sx = j; break;
+        case 1: sy = j; sx = e - r; break;
+        case 2: sy = e - r; sx = e - j; break;
+        default: sy = e - j; sx = r; break;
+      }
+      const int o = sy * kRbStamp + sx;
+      uint4 pk;
+      pk.x = f32_to_bf16_rne(stp[o]) | ((unsigned)f32_to_bf16_rne(stp[kRbStamp * kRbStamp + o]) << 16);
+      pk.y = f32_to_bf16_rne(stp[2 * kRbStamp * kRbStamp + o]);
+      pk.z = 0u;
+      pk.w = 0u;
+      reinterpret_cast<uint4*>(M1)[(r + 1) * kRbMapSide + j + 1] = pk;
+    }
   }
   __syncthreads();
-  rb_stage2_gemm<true, 9>(M32, nullptr, M64, nullptr, a.w[0], a.bias[0], a.KP[0]);
+  rb_stage1_layer<true, false>(M1, M0, a.w[0], a.bias[0], a.KP[0]);
   __syncthreads();
-  rb_stage2_gemm<false, 19>(M32, M64, nullptr, a.y + (int64_t)c * 16 * 16 * 64, a.w[1], a.bias[1], a.KP[1]);
+  // M1 becomes a 32-channel map: zero it again (its border is read by conv b)
+  for (int i = tid; i < (int)(kRbMapBytes / 16); i += kRbFusedThreads) reinterpret_cast<uint4*>(M1)[i] = zero;
+  __syncthreads();
+  rb_stage1_layer<false, false>(M0, M1, a.w[1], a.bias[1], a.KP[1]);
+  __syncthreads();
+  rb_stage1_layer<false, true>(M1, M0, a.w[2], a.bias[2], a.KP[2]);
+  __syncthreads();
+  // block 2 on the same copy: M0 (block 1's output, zero border) is its
+  // input map; conv a's output (18 x 18 x 64, zero border) goes over M1
+  for (int i = tid; i < (int)(kRbMap16Bytes / 16); i += kRbFusedThreads) reinterpret_cast<uint4*>(M1)[i] = zero;
+  __syncthreads();
+  rb_stage2_gemm<true, 9>(M0, nullptr, M1, nullptr, a.w[3], a.bias[3], a.KP[3]);
+  __syncthreads();
+  rb_stage2_gemm<false, 19>(M0, M1, nullptr, a.y + (int64_t)c * 16 * 16 * 64, a.w[4], a.bias[4], a.KP[4]);
 }
 
 // ---------------------------------------------------------------------------
@@ -579,8 +549,8 @@ RbPlan rb_plan(int n) {
     p.w[l] = take((size_t)gm.co * kp * 2);
     p.bias[l] = take((size_t)gm.co * 4);
   }
-  p.act[0] = take((size_t)copies * 32 * 32 * 32 * 2);   // stage 1 output, then stage 3's channel sums
-  p.act[1] = take((size_t)copies * 16 * 16 * 64 * 2);   // stage 2 output
+  p.act[0] = take((size_t)copies * 16 * 16 * 64 * 2);   // block 2 output (bf16)
+  p.act[1] = take((size_t)copies * 128 * 4);            // block 3 channel sums (FP32)
   p.total = o;
   return p;
 }
@@ -606,35 +576,21 @@ hipError_t launch_rb_score(const float* params, const float* stamps, int n, floa
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   const int64_t copies = 4 * (int64_t)n;
-  unsigned short* A1 = reinterpret_cast<unsigned short*>(ws + p.act[0]);   // stage 1 out: [copies][32][32][32]
-  unsigned short* A2 = reinterpret_cast<unsigned short*>(ws + p.act[1]);   // stage 2 out: [copies][16][16][64]
-  float* feat = reinterpret_cast<float*>(ws + p.act[0]);                    // stage 3 out: [copies][128]
+  unsigned short* A2 = reinterpret_cast<unsigned short*>(ws + p.act[0]);   // blocks 1-2 out: [copies][16][16][64]
+  float* feat = reinterpret_cast<float*>(ws + p.act[1]);                    // block 3 out: [copies][128]
   {
     RbStage1Args sa{};
     sa.stamps = stamps;
-    for (int l = 0; l < 3; ++l) {
+    for (int l = 0; l < 5; ++l) {
       sa.w[l] = reinterpret_cast<const unsigned short*>(ws + p.w[l]);
       sa.bias[l] = reinterpret_cast<const float*>(ws + p.bias[l]);
       sa.KP[l] = p.KP[l];
     }
-    sa.y = A1;
-    sa.copies = (int)copies;
-    if (sa.KP[0] != 96 || sa.KP[1] != 288 || sa.KP[2] != 288) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_rb_stage1, dim3((unsigned)copies), dim3(kRbFusedThreads), kRbStage1Lds, st, sa);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
-  {
-    RbStage2Args sa{};
-    sa.x = A1;
-    for (int l = 0; l < 2; ++l) {
-      sa.w[l] = reinterpret_cast<const unsigned short*>(ws + p.w[3 + l]);
-      sa.bias[l] = reinterpret_cast<const float*>(ws + p.bias[3 + l]);
-      sa.KP[l] = p.KP[3 + l];
-    }
     sa.y = A2;
     sa.copies = (int)copies;
-    if (sa.KP[0] != 288 || sa.KP[1] != 608) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_rb_stage2, dim3((unsigned)copies), dim3(kRbFusedThreads), kRbStage2Lds, st, sa);
+    if (sa.KP[0] != 96 || sa.KP[1] != 288 || sa.KP[2] != 288 || sa.KP[3] != 288 || sa.KP[4] != 608)
+      return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_rb_stage1, dim3((unsigned)copies), dim3(kRbFusedThreads), kRbStage1Lds, st, sa);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   {
@@ -659,9 +615,6 @@ hipError_t launch_rb_score(const float* params, const float* stamps, int n, floa
 hipError_t prepare_rb_attributes() {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rb_stage1),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRbStage1Lds);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rb_stage2), hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)kRbStage2Lds);
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rb_stage3),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRbStage3Lds);
