@@ -113,10 +113,19 @@ class GatedDifferencer:
 
     def __init__(self, width, height, L, dk, db, params, std: Standardizer, *, threshold=1.05,
                  precision=SFFT_NET_BF16, image_dtype="float32", n_stamps=N_STAMPS, device="cuda",
-                 refit_background=True, max_pairs=1):
+                 refit_background=True, max_pairs=1, in_flight=1, solve_team=0):
         import torch
         self.torch = torch
-        self.diff = Differencer(width, height, L, dk, db, image_dtype=image_dtype, device=device)
+        if in_flight < 1:
+            raise ValueError("in_flight must be >= 1")
+        self.diff = Differencer(width, height, L, dk, db, image_dtype=image_dtype, device=device,
+                                solve_team=solve_team)
+        # run_batch: pair k of a group is refitted, subtracted (and, if
+        # rejected, fitted in full) in slot k % in_flight, each slot a
+        # Differencer (handle, workspace, result buffers) with its own stream
+        self.slots = [self.diff] + [Differencer(width, height, L, dk, db, image_dtype=image_dtype, device=device,
+                                                solve_team=solve_team) for _ in range(in_flight - 1)]
+        self.slot_streams = [torch.cuda.Stream() for _ in range(in_flight)] if in_flight > 1 else None
         self.max_pairs = int(max_pairs)
         self.net = Surrogate(params, self.diff.N, n_stamps=n_stamps, max_pairs=self.max_pairs,
                              handle=self.diff.handle, device=device)
@@ -160,13 +169,24 @@ class GatedDifferencer:
         d.run(R, S, max_refine=max_refine, stream=stream)
         return False, chi_pred, float(d.buf.chi2.item())
 
+    def close(self):
+        """Release the slots' handles now (the network shares the first)."""
+        for sd in self.slots:
+            sd.close()
+
     def run_batch(self, pairs, max_refine=1, stream=None):
         """Gated differencing of up to max_pairs pairs [(R, S, centers), ...]
         with one network launch for all of them and one host read of their
-        chi2 values; the rejected pairs are then fitted in full. Every pair's
-        difference image goes through the one output buffer (diff.buf.diff),
-        overwritten pair after pair. Returns (accepted, chi2 of the
-        predictions, final chi2) as lists."""
+        chi2 values; the rejected pairs are then fitted in full. Pair k is
+        refitted and subtracted in slot k % in_flight, and the rejected ones
+        are fitted in full in rounds of one per slot; with several slots, each
+        on its own stream, one pair's refit (small, latency-bound kernels)
+        overlaps other pairs' subtracts. Difference images go through the
+        slots' output buffers (slots[j].buf.diff), each overwritten by the
+        slot's next pair. Every pair's chi2 values are those of the
+        single-slot path with the same solve team. Returns (accepted, chi2 of
+        the predictions, final chi2) as lists."""
+        torch = self.torch
         B = len(pairs)
         if B > self.max_pairs:
             raise ValueError(f"{B} pairs > max_pairs = {self.max_pairs}")
@@ -177,16 +197,40 @@ class GatedDifferencer:
                          out=self.pred_all[:B], stream=stream)
         sfft_surrogate_destandardize(d.handle, self.pred_all[:B], self.mean, self.scale, B, d.N,
                                      self.coef_all[:B], stream)
+        nsl = len(self.slots)
+        main = stream if stream is not None else torch.cuda.current_stream()
+        if nsl > 1:
+            for s in self.slot_streams:
+                s.wait_stream(main)        # the predicted coefficients, and the inputs
+
+        def on_slot(k, j):
+            st = self.slot_streams[j] if nsl > 1 else stream
+            if nsl > 1:
+                for t in pairs[k][:2]:
+                    t.record_stream(st)
+            return self.slots[j], st
+
         for k, (R, S, C) in enumerate(pairs):
+            sd, st = on_slot(k, k % nsl)
             if self.refit:
-                d.refit_background(R, S, coef=self.coef_all[k], stream=stream)
-            sfft_subtract(d.handle, d.desc, R, S, self.coef_all[k], d.buf.diff, self.chi2_all[k:k + 1], d.buf.ws,
-                          stream)
+                sd.refit_background(R, S, coef=self.coef_all[k], stream=st)
+            sfft_subtract(sd.handle, sd.desc, R, S, self.coef_all[k], sd.buf.diff, self.chi2_all[k:k + 1],
+                          sd.buf.ws, st)
+        if nsl > 1:
+            for s in self.slot_streams:
+                main.wait_stream(s)
         chi_pred = self.chi2_all[:B].cpu().tolist()     # the judge's decisions need the values on the host
         accepted = [c <= self.threshold for c in chi_pred]
         final = list(chi_pred)
-        for k, (R, S, C) in enumerate(pairs):
-            if not accepted[k]:
-                d.run(R, S, max_refine=max_refine, stream=stream)
-                final[k] = float(d.buf.chi2.item())
+        rejected = [k for k in range(B) if not accepted[k]]
+        for i in range(0, len(rejected), nsl):         # rounds of full fits, one pair per slot
+            group = rejected[i:i + nsl]
+            for j, k in enumerate(group):
+                sd, st = on_slot(k, j)
+                sd.run(pairs[k][0], pairs[k][1], max_refine=max_refine, stream=st)
+            if nsl > 1:
+                for s in self.slot_streams:
+                    main.wait_stream(s)
+            for j, k in enumerate(group):
+                final[k] = float(self.slots[j].buf.chi2.item())
         return accepted, chi_pred, final

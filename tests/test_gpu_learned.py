@@ -126,3 +126,37 @@ def test_gated_fallback_threshold_zero_and_corrupt_weights():
     assert not acc and not np.isfinite(chi_pred) and chi_final == chi_plain
     for o in (plain, g0.diff, g1.diff):
         o.close()
+
+
+def test_gated_batch_pairs_in_flight_match_one_slot():
+    """run_batch with three pairs in flight (slots with their own streams,
+    handles and buffers) gives, pair by pair, the same prediction chi2,
+    decision and final chi2 as one slot with the same solve team. The
+    threshold sits at the median prediction, so some pairs are rejected and
+    their full fits run in rounds over the slots."""
+    import torch
+    import synth.gpu as sg
+    from paper_2603_08593_amd.learned import GatedDifferencer, load_weights
+    params, std, _ = load_weights(WEIGHTS)
+    pairs, k = [], 9200
+    while len(pairs) < 5:
+        pr = sg.make_learned_pair(k)
+        k += 1
+        cen = synth.pick_centers(pr["xs"], pr["ys"], pr["flux"], 2048, 4096, 64, 32, 5)
+        if len(cen) == 64:
+            pairs.append((pr["R"], pr["S"], torch.from_numpy(cen).cuda()))
+    g0 = GatedDifferencer(2048, 4096, 11, 2, 2, params, std, max_pairs=5, solve_team=32)
+    _, pred0, _ = g0.run_batch(pairs)
+    thr = min(sorted(pred0)[2], 1.05)
+    g0.threshold = thr
+    acc1, pred1, fin1 = g0.run_batch(pairs)
+    g3 = GatedDifferencer(2048, 4096, 11, 2, 2, params, std, max_pairs=5, in_flight=3, solve_team=32,
+                          threshold=thr)
+    acc3, pred3, fin3 = g3.run_batch(pairs)
+    torch.cuda.synchronize()
+    print(f"  threshold {thr:.5f}: accepted {acc1}; final chi2 {[round(c, 6) for c in fin1]}", flush=True)
+    assert any(acc1) and not all(acc1)
+    assert acc3 == acc1 and pred3 == pred1 and fin3 == fin1
+    assert max(fin1) <= 1.05
+    g0.close()
+    g3.close()
