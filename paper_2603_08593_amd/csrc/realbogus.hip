@@ -37,6 +37,35 @@ __device__ __forceinline__ float bf16_to_f32(unsigned short h) {
   return __builtin_bit_cast(float, (unsigned)h << 16);
 }
 
+// The convolution GEMMs put the weights in the matrix-core instruction's
+// first operand and the activations in its second, so lane (g, l16) of a
+// 16 x 16 result tile holds output channels 4 g .. 4 g + 3 of pixel l16:
+// four adjacent channels of one pixel, stored as one 8-byte access.
+typedef __bf16 bf16x2_rb __attribute__((ext_vector_type(2)));
+typedef float floatx2_rb __attribute__((ext_vector_type(2)));
+
+// two floats to a pair of bf16 (round to nearest even, the rounding of
+// f32_to_bf16_rne), low half first
+__device__ __forceinline__ unsigned bf16x2_rne(float lo, float hi) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(floatx2_rb{lo, hi}, bf16x2_rb));
+}
+// bias, optional residual (4 bf16 at r), ReLU, packed to 4 bf16
+__device__ __forceinline__ uint2 rb_act4(const floatx4_rb& acc, const float (&b)[4], const uint2* r) {
+  float v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = acc[i] + b[i];
+  if (r) {
+    const uint2 x = *r;
+    v[0] += __builtin_bit_cast(float, x.x << 16);
+    v[1] += __builtin_bit_cast(float, x.x & 0xFFFF0000u);
+    v[2] += __builtin_bit_cast(float, x.y << 16);
+    v[3] += __builtin_bit_cast(float, x.y & 0xFFFF0000u);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = fmaxf(v[i], 0.0f);
+  return uint2{bf16x2_rne(v[0], v[1]), bf16x2_rne(v[2], v[3])};
+}
+
 // ---------------------------------------------------------------------------
 // weights: FP32 [out][in][ky][kx] (+ projection [out][in]) -> bf16 [out][KP]
 // with k = tap * CINP + c for the 3x3 part and 9 CINP + c for the projection
@@ -107,9 +136,13 @@ __device__ __forceinline__ void rb_stage1_layer(const unsigned char* in, unsigne
   const int l16 = lane & 15, g = lane >> 4;
   constexpr int NKC = CIN8 ? 3 : 9;            // k chunks: KP = 96 (stem), 288
   const int cin = CIN8 ? 8 : 32;
-  // the lane's weights of every k chunk and its two biases, held in
-  // registers for the 4 passes
-  const float bias2[2] = {bias[l16], bias[16 + l16]};
+  // the lane's weights of every k chunk and the biases of its result
+  // channels 16 t + 4 g + i, held in registers for the 2 passes
+  float bias4[2][4];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bias4[t][i] = bias[16 * t + 4 * g + i];
   uint4 Bw[NKC][2];
 #pragma unroll
   for (int kc = 0; kc < NKC; ++kc)
@@ -146,31 +179,26 @@ __device__ __forceinline__ void rb_stage1_layer(const unsigned char* in, unsigne
       for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int m = 0; m < 4; ++m)
-          acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_rb, A[m]),
-                                                              __builtin_bit_cast(bf16x8_rb, Bw[kc][t]), acc[m][t],
+          acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_rb, Bw[kc][t]),
+                                                              __builtin_bit_cast(bf16x8_rb, A[m]), acc[m][t],
                                                               0, 0, 0);
       if (kc + 1 < NKC) {
 #pragma unroll
         for (int m = 0; m < 4; ++m) A[m] = An[m];
       }
     }
-    // epilogue: lane (g, l16), element q -> pixel 16 m + 4 g + q, channel 16 t + l16
+    // epilogue: lane (g, l16), element i -> channel 16 t + 4 g + i of pixel 16 m + l16
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+    for (int m = 0; m < 4; ++m) {
+      const int P = 16 * (mt0 + m) + l16;
+      const int p = ((P >> 5) + 1) * kRbMapSide + (P & 31) + 1;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int P = 16 * (mt0 + m) + 4 * g + q;
-        const int p = ((P >> 5) + 1) * kRbMapSide + (P & 31) + 1;
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          const int co = 16 * t + l16;
-          const int off = rb_map_off(p, co >> 3) + 2 * (co & 7);
-          float v = acc[m][t][q] + bias2[t];
-          if (RES) v += bf16_to_f32(*reinterpret_cast<const unsigned short*>(out + off));
-          v = fmaxf(v, 0.0f);
-          *reinterpret_cast<unsigned short*>(out + off) = f32_to_bf16_rne(v);
-        }
+      for (int t = 0; t < 2; ++t) {
+        const int co = 16 * t + 4 * g;
+        uint2* dst = reinterpret_cast<uint2*>(out + rb_map_off(p, co >> 3) + 2 * (co & 7));
+        *dst = rb_act4(acc[m][t], bias4[t], RES ? dst : nullptr);
       }
+    }
   }
 }
 
@@ -204,7 +232,11 @@ __device__ __forceinline__ void rb_stage2_gemm(const unsigned char* in32, const 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, g = lane >> 4;
   const int h = wave & 1;
-  const float bias2[2] = {bias[32 * h + l16], bias[32 * h + 16 + l16]};
+  float bias4[2][4];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bias4[t][i] = bias[32 * h + 16 * t + 4 * g + i];
   uint4 Bw[NKC][2];
 #pragma unroll
   for (int kc = 0; kc < NKC; ++kc)
@@ -250,32 +282,30 @@ __device__ __forceinline__ void rb_stage2_gemm(const unsigned char* in32, const 
       for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int m = 0; m < 4; ++m)
-          acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_rb, A[m]),
-                                                              __builtin_bit_cast(bf16x8_rb, Bw[kc][t]), acc[m][t],
+          acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_rb, Bw[kc][t]),
+                                                              __builtin_bit_cast(bf16x8_rb, A[m]), acc[m][t],
                                                               0, 0, 0);
       if (kc + 1 < NKC) {
 #pragma unroll
         for (int m = 0; m < 4; ++m) A[m] = An[m];
       }
     }
+    // lane (g, l16), element i -> channel 32 h + 16 t + 4 g + i of pixel 16 m + l16
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+    for (int m = 0; m < 4; ++m) {
+      const int P = 16 * (mt0 + m) + l16;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int P = 16 * (mt0 + m) + 4 * g + q;
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          const int co = 32 * h + 16 * t + l16;
-          const float v = fmaxf(acc[m][t][q] + bias2[t], 0.0f);
-          const unsigned short b = f32_to_bf16_rne(v);
-          if (CONV_A) {
-            const int p = ((P >> 4) + 1) * kRbMap16Side + (P & 15) + 1;
-            *reinterpret_cast<unsigned short*>(out64 + rb_map16_off(p, co >> 3) + 2 * (co & 7)) = b;
-          } else {
-            gout[(int64_t)P * 64 + co] = b;
-          }
+      for (int t = 0; t < 2; ++t) {
+        const int co = 32 * h + 16 * t + 4 * g;
+        const uint2 b = rb_act4(acc[m][t], bias4[t], nullptr);
+        if (CONV_A) {
+          const int p = ((P >> 4) + 1) * kRbMap16Side + (P & 15) + 1;
+          *reinterpret_cast<uint2*>(out64 + rb_map16_off(p, co >> 3) + 2 * (co & 7)) = b;
+        } else {
+          *reinterpret_cast<uint2*>(gout + (int64_t)P * 64 + co) = b;
         }
       }
+    }
   }
 }
 
@@ -366,6 +396,12 @@ __device__ __forceinline__ int rb_map8_off(int y, int x, int cg) {
   return (y * kRbMap8Side + x) * 256 + ((cg ^ ((x + 8 * (y & 1)) & 15)) << 4);
 }
 
+// block 3's output in LDS: [pixel][channel] bf16 with a pitch of 136
+// channels (272 bytes, 16 bytes past a multiple of 256), so the 16 pixels
+// that a quarter-wave's 8-byte stores cover start on distinct banks
+constexpr int kRbYPitch = 136;
+static_assert(64 * kRbYPitch * 2 <= (int)kRbMap16Bytes, "block 3's output fits over its input map");
+
 // one GEMM of stage 3: 64 output pixels (8 x 8) x 128 channels.
 // CONV_A: input the 18 x 18 block-input map (stride 2); else the 10 x 10
 // map (stride 1) plus the projection chunk from the block-input map.
@@ -375,8 +411,11 @@ __device__ __forceinline__ void rb_stage3_gemm(const unsigned char* in64, const 
                                                const unsigned short* w, const float* bias, int KP) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, g = lane >> 4;
-  const int co = 16 * wave + l16;           // weight row of this lane, output channel of its column
-  const float bias1 = bias[co];
+  const int co = 16 * wave + l16;           // weight row of this lane
+  const int co4 = 16 * wave + 4 * g;        // its result channels co4 .. co4 + 3
+  float bias4[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) bias4[i] = bias[co4 + i];
   uint4 Bw[NKC];
 #pragma unroll
   for (int kc = 0; kc < NKC; ++kc)
@@ -413,8 +452,8 @@ __device__ __forceinline__ void rb_stage3_gemm(const unsigned char* in64, const 
     if (kc + 1 < NKC) load_a(kc + 1, An);
 #pragma unroll
     for (int m = 0; m < 4; ++m)
-      acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_rb, A[m]),
-                                                       __builtin_bit_cast(bf16x8_rb, Bw[kc]), acc[m], 0, 0, 0);
+      acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_rb, Bw[kc]),
+                                                       __builtin_bit_cast(bf16x8_rb, A[m]), acc[m], 0, 0, 0);
     if (kc + 1 < NKC) {
 #pragma unroll
       for (int m = 0; m < 4; ++m) A[m] = An[m];
@@ -423,19 +462,16 @@ __device__ __forceinline__ void rb_stage3_gemm(const unsigned char* in64, const 
   // conv b: its output overwrites LDS that the other waves may still read,
   // so it waits for them
   if (!CONV_A) __syncthreads();
+  // lane (g, l16), element i -> channel co4 + i of pixel 16 m + l16
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int P = 16 * m + 4 * g + q;
-      const float v = fmaxf(acc[m][q] + bias1, 0.0f);
-      const unsigned short b = f32_to_bf16_rne(v);
-      if (CONV_A)
-        *reinterpret_cast<unsigned short*>(out128 + rb_map8_off((P >> 3) + 1, (P & 7) + 1, co >> 3) +
-                                           2 * (co & 7)) = b;
-      else
-        yout[P * 128 + co] = b;
-    }
+  for (int m = 0; m < 4; ++m) {
+    const int P = 16 * m + l16;
+    const uint2 b = rb_act4(acc[m], bias4, nullptr);
+    if (CONV_A)
+      *reinterpret_cast<uint2*>(out128 + rb_map8_off((P >> 3) + 1, (P & 7) + 1, co4 >> 3) + 2 * (co4 & 7)) = b;
+    else
+      *reinterpret_cast<uint2*>(yout + P * kRbYPitch + co4) = b;
+  }
 }
 
 struct RbStage3Args {
@@ -474,7 +510,7 @@ __global__ __launch_bounds__(kRbFusedThreads, 1) void k_rb_stage3(RbStage3Args a
   __syncthreads();
   if (tid < 128) {
     float sr = 0.0f;
-    for (int px = 0; px < 64; ++px) sr += bf16_to_f32(Y[px * 128 + tid]);
+    for (int px = 0; px < 64; ++px) sr += bf16_to_f32(Y[px * kRbYPitch + tid]);
     a.feat[(int64_t)c * 128 + tid] = sr;
   }
 }
