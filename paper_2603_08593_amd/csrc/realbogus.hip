@@ -107,11 +107,12 @@ __global__ __launch_bounds__(256) void k_rb_pack(RbPackArgs a) {
 // and block 2's output (32 KB) are the only traffic besides the
 // L2-resident weights.
 // Maps are 34 x 34 pixels (a zero border of one pixel, so the 3 x 3 taps
-// need no bounds checks), bf16, 32 channels per pixel (64 bytes) with the
-// four 16-byte channel groups of pixel p stored in the order
-// cg ^ ((p >> 2) & 3): 16 consecutive pixels of one channel group then fall
-// on 16 different 16-byte bank groups. The input map holds 8 channels per
-// pixel (16 bytes, no swizzle). Every output is the sum of its k chunks in
+// need no bounds checks), bf16, 32 channels as four planes of 8-channel
+// groups (16 bytes per pixel in each plane): 16 consecutive pixels of one
+// group are 256 contiguous bytes, on distinct banks, and a tap's pixel
+// offset is a constant added to a per-lane base, which the LDS instruction
+// takes as its immediate offset. The input map holds 8 channels per pixel
+// (plane 0 alone). Every output is the sum of its k chunks in
 // order, one v_mfma_f32_16x16x32_bf16 per chunk and output tile, then the
 // epilogue (bias, shortcut, ReLU, rounding to bf16) in FP32: the rounding
 // points the FP64 oracle reproduces.
@@ -123,8 +124,10 @@ constexpr int kRbMapPix = kRbMapSide * kRbMapSide;
 constexpr size_t kRbMapBytes = (size_t)kRbMapPix * 64;          // 32 channels of bf16
 constexpr size_t kRbStage1Lds = 2 * kRbMapBytes;
 
+constexpr int kRbPlane = kRbMapPix * 16;                        // bytes of one channel group
+
 __device__ __forceinline__ int rb_map_off(int p, int cg) {      // bytes, 32-channel map
-  return p * 64 + ((cg ^ ((p >> 2) & 3)) << 4);
+  return cg * kRbPlane + p * 16;
 }
 
 // one layer: out = relu(conv3x3(in) + bias [+ res]) on the 32 x 32 interior;
