@@ -210,8 +210,8 @@ __device__ __forceinline__ void rb_stage1_layer(const unsigned char* in, unsigne
 // projection of the block input appended to its k range), run by the first
 // fused kernel after block 1 on the same copy. LDS: the block input is block
 // 1's output map (34 x 34 x 32), conv a's output an 18 x 18 map of 64
-// channels over the other map's space (a zero border, 128 bytes per pixel,
-// channel group cg of pixel p stored at cg ^ ((p >> 1) & 7)); conv b's
+// channels over the other map's space (a zero border; eight planes of
+// 8-channel groups, 16 bytes per pixel in each, as block 1's maps); conv b's
 // output goes to memory. Wave w computes the output channels 32 (w & 1) ..
 // + 31 of half the pixels, with that half's weights in registers.
 // ---------------------------------------------------------------------------
@@ -220,8 +220,10 @@ constexpr int kRbMap16Side = 18;
 constexpr size_t kRbMap16Bytes = (size_t)kRbMap16Side * kRbMap16Side * 128;   // 64 channels of bf16
 static_assert(kRbMap16Bytes <= kRbMapBytes, "block 2's conv a map fits over block 1's second map");
 
+constexpr int kRbPlane16 = kRbMap16Side * kRbMap16Side * 16;    // bytes of one channel group
+
 __device__ __forceinline__ int rb_map16_off(int p, int cg) {    // bytes, 64-channel map
-  return p * 128 + ((cg ^ ((p >> 1) & 7)) << 4);
+  return cg * kRbPlane16 + p * 16;
 }
 
 // one GEMM of block 2: 256 output pixels (16 x 16) x 64 channels; wave w:
