@@ -126,6 +126,21 @@ constexpr size_t kRbStage1Lds = 2 * kRbMapBytes;
 
 constexpr int kRbPlane = kRbMapPix * 16;                        // bytes of one channel group
 
+// zero the one-pixel border of np consecutive planes (side x side pixels,
+// 16 bytes each); the layers write every interior pixel of their maps, so
+// only the borders that the 3 x 3 taps read need clearing
+__device__ __forceinline__ void rb_zero_border(unsigned char* base, int np, int side, int plane_bytes) {
+  const int nb = 4 * side - 4;
+  for (int i = threadIdx.x; i < np * nb; i += kRbFusedThreads) {
+    const int pl = i / nb, k = i - pl * nb;
+    int y, x;
+    if (k < side) { y = 0; x = k; }
+    else if (k < 2 * side) { y = side - 1; x = k - side; }
+    else { const int e = k - 2 * side; y = 1 + (e >> 1); x = (e & 1) ? side - 1 : 0; }
+    *reinterpret_cast<uint4*>(base + pl * plane_bytes + (y * side + x) * 16) = uint4{0u, 0u, 0u, 0u};
+  }
+}
+
 __device__ __forceinline__ int rb_map_off(int p, int cg) {      // bytes, 32-channel map
   return cg * kRbPlane + p * 16;
 }
@@ -330,9 +345,9 @@ __global__ __launch_bounds__(kRbFusedThreads, 1) void k_rb_stage1(RbStage1Args a
   const int c = blockIdx.x;
   if (c >= a.copies) return;
   const int tid = threadIdx.x;
-  const uint4 zero = {0u, 0u, 0u, 0u};
-  // zero both maps (borders included), then the copy's input into M1
-  for (int i = tid; i < (int)(kRbStage1Lds / 16); i += kRbFusedThreads) reinterpret_cast<uint4*>(rbm)[i] = zero;
+  // the borders of both maps (M0 and M1 are 8 consecutive planes), then the
+  // copy's input into M1's first plane
+  rb_zero_border(rbm, 8, kRbMapSide, kRbPlane);
   __syncthreads();
   // the copy's input: copy c is candidate c / 4 turned by (c mod 4) quarter
   // turns (numpy's rot90 on the two image axes: one turn maps
@@ -364,16 +379,16 @@ __global__ __launch_bounds__(kRbFusedThreads, 1) void k_rb_stage1(RbStage1Args a
   __syncthreads();
   rb_stage1_layer<true, false>(M1, M0, a.w[0], a.bias[0], a.KP[0]);
   __syncthreads();
-  // M1 becomes a 32-channel map: zero it again (its border is read by conv b)
-  for (int i = tid; i < (int)(kRbMapBytes / 16); i += kRbFusedThreads) reinterpret_cast<uint4*>(M1)[i] = zero;
-  __syncthreads();
+  // M1 becomes a 32-channel map: conv a writes every interior pixel of its
+  // four planes, and their borders are still zero (the input sat in the
+  // interior of the first plane)
   rb_stage1_layer<false, false>(M0, M1, a.w[1], a.bias[1], a.KP[1]);
   __syncthreads();
   rb_stage1_layer<false, true>(M1, M0, a.w[2], a.bias[2], a.KP[2]);
   __syncthreads();
   // block 2 on the same copy: M0 (block 1's output, zero border) is its
   // input map; conv a's output (18 x 18 x 64, zero border) goes over M1
-  for (int i = tid; i < (int)(kRbMap16Bytes / 16); i += kRbFusedThreads) reinterpret_cast<uint4*>(M1)[i] = zero;
+  rb_zero_border(M1, 8, kRbMap16Side, kRbPlane16);
   __syncthreads();
   rb_stage2_gemm<true, 9>(M0, nullptr, M1, nullptr, a.w[3], a.bias[3], a.KP[3]);
   __syncthreads();
