@@ -126,18 +126,20 @@ constexpr size_t kRbStage1Lds = 2 * kRbMapBytes;
 
 constexpr int kRbPlane = kRbMapPix * 16;                        // bytes of one channel group
 
-// zero the one-pixel border of np consecutive planes (side x side pixels,
-// 16 bytes each); the layers write every interior pixel of their maps, so
-// only the borders that the 3 x 3 taps read need clearing
-__device__ __forceinline__ void rb_zero_border(unsigned char* base, int np, int side, int plane_bytes) {
+// zero the one-pixel border of np consecutive planes (side x side pixels of
+// `groups` 16-byte groups each); the layers write every interior pixel of
+// their maps, so only the borders that the 3 x 3 taps read need clearing
+__device__ __forceinline__ void rb_zero_border(unsigned char* base, int np, int side, int plane_bytes,
+                                               int groups = 1) {
   const int nb = 4 * side - 4;
-  for (int i = threadIdx.x; i < np * nb; i += kRbFusedThreads) {
-    const int pl = i / nb, k = i - pl * nb;
+  for (int i = threadIdx.x; i < np * nb * groups; i += kRbFusedThreads) {
+    const int q = i % groups, rest = i / groups;
+    const int pl = rest / nb, k = rest - pl * nb;
     int y, x;
     if (k < side) { y = 0; x = k; }
     else if (k < 2 * side) { y = side - 1; x = k - side; }
     else { const int e = k - 2 * side; y = 1 + (e >> 1); x = (e & 1) ? side - 1 : 0; }
-    *reinterpret_cast<uint4*>(base + pl * plane_bytes + (y * side + x) * 16) = uint4{0u, 0u, 0u, 0u};
+    *reinterpret_cast<uint4*>(base + pl * plane_bytes + ((y * side + x) * groups + q) * 16) = uint4{0u, 0u, 0u, 0u};
   }
 }
 
@@ -510,8 +512,10 @@ __global__ __launch_bounds__(kRbFusedThreads, 1) void k_rb_stage3(RbStage3Args a
   const int c = blockIdx.x;
   if (c >= a.copies) return;
   const int tid = threadIdx.x;
-  const uint4 zero = {0u, 0u, 0u, 0u};
-  for (int i = tid; i < (int)(kRbStage3Lds / 16); i += kRbFusedThreads) reinterpret_cast<uint4*>(rbm)[i] = zero;
+  // borders only: the block input's planes (their interiors are filled
+  // below) and conv a's output map (conv a writes every interior pixel)
+  rb_zero_border(M64, 8, kRbMap16Side, kRbPlane16);
+  rb_zero_border(M128, 1, kRbMap8Side, 0, 16);
   __syncthreads();
   const uint4* src = reinterpret_cast<const uint4*>(a.x + (int64_t)c * 16 * 16 * 64);
   for (int i = tid; i < 16 * 16 * 8; i += kRbFusedThreads) {
